@@ -1,0 +1,107 @@
+/*
+ * CPU oracle of the Heisenberg Metropolis hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the GPU library; only
+ * the tests, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it.  It shares no code, header or table with the GPU library.
+ *
+ * Plain serial C, double precision, compiled without floating-point
+ * contraction (-ffp-contract=off) so that every product and sum is rounded
+ * separately in the order written.
+ *
+ * Model (paper, section "Classical spin Hamiltonian", Eqs. 1-2):
+ *   H = - sum_<ij> J_ij S_i.S_j - B sum_i S_i.n_i - sum_i k_i (S_i.e_i)^2
+ * with every unordered bond counted once and the anisotropy entering Eq. 1 with
+ * a minus sign (k > 0 is an easy axis).
+ * Dynamics (paper, section "Monte Carlo Metropolis algorithm", Eq. 4): a trial
+ * direction uniform on the sphere is accepted when dE <= 0 or u < exp(-dE/T),
+ * k_B = 1; one attempt per site makes one Monte Carlo step (MCS).  Sites are
+ * visited colour class by colour class of a greedy colouring (breadth-first
+ * order), ascending site index inside a class.  After every MCS the energy, the magnetisation vector
+ * and the number of accepted moves are recorded.
+ */
+#ifndef HSIM_ORACLE_H
+#define HSIM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Lattice in user order.  Spins are stored [i][3]. */
+typedef struct {
+    int64_t n;
+    const int64_t *row_ptr;  /* n+1 */
+    const int32_t *col;      /* nnz */
+    const double *J;         /* nnz, symmetric */
+    const double *k;         /* n, or NULL for k = 0 */
+    const double *axis;      /* 3n, or NULL for +z */
+    const double *ndir;      /* 3n, or NULL for +z */
+} or_lattice;
+
+enum { OR_PROPOSAL_EXACT = 0, OR_PROPOSAL_F32MAP = 1 };
+enum { OR_INIT_GIVEN = 0, OR_INIT_COLD_Z = 1, OR_INIT_RANDOM = 2 };
+
+typedef struct {
+    uint64_t seed;           /* Philox key */
+    uint32_t replica;        /* third counter word */
+    int32_t n_steps;         /* T/B steps in this call */
+    int32_t mcs_per_step;
+    int32_t first_step;      /* absolute index of the first step (resume) */
+    int32_t recompute_every; /* P: E reset to the full sum at in-step MCS m with m % P == 0 (0: step start only) */
+    const double *T;         /* n_steps temperatures (0 = greedy, +inf = beta 0) */
+    const double *B;         /* n_steps field intensities */
+    int32_t proposal;        /* OR_PROPOSAL_* */
+    int32_t init;            /* OR_INIT_*, applied to spins before the first step */
+    const int64_t *order;    /* NULL, or a permutation: visiting order inside each class */
+    const int32_t *colour;   /* NULL (computed here) or a colouring to validate and use */
+    int32_t check_every_update; /* O(n) full-energy check of every accepted move */
+} or_params;
+
+typedef struct {
+    double *spins;           /* 3n in/out */
+    double *history;         /* n_steps*mcs_per_step*5: E, Mx, My, Mz, n_acc */
+    uint8_t *accept;         /* NULL or (n_steps*mcs_per_step)*n, user order */
+    double *e_full;          /* NULL or n_steps*mcs_per_step: full energy after each MCS */
+    int64_t near_ties;       /* decisions with |u - p| <= 4 ulp(p) */
+    double max_incr_err;     /* max |E_incr - E_full| / scale over all MCS */
+    double max_update_err;   /* max |dE - (E_after - E_before)| / scale */
+    int64_t n_decisions;
+} or_outputs;
+
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror and Shaw, SC'11). */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void or_philox_batch(int64_t count, const uint32_t *ctr /*4*count*/, const uint32_t *key /*2*/, uint32_t *out);
+/* Uniform maps of the random words: 53-bit and 23-bit odd-grid values in (0,1). */
+double or_u53(uint32_t hi, uint32_t lo);
+double or_u24(uint32_t w);
+/* Exact (Marsaglia 1972) sphere point from counters {site, g, rep, 1..}.  Returns attempts used. */
+int or_sphere_exact(uint64_t seed, uint32_t site, uint32_t g, uint32_t rep, double out[3]);
+/* Single-call proposal of the FP32 production mode, evaluated in double; u_out gets the acceptance uniform. */
+void or_sphere_f32map(uint64_t seed, uint32_t site, uint32_t g, uint32_t rep, double out[3], double *u_out);
+
+/* 0 if valid, else a negative code: -1 argument, -2 structure, -3 values. */
+int or_validate(const or_lattice *lat);
+/* Greedy colouring in breadth-first order (components by lowest site index,
+ * neighbours in CSR order), smallest colour unused by a coloured neighbour.
+ * Returns the number of colours. */
+int or_greedy_colour(const or_lattice *lat, int32_t *colour);
+/* Number of links whose two ends share a colour. */
+int64_t or_count_conflicts(const or_lattice *lat, const int32_t *colour);
+
+/* Energy pieces of Eq. 1 for one configuration. */
+double or_energy(const or_lattice *lat, double B, const double *spins,
+                 double *e_ex, double *e_zee, double *e_ani, double *scale);
+/* Bonds i < j in row-major CSR order; returns their number. */
+int64_t or_bonds(const or_lattice *lat, int32_t *bond_ij /* 2*nb or NULL */, double *J_bond /* nb or NULL */);
+/* Gradient of g*E: gS (3n), gJ per bond, gk (n), gB (scalar), all added to. */
+void or_energy_grad(const or_lattice *lat, double B, const double *spins, double g,
+                    double *gS, double *gJ_bond, double *gk, double *gB);
+
+/* Run the colour-ordered sweep.  Returns 0 or a negative code. */
+int or_run(const or_lattice *lat, const or_params *p, or_outputs *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
