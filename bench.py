@@ -1,0 +1,191 @@
+"""Benchmark of the batched Heisenberg Metropolis sweep on one MI355X.
+
+Workload (one "step" = one whole run of the hot path): periodic simple-cubic
+64^3 lattice (262144 unit spins), J = 1 to the 6 nearest neighbours, uniaxial
+K = 0.1 along z, B = 0; 64 replicas at temperatures 0.1 -> 3.0 (one per
+replica), cold start, seed 1, 10^4 MCS per replica, single-precision spins and
+fields with a double-precision history of (E, M, accepted) after every MCS;
+all replicas in one persistent launch (replica-lane layout).
+
+Printed: one JSON line with the throughput (attempted spin updates per second,
+inputs resident in HBM), the per-replica plain-launch rate on a bounded sample,
+the roofline of the dominant kernel (HBM, algorithmic bytes per update) and
+the CPU oracle's rate on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin updates/sec (batched replicas) vs plain launch; % HBM roofline; obs err"
+HBM_PEAK_GBS = 8000.0
+L, R, MCS, K_ANI, SEED = 64, 64, 10000, 0.1, 1
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mcs", type=int, default=MCS, help="MCS per replica per step")
+    ap.add_argument("--launch", default="persistent", choices=["persistent", "graph", "plain", "auto"])
+    ap.add_argument("--plain-mcs", type=int, default=8, help="MCS per replica of the plain-launch sample")
+    ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS per thread of the CPU oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    return ap.parse_args()
+
+
+def workload():
+    import synth
+    lat = synth.sc_periodic(L)
+    lat.k = np.full(lat.n, K_ANI)
+    T = synth.replica_temperatures(R, 0.1, 3.0)
+    return lat, T
+
+
+def b_alg_replica_lane(zbar, a, lanes):
+    """Algorithmic bytes per attempted update, replica-lane layout: own spin
+    (12) + neighbour spins counted once per MCS (12) + write on accept (12 a)
+    + the lattice row (4 B offset + 8 B per neighbour: column and J) shared by
+    the lanes."""
+    return 24.0 + 12.0 * a + (4.0 + 8.0 * zbar) / lanes
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(replicas shard across GPUs without communication)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1803_07030_amd import hsim
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    lat, T = workload()
+    launch = dict(persistent=hsim.LAUNCH_PERSISTENT, graph=hsim.LAUNCH_GRAPH,
+                  plain=hsim.LAUNCH_PLAIN, auto=hsim.LAUNCH_AUTO)[args.launch]
+    with torch.cuda.stream(stream):
+        plan = hsim.Plan(lat)
+        batch = hsim.Batch([plan] * R, seed=SEED, precision=hsim.FP32,
+                           layout=hsim.LAYOUT_REPLICA).bind(1, args.mcs)
+        Tm = T[:, None]
+
+        def one_step():
+            batch.init_spins(hsim.INIT_COLD_Z)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            batch.run(Tm, 0.0, recompute_every=100, launch=launch)
+            e1.record(stream)
+            return e0, e1
+
+        for _ in range(args.warmup):
+            one_step()
+        stream.synchronize()
+        assert batch.status() == 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs = [one_step() for _ in range(args.steps)]
+        stream.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        assert batch.status() == 0
+        kern_ms = [a.elapsed_time(b) for a, b in evs]
+        hist = batch.history.cpu().numpy()
+    n_upd_step = R * lat.n * args.mcs
+    value = n_upd_step * args.steps / wall
+    acc = float(hist[..., 4].mean() / lat.n)
+    zbar = lat.mean_degree
+    balg = b_alg_replica_lane(zbar, acc, 64)
+    avg_launch_s = float(np.mean(kern_ms)) / 1e3
+    achieved = balg * n_upd_step / avg_launch_s / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "spin updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"sc{L}^3 periodic J=1 K={K_ANI} z, {R} replicas T=0.1..3.0, "
+                               f"{args.mcs} MCS, cold start, f32 spins, f64 history, "
+                               f"{args.launch} launch, replica-lane layout",
+                   "sites": lat.n, "replicas": R, "mcs": args.mcs,
+                   "updates_per_step": n_upd_step, "launch": args.launch},
+        "acceptance": acc,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_update": balg, "kernel_ms": float(np.mean(kern_ms))},
+    }
+    if not args.no_plain:
+        out["plain_launch"] = plain_launch(lat, T, args.plain_mcs, stream)
+        out["vs_plain_launch"] = value / out["plain_launch"]["value"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(lat, T, args.cpu_mcs, hist)
+    print(json.dumps(out))
+
+
+def plain_launch(lat, T, mcs, stream):
+    """Per-replica plain launches: each replica its own single-replica batch
+    (site-lane kernel), one launch per (replica, MCS, colour) plus the per-MCS
+    history reduction, no graph; bounded sample of mcs MCS per replica."""
+    import torch
+    from paper_1803_07030_amd import hsim
+    with torch.cuda.stream(stream):
+        plan = hsim.Plan(lat)
+        batches = []
+        for r in range(R):
+            b = hsim.Batch([plan], seed=SEED, replica_ids=[r], precision=hsim.FP32,
+                           layout=hsim.LAYOUT_SITE).bind(1, mcs)
+            b.init_spins(hsim.INIT_COLD_Z)
+            batches.append(b)
+        batches[0].run([[T[0]]], 0.0, launch=hsim.LAUNCH_PLAIN)   # warm-up
+        stream.synchronize()
+        for b in batches:
+            b.init_spins(hsim.INIT_COLD_Z)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for r, b in enumerate(batches):
+            b.run([[T[r]]], 0.0, launch=hsim.LAUNCH_PLAIN)
+        stream.synchronize()
+        dt = time.perf_counter() - t0
+    upd = R * lat.n * mcs
+    return {"value": upd / dt, "unit": "spin updates/s", "sample": f"{R} replicas x {mcs} MCS",
+            "launches": R * mcs * (lat_colours(plan) + 1)}
+
+
+def lat_colours(plan):
+    return int(plan.info.n_colours)
+
+
+def cpu_baseline(lat, T, mcs, gpu_hist):
+    """The CPU oracle (double precision, same proposal map as the production
+    path) on a bounded sample: one replica per thread, replicas at the
+    workload's temperatures, cold start, mcs MCS each."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    reps = [int(r) for r in np.linspace(0, R - 1, threads).round()]
+    jobs = [dict(lat=lat, T=[T[r]], B=[0.0], mcs_per_step=mcs, seed=SEED, replica=r, init="cold",
+                 proposal=oracle.PROPOSAL_F32MAP) for r in reps]
+    t0 = time.perf_counter()
+    res, used = oracle.run_replicas(jobs, threads=threads)
+    dt = time.perf_counter() - t0
+    upd = len(jobs) * lat.n * mcs
+    # observable error of the same MCS: single-precision GPU vs double oracle
+    err_e = max(float(np.max(np.abs(gpu_hist[r, 0, :mcs, 0] - x["history"][0, :, 0]))) / lat.n
+                for r, x in zip(reps, res))
+    err_m = max(float(np.max(np.abs(gpu_hist[r, 0, :mcs, 3] - x["history"][0, :, 3]))) / lat.n
+                for r, x in zip(reps, res))
+    return {"value": upd / dt, "unit": "spin updates/s", "cores": used, "kind": "oracle",
+            "sample": f"{len(jobs)} replicas x {lat.n} sites x {mcs} MCS, one replica per thread",
+            "obs_err": {"E_per_site_max_abs": err_e, "Mz_per_site_max_abs": err_m,
+                        "mcs_compared": mcs}}
+
+
+if __name__ == "__main__":
+    main()

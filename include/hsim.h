@@ -1,0 +1,215 @@
+/*
+ * hsim — Metropolis Monte Carlo of the classical Heisenberg model on MI355X
+ * (gfx950).  C-ABI of libhsim.so.
+ *
+ * Model (paper, section "Classical spin Hamiltonian", Eqs. 1-2), k_B = 1:
+ *   E(S) = - sum_<ij> J_ij S_i.S_j  - B sum_i S_i.n_i  - sum_i k_i (S_i.e_i)^2
+ * every unordered bond <ij> counted once; k_i > 0 is an easy axis e_i; the
+ * field has one intensity B per temperature/field step and a fixed unit
+ * direction n_i per site.
+ * Dynamics (paper, section "Monte Carlo Metropolis algorithm", Eq. 4): a trial
+ * direction uniform on the sphere, accepted when dE <= 0 or u < exp(-dE/T).
+ * One attempt per site is one Monte Carlo step (MCS).  Sites are updated one
+ * colour class of a greedy breadth-first colouring at a time (all sites of a
+ * class in parallel), classes in ascending order.
+ * Output (paper, section "VEGAS software package"): after every MCS of every
+ * temperature/field step, the energy, the magnetisation vector and the number
+ * of accepted moves of every replica, in double precision.
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = 64-bit batch
+ * seed (low word first), counter = {user site index, g, replica id, attempt}
+ * with g = step * mcs_per_step + m (absolute step index).  A run therefore
+ * does not depend on the internal site order, the layout, the launch mode or
+ * on how a schedule is split into resumed runs.
+ *
+ * Conventions of every call:
+ *  - Every function returns hsim_status: HSIM_OK (0) or a negative code; on
+ *    failure hsim_last_error() gives a message (thread-local).  No C++
+ *    exception crosses this interface.
+ *  - Host arrays are read during the call and not retained.
+ *  - Device buffers passed in (workspace, spins, history, traces, energy
+ *    inputs and gradients) are owned by the caller, must stay allocated until
+ *    the work queued on the given stream has finished, and are never freed by
+ *    the library.  Plans and batches own their own device tables until
+ *    destroyed.
+ *  - Calls that take a hipStream_t only enqueue work and return.
+ *  - Spin arrays at this interface are in user order, double precision, [i][3].
+ */
+#ifndef HSIM_H
+#define HSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hsim_status;
+#define HSIM_OK 0
+#define HSIM_E_ARG (-1)          /* null pointer, bad size or bad enum */
+#define HSIM_E_CSR (-2)          /* asymmetric, self loop, duplicate or out-of-range CSR */
+#define HSIM_E_PARAM (-3)        /* non-finite value, axis norm off by > 1e-9, T < 0 */
+#define HSIM_E_STATE (-4)        /* call order: e.g. run before bind */
+#define HSIM_E_DEVICE (-5)       /* HIP runtime error (message in hsim_last_error) */
+#define HSIM_E_UNSUPPORTED (-6)  /* combination not provided (e.g. FP64 in the replica layout) */
+#define HSIM_E_TIMEOUT (-7)      /* a device barrier wait reached its cap */
+#define HSIM_E_NUMERIC (-8)      /* NaN energy change seen on the device */
+
+typedef struct hsim_plan_s *hsim_plan;   /* one lattice; opaque */
+typedef struct hsim_batch_s *hsim_batch; /* replicas over one or more plans; opaque */
+
+typedef enum { HSIM_FP32 = 0, HSIM_FP64_EXACT = 1 } hsim_precision;
+
+/* Spin layouts.  SITE: one lane per site of one replica, spins [3][n] per
+ * replica.  REPLICA: replicas sharing one lattice, one lane per replica of
+ * one site, spins [3][n][R padded to 64]; FP32 only.  BLOCK: each replica
+ * owned by one workgroup for the whole run (spins staged in LDS when they
+ * fit).  AUTO lets the library choose. */
+typedef enum {
+    HSIM_LAYOUT_AUTO = 0, HSIM_LAYOUT_SITE = 1, HSIM_LAYOUT_REPLICA = 2, HSIM_LAYOUT_BLOCK = 3
+} hsim_layout;
+
+/* PLAIN: kernels enqueued one by one.  GRAPH: the same kernels captured once
+ * into a hipGraph and replayed.  PERSISTENT: one launch that loops over MCS
+ * and colours with device-wide barriers.  AUTO: the library's choice. */
+typedef enum {
+    HSIM_LAUNCH_PLAIN = 0, HSIM_LAUNCH_PERSISTENT = 1, HSIM_LAUNCH_GRAPH = 2, HSIM_LAUNCH_AUTO = 3
+} hsim_launch;
+
+enum { HSIM_INIT_GIVEN = 0, HSIM_INIT_COLD_Z = 1, HSIM_INIT_RANDOM = 2 };
+
+/* run_flags */
+#define HSIM_RUN_TRACE_ACCEPTS 0x1u   /* write the accept bitmap to d_trace */
+
+/* ------------------------------------------------------------------ plans */
+/* Ingest one lattice (paper, section "Material building": sites, exchange
+ * links with their constants, a field axis per site; anisotropy file: a
+ * constant and an axis per site).
+ *   row_ptr [n+1] int64, col [nnz] int32: both directions of every link,
+ *     J [nnz]: the constant of each entry; J must be symmetric.
+ *   k [n] (NULL: 0), axis [3n] unit (NULL: +z), field_dir [3n] unit (NULL: +z).
+ * Validates (HSIM_E_CSR / HSIM_E_PARAM), colours the graph greedily in
+ * breadth-first order (components by lowest site index, neighbours in CSR
+ * order, smallest colour unused by a coloured neighbour), sorts sites by
+ * (colour, user index) and keeps every row's CSR entry order.  Host work
+ * only; device tables are uploaded on first use.  flags: reserved, pass 0. */
+hsim_status hsim_plan_create(hsim_plan *out, int64_t n_sites, const int64_t *row_ptr,
+                             const int32_t *col, const double *J, const double *k,
+                             const double *axis, const double *field_dir, uint32_t flags);
+
+typedef struct {
+    int64_t n_sites, nnz, n_bonds;
+    int32_t n_colours;
+    int32_t max_degree;
+    int64_t colour_size[64];  /* sizes of the first 64 classes */
+    double mean_degree;
+    int32_t uniform_anisotropy; /* 1 if k and axis are the same at every site */
+    int32_t uniform_field_dir;  /* 1 if n is the same at every site */
+} hsim_plan_info_t;
+
+hsim_status hsim_plan_info(hsim_plan plan, hsim_plan_info_t *out);
+/* Colour of every site, user order [n]. */
+hsim_status hsim_plan_colouring(hsim_plan plan, int32_t *colour_out);
+/* Bonds i < j in row-major CSR order (the order of every per-bond array):
+ * bond_ij_out [2*n_bonds] (may be NULL), *n_bonds_out (may be NULL). */
+hsim_status hsim_plan_bonds(hsim_plan plan, int32_t *bond_ij_out, int64_t *n_bonds_out);
+void hsim_plan_destroy(hsim_plan plan);
+
+/* ---------------------------------------------------------------- batches */
+/* n_rep replicas; replica r runs on lattice plan_of_rep[r] and draws its
+ * random words with counter word 2 = replica_id[r] (NULL: r).  Plans must
+ * outlive the batch. */
+hsim_status hsim_batch_create(hsim_batch *out, int32_t n_rep, const hsim_plan *plan_of_rep,
+                              uint64_t seed, const uint32_t *replica_id,
+                              hsim_precision precision, hsim_layout layout);
+
+typedef struct {
+    int32_t layout;           /* resolved hsim_layout */
+    int32_t n_rep, n_phases;  /* replicas, colour phases per MCS (max over lattices) */
+    int64_t total_sites;      /* sum of lattice sizes over replicas */
+    int32_t lds_resident;     /* BLOCK layout: spins held in LDS */
+    int32_t reserved;
+} hsim_batch_info_t;
+hsim_status hsim_batch_info(hsim_batch b, hsim_batch_info_t *out);
+
+/* Device bytes the caller must provide for a history of n_steps steps of
+ * mcs_per_step MCS.  History layout: double [n_rep][n_steps][mcs_per_step][5]
+ * = {E, Mx, My, Mz, accepted}.  Spins: the internal layout of the batch. */
+hsim_status hsim_batch_sizes(hsim_batch b, int32_t n_steps, int32_t mcs_per_step,
+                             size_t *workspace_bytes, size_t *spin_bytes,
+                             size_t *history_bytes);
+/* Attach caller-owned device buffers (sizes from hsim_batch_sizes, 256-byte
+ * aligned).  Must precede init/run; may be called again to re-attach. */
+hsim_status hsim_batch_bind(hsim_batch b, int32_t n_steps, int32_t mcs_per_step,
+                            void *d_workspace, void *d_spins, void *d_history);
+/* Initial state (paper, section "File Formats": initial-state file).
+ * GIVEN: host_spins [n_rep][n_r][3] user order, concatenated over replicas;
+ * COLD_Z: all +z; RANDOM: exact sphere point from counter
+ * {site, 0xFFFFFFFF, replica id, 1..} (the same map as the FP64 trial move),
+ * rounded to single precision in FP32 mode. */
+hsim_status hsim_batch_init_spins(hsim_batch b, int32_t mode, const double *host_spins,
+                                  void *stream);
+/* Run steps [first_step, first_step + n_steps) of the bound history.
+ *   T, B: host arrays [n_rep][n_steps] (temperature >= 0, +inf allowed; field
+ *     intensity); copied before return.
+ *   recompute_every P: the energy carried between MCS is reset to a double
+ *     precision full sum at every in-step MCS m with m % P == 0 (0: only at
+ *     step start).
+ *   d_trace: NULL, or with HSIM_RUN_TRACE_ACCEPTS a zeroed uint32 bitmap
+ *     [n_rep][n_steps*mcs_per_step][ceil(n/32)] receiving bit (site % 32) of
+ *     word site/32 for every accepted move (SITE and BLOCK layouts).
+ * Spins carry over between steps and between calls. */
+hsim_status hsim_batch_run(hsim_batch b, int32_t first_step, int32_t n_steps, const double *T,
+                           const double *B, int32_t recompute_every, hsim_launch launch,
+                           uint32_t run_flags, uint32_t *d_trace, void *stream);
+/* Replica rep's spins in user order, double [n][3], into device memory. */
+hsim_status hsim_batch_spins_to_user(hsim_batch b, int32_t rep, double *d_out, void *stream);
+/* Device status word after the stream has been synchronised: 0, or
+ * HSIM_E_NUMERIC / HSIM_E_TIMEOUT.  Clears it. */
+hsim_status hsim_batch_status(hsim_batch b, int32_t *device_status_out);
+/* Time the launch modes and tile shapes available for this batch on
+ * trial_mcs MCS (restoring the spins afterwards) and keep the fastest for
+ * HSIM_LAUNCH_AUTO.  The choice never changes spin trajectories.  Results
+ * are cached in cache_path (NULL: no file). */
+hsim_status hsim_autotune(hsim_batch b, const char *cache_path, int32_t trial_mcs,
+                          void *stream);
+void hsim_batch_destroy(hsim_batch b);
+
+/* ------------------------------------------------- energy and its gradient */
+/* Eq. 1 for `batch` configurations of one lattice, precision HSIM_FP32
+ * (float inputs, double accumulation) or HSIM_FP64_EXACT (double inputs).
+ *   d_spins [batch][3][n] user order; d_J_bond [n_bonds] in hsim_plan_bonds
+ *   order; d_k [n]; d_axis [3][n]; B scalar; d_field_dir [3][n] (NULL: +z).
+ *   d_E [batch] double receives the energies. */
+hsim_status hsim_energy_forward(hsim_plan plan, int32_t batch, hsim_precision precision,
+                                const void *d_spins, const void *d_J_bond, const void *d_k,
+                                const void *d_axis, double B, const void *d_field_dir,
+                                double *d_E, void *stream);
+/* Vector-Jacobian product of the energies with upstream d_gE [batch]:
+ *   d_gS [batch][3][n]   = gE_b (-sum_j J_ij S_j - B n_i - 2 k_i (S_i.e_i) e_i)
+ *   d_gJ_bond [n_bonds]  = sum_b gE_b (-S_i.S_j)
+ *   d_gk [n]             = sum_b gE_b (-(S_i.e_i)^2)
+ *   d_gB [1] (double)    = sum_b gE_b (-sum_i S_i.n_i)
+ * Any output may be NULL.  Outputs are overwritten (not accumulated); gS, gJ
+ * and gk have the precision of the inputs. */
+hsim_status hsim_energy_backward(hsim_plan plan, int32_t batch, hsim_precision precision,
+                                 const void *d_spins, const void *d_J_bond, const void *d_k,
+                                 const void *d_axis, double B, const void *d_field_dir,
+                                 const double *d_gE, void *d_gS, void *d_gJ_bond, void *d_gk,
+                                 double *d_gB, void *stream);
+/* Fluctuation estimate of d<O>/d(theta) from n samples of the equilibrium
+ * chain at inverse temperature beta:
+ *   d<O>/dtheta = <dO/dtheta> - beta (<O dE/dtheta> - <O><dE/dtheta>)
+ * d_O, d_dE [n] double, d_dO [n] double or NULL (0); d_out [2] double receives
+ * the estimate and the covariance term. */
+hsim_status hsim_fluct_estimate(int64_t n, double beta, const double *d_O, const double *d_dE,
+                                const double *d_dO, double *d_out, void *stream);
+
+const char *hsim_last_error(void);
+const char *hsim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

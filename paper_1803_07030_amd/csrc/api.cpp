@@ -1,0 +1,216 @@
+// extern "C" entry points of libhsim.so (declared in include/hsim.h).  Each
+// one validates its arguments, runs the C++ implementation and turns any
+// error into an hsim_status plus a thread-local message: no exception leaves
+// the library.
+#include <cstring>
+#include <string>
+
+#include "hsim_host.h"
+
+hsim_plan plan_create_impl(int64_t, const int64_t *, const int32_t *, const double *,
+                           const double *, const double *, const double *);
+void energy_forward_impl(hsim_plan, int32_t, hsim_precision, const void *, const void *,
+                         const void *, const void *, double, const void *, double *, hipStream_t);
+void energy_backward_impl(hsim_plan, int32_t, hsim_precision, const void *, const void *,
+                          const void *, const void *, double, const void *, const double *, void *,
+                          void *, void *, double *, hipStream_t);
+hsim_batch batch_create_impl(int32_t, const hsim_plan *, uint64_t, const uint32_t *,
+                             hsim_precision, hsim_layout);
+void batch_sizes_impl(hsim_batch, int32_t, int32_t, size_t *, size_t *, size_t *);
+void batch_bind_impl(hsim_batch, int32_t, int32_t, void *, void *, void *);
+void batch_init_impl(hsim_batch, int32_t, const double *, hipStream_t);
+void batch_run_impl(hsim_batch, int32_t, int32_t, const double *, const double *, int32_t,
+                    hsim_launch, uint32_t, uint32_t *, hipStream_t);
+void batch_to_user_impl(hsim_batch, int32_t, double *, hipStream_t);
+int32_t batch_status_impl(hsim_batch);
+void autotune_impl(hsim_batch, const char *, int32_t, hipStream_t);
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+hsim_status guarded(F &&f)
+{
+    try {
+        f();
+        g_last_error.clear();
+        return HSIM_OK;
+    } catch (const hsim::Error &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host out of memory";
+        return HSIM_E_DEVICE;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return HSIM_E_DEVICE;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return HSIM_E_DEVICE;
+    }
+}
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+
+}  // namespace
+
+extern "C" {
+
+hsim_status hsim_plan_create(hsim_plan *out, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                             const double *J, const double *k, const double *axis,
+                             const double *field_dir, uint32_t flags)
+{
+    return guarded([&] {
+        if (!out) throw hsim::Error(HSIM_E_ARG, "plan_create: NULL out");
+        if (flags != 0) throw hsim::Error(HSIM_E_ARG, "plan_create: flags must be 0");
+        *out = nullptr;
+        *out = plan_create_impl(n, row_ptr, col, J, k, axis, field_dir);
+    });
+}
+
+hsim_status hsim_plan_info(hsim_plan p, hsim_plan_info_t *out)
+{
+    return guarded([&] {
+        if (!p || !out) throw hsim::Error(HSIM_E_ARG, "plan_info: NULL argument");
+        std::memset(out, 0, sizeof(*out));
+        out->n_sites = p->n;
+        out->nnz = p->nnz;
+        out->n_bonds = p->nb;
+        out->n_colours = p->ncol;
+        out->max_degree = p->maxdeg;
+        for (int c = 0; c < p->ncol && c < 64; ++c) out->colour_size[c] = p->cls_off[c + 1] - p->cls_off[c];
+        out->mean_degree = p->n > 0 ? (double)p->nnz / (double)p->n : 0.0;
+        out->uniform_anisotropy = p->kmode != hsim::K_SITE;
+        out->uniform_field_dir = p->fmode == hsim::F_UNIFORM;
+    });
+}
+
+hsim_status hsim_plan_colouring(hsim_plan p, int32_t *colour_out)
+{
+    return guarded([&] {
+        if (!p || (!colour_out && p->n > 0)) throw hsim::Error(HSIM_E_ARG, "plan_colouring: NULL argument");
+        if (p->n > 0) std::memcpy(colour_out, p->colour.data(), p->n * sizeof(int32_t));
+    });
+}
+
+hsim_status hsim_plan_bonds(hsim_plan p, int32_t *bond_ij_out, int64_t *n_bonds_out)
+{
+    return guarded([&] {
+        if (!p) throw hsim::Error(HSIM_E_ARG, "plan_bonds: NULL plan");
+        if (n_bonds_out) *n_bonds_out = p->nb;
+        if (bond_ij_out && p->nb > 0)
+            std::memcpy(bond_ij_out, p->bond_ij.data(), 2 * p->nb * sizeof(int32_t));
+    });
+}
+
+void hsim_plan_destroy(hsim_plan p) { delete p; }
+
+hsim_status hsim_batch_create(hsim_batch *out, int32_t n_rep, const hsim_plan *plans, uint64_t seed,
+                              const uint32_t *replica_id, hsim_precision precision,
+                              hsim_layout layout)
+{
+    return guarded([&] {
+        if (!out) throw hsim::Error(HSIM_E_ARG, "batch_create: NULL out");
+        *out = nullptr;
+        *out = batch_create_impl(n_rep, plans, seed, replica_id, precision, layout);
+    });
+}
+
+hsim_status hsim_batch_info(hsim_batch b, hsim_batch_info_t *out)
+{
+    return guarded([&] {
+        if (!b || !out) throw hsim::Error(HSIM_E_ARG, "batch_info: NULL argument");
+        std::memset(out, 0, sizeof(*out));
+        out->layout = b->layout;
+        out->n_rep = b->R;
+        out->n_phases = b->ncol_max;
+        out->total_sites = b->total_sites;
+        out->lds_resident = b->layout == HSIM_LAYOUT_BLOCK && b->lds;
+    });
+}
+
+hsim_status hsim_batch_sizes(hsim_batch b, int32_t n_steps, int32_t mcs, size_t *ws, size_t *sp,
+                             size_t *hist)
+{
+    return guarded([&] { batch_sizes_impl(b, n_steps, mcs, ws, sp, hist); });
+}
+
+hsim_status hsim_batch_bind(hsim_batch b, int32_t n_steps, int32_t mcs, void *ws, void *sp, void *hist)
+{
+    return guarded([&] { batch_bind_impl(b, n_steps, mcs, ws, sp, hist); });
+}
+
+hsim_status hsim_batch_init_spins(hsim_batch b, int32_t mode, const double *host, void *stream)
+{
+    return guarded([&] { batch_init_impl(b, mode, host, S(stream)); });
+}
+
+hsim_status hsim_batch_run(hsim_batch b, int32_t first_step, int32_t n_steps, const double *T,
+                           const double *B, int32_t recompute_every, hsim_launch launch,
+                           uint32_t run_flags, uint32_t *d_trace, void *stream)
+{
+    return guarded([&] {
+        batch_run_impl(b, first_step, n_steps, T, B, recompute_every, launch, run_flags, d_trace,
+                       S(stream));
+    });
+}
+
+hsim_status hsim_batch_spins_to_user(hsim_batch b, int32_t rep, double *d_out, void *stream)
+{
+    return guarded([&] { batch_to_user_impl(b, rep, d_out, S(stream)); });
+}
+
+hsim_status hsim_batch_status(hsim_batch b, int32_t *out)
+{
+    return guarded([&] {
+        if (!out) throw hsim::Error(HSIM_E_ARG, "batch_status: NULL out");
+        *out = batch_status_impl(b);
+    });
+}
+
+hsim_status hsim_autotune(hsim_batch b, const char *cache_path, int32_t trial_mcs, void *stream)
+{
+    return guarded([&] { autotune_impl(b, cache_path, trial_mcs, S(stream)); });
+}
+
+void hsim_batch_destroy(hsim_batch b) { delete b; }
+
+hsim_status hsim_energy_forward(hsim_plan plan, int32_t batch, hsim_precision precision,
+                                const void *d_spins, const void *d_J_bond, const void *d_k,
+                                const void *d_axis, double B, const void *d_field_dir,
+                                double *d_E, void *stream)
+{
+    return guarded([&] {
+        energy_forward_impl(plan, batch, precision, d_spins, d_J_bond, d_k, d_axis, B,
+                            d_field_dir, d_E, S(stream));
+    });
+}
+
+hsim_status hsim_energy_backward(hsim_plan plan, int32_t batch, hsim_precision precision,
+                                 const void *d_spins, const void *d_J_bond, const void *d_k,
+                                 const void *d_axis, double B, const void *d_field_dir,
+                                 const double *d_gE, void *d_gS, void *d_gJ_bond, void *d_gk,
+                                 double *d_gB, void *stream)
+{
+    return guarded([&] {
+        energy_backward_impl(plan, batch, precision, d_spins, d_J_bond, d_k, d_axis, B,
+                             d_field_dir, d_gE, d_gS, d_gJ_bond, d_gk, d_gB, S(stream));
+    });
+}
+
+hsim_status hsim_fluct_estimate(int64_t n, double beta, const double *d_O, const double *d_dE,
+                                const double *d_dO, double *d_out, void *stream)
+{
+    return guarded([&] {
+        if (n < 1 || !d_O || !d_dE || !d_out) throw hsim::Error(HSIM_E_ARG, "fluct_estimate: bad argument");
+        if (!std::isfinite(beta) || beta < 0) throw hsim::Error(HSIM_E_PARAM, "beta must be finite and >= 0");
+        hsim::hip_check(hsim::launch_fluct(S(stream), n, beta, d_O, d_dE, d_dO, d_out), "fluct launch");
+    });
+}
+
+const char *hsim_last_error(void) { return g_last_error.c_str(); }
+
+const char *hsim_version(void) { return "hsim 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,645 @@
+// Batches: replicas over plans, their spin layout, tiles and workspace, and
+// the launch sequence of a run (paper, section "Monte Carlo Metropolis
+// algorithm": MCS after MCS, every site once per MCS; section "VEGAS software
+// package": history after every MCS of every temperature/field step).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "hsim_host.h"
+
+using hsim::Error;
+using hsim::hip_check;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
+
+int device_lds_limit()
+{
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return 160 * 1024 - 1024;
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 160 * 1024 - 1024;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 64 * 1024 - 1024;
+    return v - 1024;
+}
+
+int device_cus()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return v;
+}
+
+}  // namespace
+
+hsim_batch_s::~hsim_batch_s()
+{
+    if (stage_done) {
+        (void)hipEventSynchronize(stage_done);
+        (void)hipEventDestroy(stage_done);
+    }
+    if (h_stage) (void)hipHostFree(h_stage);
+}
+
+hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
+                             const uint32_t *rep_id, hsim_precision prec, hsim_layout layout)
+{
+    if (R < 1 || !plans) throw Error(HSIM_E_ARG, "batch needs at least one replica");
+    if (prec != HSIM_FP32 && prec != HSIM_FP64_EXACT) throw Error(HSIM_E_ARG, "bad precision");
+    if (layout < HSIM_LAYOUT_AUTO || layout > HSIM_LAYOUT_BLOCK) throw Error(HSIM_E_ARG, "bad layout");
+    for (int r = 0; r < R; ++r)
+        if (!plans[r]) throw Error(HSIM_E_ARG, "NULL plan");
+    auto *b = new hsim_batch_s();
+    try {
+        b->R = R;
+        b->plans.assign(plans, plans + R);
+        b->rep_id.resize(R);
+        for (int r = 0; r < R; ++r) b->rep_id[r] = rep_id ? rep_id[r] : (uint32_t)r;
+        b->seed = seed;
+        b->f64 = prec == HSIM_FP64_EXACT;
+        const size_t elem = b->f64 ? 8 : 4;
+        bool shared = true;
+        int64_t max_n = 0, max_cls = 0;
+        for (int r = 0; r < R; ++r) {
+            hsim_plan P = plans[r];
+            shared = shared && P == plans[0];
+            b->kmode = std::max(b->kmode, P->kmode);
+            b->fmode = std::max(b->fmode, P->fmode);
+            b->ncol_max = std::max(b->ncol_max, P->ncol);
+            b->total_sites += P->n;
+            max_n = std::max(max_n, P->n);
+            for (int c = 0; c < P->ncol; ++c)
+                max_cls = std::max<int64_t>(max_cls, P->cls_off[c + 1] - P->cls_off[c]);
+        }
+        if (b->total_sites > (int64_t)INT32_MAX) throw Error(HSIM_E_UNSUPPORTED, "batch too large");
+        const int64_t lds_limit = device_lds_limit();
+        const bool fits_lds = 3 * pad64(max_n) * (int64_t)elem <= lds_limit;
+        int lay = layout;
+        if (lay == HSIM_LAYOUT_REPLICA && (b->f64 || !shared))
+            throw Error(HSIM_E_UNSUPPORTED, "replica layout needs FP32 and one shared lattice");
+        if (lay == HSIM_LAYOUT_AUTO) {
+            if (!b->f64 && shared && R >= 16) lay = HSIM_LAYOUT_REPLICA;
+            else if (fits_lds) lay = HSIM_LAYOUT_BLOCK;
+            else lay = HSIM_LAYOUT_SITE;
+        }
+        b->layout = lay;
+        if (lay == HSIM_LAYOUT_REPLICA) {
+            hsim_plan P = plans[0];
+            b->Rp = R > 32 ? (int32_t)((R + 63) / 64 * 64) : 32;
+            b->la.tile_off[0] = 0;
+            for (int c = 0; c < P->ncol; ++c) {
+                const int sz = P->cls_off[c + 1] - P->cls_off[c];
+                b->la.tile_off[c + 1] = b->la.tile_off[c] + (sz + hsim::kRepTile - 1) / hsim::kRepTile;
+            }
+            b->rep_ntiles = b->la.tile_off[P->ncol];
+        } else {
+            b->spin_off.resize(R);
+            int64_t off = 0;
+            for (int r = 0; r < R; ++r) {
+                b->spin_off[r] = off;
+                off += 3 * pad64(plans[r]->n);
+            }
+            b->spin_elems = off;
+            if (lay == HSIM_LAYOUT_SITE) {
+                const int C = b->ncol_max;
+                b->tile_off.assign(C + 1, 0);
+                b->rep_tiles.assign((size_t)R * C * 2, 0);
+                for (int c = 0; c < C; ++c) {
+                    b->tile_off[c] = (int32_t)b->tiles.size();
+                    for (int r = 0; r < R; ++r) {
+                        hsim_plan P = plans[r];
+                        const int32_t t0 = (int32_t)b->tiles.size();
+                        if (c < P->ncol)
+                            for (int32_t s = P->cls_off[c]; s < P->cls_off[c + 1]; s += hsim::kSiteBlock)
+                                b->tiles.push_back({r, s, std::min(s + hsim::kSiteBlock, P->cls_off[c + 1]), c});
+                        b->rep_tiles[((size_t)r * C + c) * 2] = t0;
+                        b->rep_tiles[((size_t)r * C + c) * 2 + 1] = (int32_t)b->tiles.size();
+                    }
+                }
+                b->tile_off[C] = (int32_t)b->tiles.size();
+                if (b->tiles.size() > (size_t)INT32_MAX / 2) throw Error(HSIM_E_UNSUPPORTED, "too many tiles");
+            } else {
+                b->lds = fits_lds;
+                b->lds_bytes = (size_t)(3 * pad64(max_n)) * elem;
+                int64_t th = std::max<int64_t>(64, (max_cls + 63) / 64 * 64);
+                b->block_threads = (int)std::min<int64_t>(th, 1024);
+            }
+        }
+    } catch (...) {
+        delete b;
+        throw;
+    }
+    return b;
+}
+
+void batch_sizes_impl(hsim_batch b, int32_t S, int32_t M, size_t *ws, size_t *sp, size_t *hist)
+{
+    if (!b || S < 1 || M < 1) throw Error(HSIM_E_ARG, "sizes: bad argument");
+    if ((uint64_t)S * (uint64_t)M >= 0xFFFFFFFFull) throw Error(HSIM_E_ARG, "steps*mcs too large");
+    size_t off = align_up(sizeof(hsim::Ctl));
+    off += align_up((size_t)b->R * 8);                 // ecarry
+    off += 2 * align_up((size_t)b->R * S * 8);         // beta, bfield
+    size_t part = 0;
+    if (b->layout == HSIM_LAYOUT_SITE) part = b->tiles.size() * hsim::kRecSite * 8;
+    else if (b->layout == HSIM_LAYOUT_REPLICA)
+        part = ((size_t)2 * b->rep_ntiles * hsim::kRecFields * b->Rp + (size_t)2 * 64 * 6 * b->Rp) * 8;
+    off += align_up(std::max<size_t>(part, 8));
+    if (ws) *ws = off;
+    const size_t elem = b->f64 ? 8 : 4;
+    if (sp) {
+        if (b->layout == HSIM_LAYOUT_REPLICA) *sp = (size_t)3 * b->plans[0]->n * b->Rp * 4;
+        else *sp = (size_t)b->spin_elems * elem;
+        if (*sp == 0) *sp = 16;
+    }
+    if (hist) *hist = (size_t)b->R * S * M * 5 * 8;
+}
+
+void hsim_batch_s::upload_tables()
+{
+    const size_t elem = f64 ? 8 : 4;
+    for (auto P : plans) P->upload_sweep();
+    if (layout == HSIM_LAYOUT_REPLICA) {
+        hsim_plan P = plans[0];
+        std::vector<uint32_t> ids(Rp, 0);
+        for (int r = 0; r < R; ++r) ids[r] = rep_id[r];
+        d_rep_id.upload(ids);
+        la.rp = (const int32_t *)P->d_rp.p;
+        la.ci = (const int32_t *)P->d_ci.p;
+        la.J = (const float *)P->d_Jf.p;
+        la.orig = (const uint32_t *)P->d_orig.p;
+        la.k = (const float *)P->d_kf.p;
+        la.ax = (const float *)P->d_axf.p;
+        la.nd = (const float *)P->d_ndf.p;
+        la.spins = (float *)spins;
+        la.rep_id = (const uint32_t *)d_rep_id.p;
+        la.k0 = (float)P->k0;
+        la.e0x = (float)P->e0[0];
+        la.e0y = (float)P->e0[1];
+        la.e0z = (float)P->e0[2];
+        la.n0x = (float)P->n0[0];
+        la.n0y = (float)P->n0[1];
+        la.n0z = (float)P->n0[2];
+        la.n = (int32_t)P->n;
+        la.Rp = Rp;
+        la.R = R;
+        la.ncol = P->ncol;
+        for (int c = 0; c <= P->ncol; ++c) la.cls_off[c] = P->cls_off[c];
+    } else {
+        reps.assign(R, hsim::RepDesc{});
+        int64_t uoff = 0;
+        for (int r = 0; r < R; ++r) {
+            hsim_plan P = plans[r];
+            hsim::RepDesc &d = reps[r];
+            d.rp = (const int32_t *)P->d_rp.p;
+            d.ci = (const int32_t *)P->d_ci.p;
+            d.J = f64 ? P->d_Jd.p : P->d_Jf.p;
+            d.orig = (const uint32_t *)P->d_orig.p;
+            d.k = f64 ? P->d_kd.p : P->d_kf.p;
+            d.ax = f64 ? P->d_axd.p : P->d_axf.p;
+            d.nd = f64 ? P->d_ndd.p : P->d_ndf.p;
+            d.spins = (char *)spins + spin_off[r] * elem;
+            d.k0 = P->k0;
+            for (int c = 0; c < 3; ++c) {
+                d.e0[c] = P->e0[c];
+                d.n0[c] = P->n0[c];
+            }
+            d.user_off = uoff;
+            uoff += P->n;
+            d.n = (int32_t)P->n;
+            d.n_pad = (int32_t)pad64(P->n);
+            d.rep_id = rep_id[r];
+            d.ncol = P->ncol;
+            for (int c = 0; c <= P->ncol; ++c) d.cls_off[c] = P->cls_off[c];
+        }
+        d_reps.upload(reps);
+        if (layout == HSIM_LAYOUT_SITE) {
+            d_tiles.upload(tiles);
+            d_rep_tiles.upload(rep_tiles);
+        }
+    }
+    tables_on_device = true;
+}
+
+void batch_bind_impl(hsim_batch b, int32_t S, int32_t M, void *ws, void *spins, void *hist)
+{
+    if (!b || !ws || !spins || !hist) throw Error(HSIM_E_ARG, "bind: NULL buffer");
+    size_t wsb = 0;
+    batch_sizes_impl(b, S, M, &wsb, nullptr, nullptr);
+    if (((uintptr_t)ws | (uintptr_t)spins | (uintptr_t)hist) % 16)
+        throw Error(HSIM_E_ARG, "bind: buffers must be 16-byte aligned");
+    b->S_hist = S;
+    b->M = M;
+    b->ws = (char *)ws;
+    b->spins = spins;
+    b->history = (double *)hist;
+    b->ws_bytes = wsb;
+    size_t off = align_up(sizeof(hsim::Ctl));
+    b->off_ecarry = off;
+    off += align_up((size_t)b->R * 8);
+    b->off_beta = off;
+    off += align_up((size_t)b->R * S * 8);
+    b->off_bfield = off;
+    off += align_up((size_t)b->R * S * 8);
+    b->off_part = off;
+    b->h_beta.assign((size_t)b->R * S, 0.0);
+    b->h_bfield.assign((size_t)b->R * S, 0.0);
+    if (b->stage_done) {
+        hip_check(hipEventSynchronize(b->stage_done), "hipEventSynchronize");
+    } else {
+        hip_check(hipEventCreateWithFlags(&b->stage_done, hipEventDisableTiming), "hipEventCreate");
+    }
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    b->h_stage = nullptr;
+    hip_check(hipHostMalloc((void **)&b->h_stage, 2 * (size_t)b->R * S * 8, hipHostMallocDefault),
+              "hipHostMalloc");
+    b->upload_tables();
+    // clear the control block once (outside any graph)
+    hip_check(hipMemset(ws, 0, align_up(sizeof(hsim::Ctl))), "hipMemset");
+    b->bound = true;
+}
+
+hsim::RunArgs hsim_batch_s::run_args(uint32_t g0, int n_mcs, int P, uint32_t *trace)
+{
+    hsim::RunArgs a{};
+    a.ctl = (hsim::Ctl *)ws;
+    a.beta = (const double *)(ws + off_beta);
+    a.bfield = (const double *)(ws + off_bfield);
+    a.ecarry = (double *)(ws + off_ecarry);
+    a.partials = (double *)(ws + off_part);
+    a.history = history;
+    a.trace = trace;
+    a.seed = seed;
+    a.g0 = g0;
+    a.M = M;
+    a.S_hist = S_hist;
+    a.P = P;
+    a.n_mcs_run = n_mcs;
+    int64_t maxn = 0;
+    for (auto p : plans) maxn = std::max(maxn, p->n);
+    a.trace_words = (int32_t)((maxn + 31) / 32);
+    a.R = R;
+    return a;
+}
+
+void batch_init_impl(hsim_batch b, int32_t mode, const double *host, hipStream_t st)
+{
+    if (!b) throw Error(HSIM_E_ARG, "init: NULL batch");
+    if (!b->bound) throw Error(HSIM_E_STATE, "init before bind");
+    if (mode != HSIM_INIT_GIVEN && mode != HSIM_INIT_COLD_Z && mode != HSIM_INIT_RANDOM)
+        throw Error(HSIM_E_ARG, "bad init mode");
+    hsim::DevBuf given;
+    if (mode == HSIM_INIT_GIVEN) {
+        if (!host) throw Error(HSIM_E_ARG, "init: GIVEN needs host spins");
+        const size_t cnt = (size_t)b->total_sites * 3;
+        for (size_t t = 0; t < cnt; ++t)
+            if (!std::isfinite(host[t])) throw Error(HSIM_E_PARAM, "non-finite initial spin");
+        given.alloc(cnt * 8);
+        hip_check(hipMemcpy(given.p, host, cnt * 8, hipMemcpyHostToDevice), "hipMemcpy");
+    }
+    if (b->layout == HSIM_LAYOUT_REPLICA) {
+        hip_check(hsim::launch_init_spins_rep(st, b->la, mode, (const double *)given.p, b->seed),
+                  "init launch");
+    } else {
+        int64_t maxn = 1;
+        for (auto p : b->plans) maxn = std::max(maxn, p->n);
+        hip_check(hsim::launch_init_spins(st, b->f64, (const hsim::RepDesc *)b->d_reps.p, b->R,
+                                          (int)maxn, mode, (const double *)given.p, nullptr, b->seed),
+                  "init launch");
+    }
+    if (given.p) hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
+namespace {
+
+// Launches of one MCS in the site and replica layouts.
+void enqueue_mcs(hsim_batch b, const hsim::RunArgs &ra, bool efull, hipStream_t st)
+{
+    if (b->layout == HSIM_LAYOUT_SITE) {
+        const auto *reps = (const hsim::RepDesc *)b->d_reps.p;
+        const auto *tiles = (const hsim::Tile *)b->d_tiles.p;
+        if (efull)
+            hip_check(hsim::launch_site_efull(st, b->f64, b->kmode, b->fmode, reps, tiles,
+                                              (int)b->tiles.size(), ra),
+                      "efull launch");
+        for (int c = 0; c < b->ncol_max; ++c)
+            hip_check(hsim::launch_site_phase(st, b->f64, b->kmode, b->fmode, ra.trace != nullptr,
+                                              reps, tiles, b->tile_off[c],
+                                              b->tile_off[c + 1] - b->tile_off[c], ra),
+                      "phase launch");
+        hip_check(hsim::launch_site_reduce(st, (const int32_t *)b->d_rep_tiles.p, b->ncol_max, ra),
+                  "reduce launch");
+    } else {
+        if (efull)
+            hip_check(hsim::launch_rep_efull(st, b->kmode, b->fmode, b->la, b->rep_ntiles, ra),
+                      "efull launch");
+        for (int c = 0; c < b->la.ncol; ++c)
+            hip_check(hsim::launch_rep_phase(st, b->kmode, b->fmode, c, b->la, ra), "phase launch");
+        hip_check(hsim::launch_rep_reduce(st, b->la, b->rep_ntiles, ra), "reduce launch");
+    }
+}
+
+bool due(uint32_t g, int M, int P)
+{
+    const uint32_t m = g % (uint32_t)M;
+    return m == 0 || (P > 0 && m % (uint32_t)P == 0);
+}
+
+void run_plain(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st, int from, int to)
+{
+    for (int t = from; t < to; ++t) enqueue_mcs(b, ra, due(ra.g0 + t, ra.M, ra.P), st);
+}
+
+void run_graph(hsim_batch b, const hsim::RunArgs &ra, hipStream_t user_st)
+{
+    const int total = ra.n_mcs_run;
+    // the legacy null stream cannot be captured: use a private stream ordered
+    // after the work already queued on the caller's stream
+    hipStream_t st = user_st;
+    hipStream_t own = nullptr;
+    if (user_st == nullptr) {
+        hip_check(hipStreamSynchronize(user_st), "hipStreamSynchronize");
+        hip_check(hipStreamCreateWithFlags(&own, hipStreamNonBlocking), "hipStreamCreate");
+        st = own;
+    }
+    struct OwnStream {
+        hipStream_t s;
+        ~OwnStream() { if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); } }
+    } guard{own};
+    int U;
+    bool efull_each;
+    if (ra.P > 0 && ra.M % ra.P == 0 && ra.P <= 512) {
+        U = ra.P;
+        efull_each = false;
+    } else {
+        U = std::min(ra.M, 64);
+        efull_each = true;
+    }
+    const int reps = total / U;
+    if (reps < 2) {
+        run_plain(b, ra, st, 0, total);
+        return;
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+        for (int t = 0; t < U; ++t) enqueue_mcs(b, ra, efull_each || t == 0, st);
+    } catch (...) {
+        (void)hipStreamEndCapture(st, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    hip_check(hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        hip_check(e, "hipGraphInstantiate");
+    }
+    for (int k = 0; k < reps; ++k) {
+        e = hipGraphLaunch(exec, st);
+        if (e != hipSuccess) break;
+    }
+    // the executable graph must outlive its queued launches
+    hipError_t e2 = hipStreamSynchronize(st);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    hip_check(e, "hipGraphLaunch");
+    hip_check(e2, "hipStreamSynchronize");
+    run_plain(b, ra, st, reps * U, total);
+}
+
+bool run_persistent(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st)
+{
+    const int bpc = hsim::rep_persistent_blocks_per_cu(b->kmode, b->fmode, b->Rp % 64 == 0 ? 64 : 32);
+    const int cus = device_cus();
+    if (bpc <= 0 || cus <= 0) return false;
+    const int groups = b->Rp / (b->Rp % 64 == 0 ? 64 : 32);
+    int grid = b->persistent_grid > 0 ? b->persistent_grid : bpc * cus;
+    grid = std::min(grid, bpc * cus);   // every block must be resident at once
+    grid = std::min(grid, std::max(1, b->rep_ntiles * groups));
+    hip_check(hsim::launch_rep_persistent(st, b->kmode, b->fmode, b->la, b->rep_ntiles, grid, ra,
+                                          1u << 25),
+              "persistent launch");
+    return true;
+}
+
+}  // namespace
+
+void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const double *T,
+                    const double *B, int32_t P, hsim_launch launch, uint32_t flags,
+                    uint32_t *trace, hipStream_t st)
+{
+    if (!b) throw Error(HSIM_E_ARG, "run: NULL batch");
+    if (!b->bound) throw Error(HSIM_E_STATE, "run before bind");
+    if (first_step < 0 || n_steps < 0 || first_step + n_steps > b->S_hist)
+        throw Error(HSIM_E_ARG, "run: steps outside the bound history");
+    if (n_steps > 0 && (!T || !B)) throw Error(HSIM_E_ARG, "run: NULL schedule");
+    if (P < 0) throw Error(HSIM_E_ARG, "run: negative recompute period");
+    if (launch < HSIM_LAUNCH_PLAIN || launch > HSIM_LAUNCH_AUTO) throw Error(HSIM_E_ARG, "bad launch mode");
+    const bool want_trace = (flags & HSIM_RUN_TRACE_ACCEPTS) != 0;
+    if (want_trace && !trace) throw Error(HSIM_E_ARG, "run: trace requested without a buffer");
+    if (want_trace && b->layout == HSIM_LAYOUT_REPLICA)
+        throw Error(HSIM_E_UNSUPPORTED, "accept trace needs the site or block layout");
+    for (int r = 0; r < b->R; ++r)
+        for (int s = 0; s < n_steps; ++s) {
+            const double t = T[(size_t)r * n_steps + s], f = B[(size_t)r * n_steps + s];
+            if (!(t >= 0.0)) throw Error(HSIM_E_PARAM, "temperature must be >= 0");
+            if (!std::isfinite(f)) throw Error(HSIM_E_PARAM, "non-finite field");
+            const size_t k = (size_t)r * b->S_hist + first_step + s;
+            b->h_beta[k] = t > 0.0 ? 1.0 / t : std::numeric_limits<double>::infinity();
+            b->h_bfield[k] = f;
+        }
+    if (n_steps == 0) return;
+    const size_t half = (size_t)b->R * b->S_hist;
+    hip_check(hipEventSynchronize(b->stage_done), "hipEventSynchronize");
+    std::memcpy(b->h_stage, b->h_beta.data(), half * 8);
+    std::memcpy(b->h_stage + half, b->h_bfield.data(), half * 8);
+    hip_check(hipMemcpyAsync(b->ws + b->off_beta, b->h_stage, half * 8, hipMemcpyHostToDevice, st),
+              "hipMemcpyAsync");
+    hip_check(hipMemcpyAsync(b->ws + b->off_bfield, b->h_stage + half, half * 8,
+                             hipMemcpyHostToDevice, st),
+              "hipMemcpyAsync");
+    hip_check(hipEventRecord(b->stage_done, st), "hipEventRecord");
+
+    const uint32_t g0 = (uint32_t)first_step * (uint32_t)b->M;
+    const int n_mcs = n_steps * b->M;
+    const hsim::RunArgs ra = b->run_args(g0, n_mcs, P, want_trace ? trace : nullptr);
+    hip_check(hsim::launch_ctl_set(st, ra.ctl, g0), "control launch");
+
+    if (b->layout == HSIM_LAYOUT_BLOCK) {
+        hip_check(hsim::launch_block_sweep(st, b->f64, b->kmode, b->fmode, want_trace, b->lds,
+                                           b->block_threads, b->lds_bytes,
+                                           (const hsim::RepDesc *)b->d_reps.p, ra),
+                  "block sweep launch");
+        return;
+    }
+    int mode = launch;
+    if (mode == HSIM_LAUNCH_AUTO) {
+        if (b->tuned_launch >= 0) mode = b->tuned_launch;
+        else mode = HSIM_LAUNCH_GRAPH;
+    }
+    if (mode == HSIM_LAUNCH_PERSISTENT) {
+        if (b->layout != HSIM_LAYOUT_REPLICA)
+            throw Error(HSIM_E_UNSUPPORTED, "persistent launch needs the replica layout");
+        if (!run_persistent(b, ra, st))
+            throw Error(HSIM_E_UNSUPPORTED, "persistent launch cannot be made co-resident");
+        return;
+    }
+    if (mode == HSIM_LAUNCH_GRAPH) run_graph(b, ra, st);
+    else run_plain(b, ra, st, 0, n_mcs);
+}
+
+void batch_to_user_impl(hsim_batch b, int32_t rep, double *out, hipStream_t st)
+{
+    if (!b || !out || rep < 0 || rep >= b->R) throw Error(HSIM_E_ARG, "spins_to_user: bad argument");
+    if (!b->bound) throw Error(HSIM_E_STATE, "spins_to_user before bind");
+    if (b->layout == HSIM_LAYOUT_REPLICA)
+        hip_check(hsim::launch_to_user_rep(st, b->la, rep, out), "to_user launch");
+    else
+        hip_check(hsim::launch_to_user(st, b->f64, (const hsim::RepDesc *)b->d_reps.p, rep,
+                                       (int)b->plans[rep]->n, out),
+                  "to_user launch");
+}
+
+int32_t batch_status_impl(hsim_batch b)
+{
+    if (!b || !b->bound) throw Error(HSIM_E_STATE, "status before bind");
+    uint32_t s = 0;
+    auto *ctl = (hsim::Ctl *)b->ws;
+    hip_check(hipMemcpy(&s, &ctl->status, 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    const uint32_t z = 0;
+    hip_check(hipMemcpy(&ctl->status, &z, 4, hipMemcpyHostToDevice), "hipMemcpy");
+    if (s & 2u) return HSIM_E_TIMEOUT;
+    if (s & 1u) return HSIM_E_NUMERIC;
+    return 0;
+}
+
+// ---------------------------------------------------------------- autotune
+// Times the launch modes (and persistent grid sizes) available for this
+// batch on trial_mcs MCS of a scratch binding, restores the spins, and keeps
+// the fastest choice for HSIM_LAUNCH_AUTO.  Every candidate runs the same
+// per-site update and the same reduction order, so the choice changes
+// neither spins nor history.
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+
+namespace {
+
+std::string tune_key(hsim_batch b)
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    (void)hipGetDevice(&dev);
+    (void)hipGetDeviceProperties(&prop, dev);
+    std::ostringstream k;
+    k << prop.gcnArchName << ":" << prop.multiProcessorCount << ":L" << b->layout << ":R" << b->R
+      << ":P" << (b->f64 ? 64 : 32);
+    for (auto p : b->plans) {
+        k << ":" << p->n << "/" << p->nnz << "/" << p->ncol;
+        if (b->layout == HSIM_LAYOUT_REPLICA) break;
+    }
+    return k.str();
+}
+
+}  // namespace
+
+void autotune_impl(hsim_batch b, const char *cache_path, int32_t trial_mcs, hipStream_t st)
+{
+    if (!b) throw Error(HSIM_E_ARG, "autotune: NULL batch");
+    if (!b->bound) throw Error(HSIM_E_STATE, "autotune before bind");
+    if (trial_mcs < 1) throw Error(HSIM_E_ARG, "autotune: trial_mcs must be >= 1");
+    if (b->layout == HSIM_LAYOUT_BLOCK) return;   // a single launch: nothing to choose
+    const std::string key = tune_key(b);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string k;
+        int mode, grid;
+        while (in >> k >> mode >> grid)
+            if (k == key) {
+                b->tuned_launch = mode;
+                b->persistent_grid = grid;
+                return;
+            }
+    }
+    // scratch binding: one step of trial_mcs MCS
+    size_t wsb = 0, spb = 0, hb = 0;
+    batch_sizes_impl(b, 1, trial_mcs, &wsb, &spb, &hb);
+    hsim::DevBuf ws, hist, saved;
+    ws.alloc(wsb);
+    hist.alloc(hb);
+    saved.alloc(spb);
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    hip_check(hipMemcpy(saved.p, b->spins, spb, hipMemcpyDeviceToDevice), "hipMemcpy");
+    // keep the caller's binding to restore it afterwards
+    const int32_t S0 = b->S_hist, M0 = b->M;
+    char *ws0 = b->ws;
+    void *sp0 = b->spins;
+    double *h0 = b->history;
+    const std::vector<double> beta0 = b->h_beta, bf0 = b->h_bfield;
+    std::vector<double> T(b->R), B(b->R);
+    for (int r = 0; r < b->R; ++r) {
+        const double be = beta0.empty() ? 1.0 : beta0[(size_t)r * S0];
+        T[r] = (be > 0.0 && std::isfinite(be)) ? 1.0 / be : 1.0;
+        B[r] = bf0.empty() ? 0.0 : bf0[(size_t)r * S0];
+    }
+    struct Cand { int mode, grid; };
+    std::vector<Cand> cands = {{HSIM_LAUNCH_PLAIN, 0}, {HSIM_LAUNCH_GRAPH, 0}};
+    if (b->layout == HSIM_LAYOUT_REPLICA) {
+        const int bpc = hsim::rep_persistent_blocks_per_cu(b->kmode, b->fmode, b->Rp % 64 == 0 ? 64 : 32);
+        const int cus = device_cus();
+        for (int f : {1, 2, 4, 8})
+            if (bpc >= f && cus > 0) cands.push_back({HSIM_LAUNCH_PERSISTENT, f * cus});
+    }
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    float best = 1e30f;
+    Cand win = cands[0];
+    std::string err;
+    try {
+        batch_bind_impl(b, 1, trial_mcs, ws.p, b->spins, hist.p);
+        for (const Cand &c : cands) {
+            b->persistent_grid = c.grid;
+            float ms_best = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                hip_check(hipMemcpyAsync(b->spins, saved.p, spb, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+                hip_check(hipEventRecord(e0, st), "hipEventRecord");
+                batch_run_impl(b, 0, 1, T.data(), B.data(), 100, (hsim_launch)c.mode, 0, nullptr, st);
+                hip_check(hipEventRecord(e1, st), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0.0f;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                ms_best = std::min(ms_best, ms);
+            }
+            if (batch_status_impl(b) != 0) continue;   // a timed-out barrier disqualifies
+            if (ms_best < best) {
+                best = ms_best;
+                win = c;
+            }
+        }
+    } catch (const std::exception &e) {
+        err = e.what();
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // restore spins and the caller's binding
+    hip_check(hipMemcpy(sp0, saved.p, spb, hipMemcpyDeviceToDevice), "hipMemcpy");
+    batch_bind_impl(b, S0, M0, ws0, sp0, h0);
+    b->h_beta = beta0;
+    b->h_bfield = bf0;
+    if (!err.empty()) throw Error(HSIM_E_DEVICE, "autotune: " + err);
+    b->tuned_launch = win.mode;
+    b->persistent_grid = win.grid;
+    if (cache_path) {
+        std::ofstream out(cache_path, std::ios::app);
+        out << key << " " << win.mode << " " << win.grid << "\n";
+    }
+}

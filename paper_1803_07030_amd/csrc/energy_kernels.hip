@@ -1,0 +1,306 @@
+// Energy of Eq. 1 (paper, section "Classical spin Hamiltonian") for a batch of
+// configurations of one lattice, its vector-Jacobian product with respect to
+// the spins, the per-bond exchange constants, the per-site anisotropy
+// constants and the field intensity, and the fluctuation estimator that turns
+// sampled derivatives into derivatives of thermal averages.
+//
+// Layout (user order): spins [batch][3][n]; per-bond constants in the plan's
+// bond order; anisotropy axes and field directions [3][n].
+//
+// The work is a sparse gather (each site reads its neighbours), so it is
+// bandwidth-bound: spins stream from HBM once per pass while the lattice
+// tables (a few MB) stay in L2.  Sums over sites and configurations are done
+// in double precision in a fixed order (wave butterfly, waves in order,
+// tiles in order, batch chunks in order).
+#include "hsim_dev.h"
+
+namespace hsim {
+
+namespace {
+
+constexpr int kEBlock = 256;
+constexpr int kEChunk = 64;   // configurations per batch chunk of the parameter gradients
+
+__device__ __forceinline__ double wsum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block sum of one double, valid in thread 0.
+__device__ __forceinline__ double bsum(double v, double *lds)
+{
+    v = wsum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += lds[k];
+    __syncthreads();
+    return t;
+}
+
+template <typename T>
+struct Site {
+    T sx, sy, sz, hx, hy, hz, k, ex, ey, ez, nx, ny, nz;
+};
+
+template <typename T>
+__device__ __forceinline__ Site<T> load_site(const EnergyArgs &a, int b, int64_t i)
+{
+    const T *S = (const T *)a.S + (size_t)b * 3 * a.n;
+    const T *Jb = (const T *)a.Jb;
+    Site<T> s;
+    s.sx = S[i];
+    s.sy = S[a.n + i];
+    s.sz = S[2 * a.n + i];
+    T hx = 0, hy = 0, hz = 0;
+    for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+        const int64_t j = a.ci[p];
+        const T J = Jb[a.bond[p]];
+        hx += J * S[j];
+        hy += J * S[a.n + j];
+        hz += J * S[2 * a.n + j];
+    }
+    s.hx = hx;
+    s.hy = hy;
+    s.hz = hz;
+    const T *kk = (const T *)a.k, *ax = (const T *)a.ax, *nd = (const T *)a.nd;
+    s.k = kk ? kk[i] : T(0);
+    s.ex = ax ? ax[i] : T(0);
+    s.ey = ax ? ax[a.n + i] : T(0);
+    s.ez = ax ? ax[2 * a.n + i] : T(1);
+    s.nx = nd ? nd[i] : T(0);
+    s.ny = nd ? nd[a.n + i] : T(0);
+    s.nz = nd ? nd[2 * a.n + i] : T(1);
+    return s;
+}
+
+}  // namespace
+
+// grid (site tiles, batch).  Forward: E partial per (config, tile).  Backward
+// (gE != NULL): also dE/dS of every site and the dE/dB partial.
+template <typename T, bool BWD>
+__global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const double *gE, T *gS,
+                                                         double *partE, double *partB)
+{
+    __shared__ double red[kEBlock / 64];
+    const int b = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * kEBlock + threadIdx.x;
+    double e = 0.0, zn = 0.0;
+    if (i < a.n) {
+        const Site<T> s = load_site<T>(a, b, i);
+        const double sx = s.sx, sy = s.sy, sz = s.sz;
+        const double an = sx * (double)s.ex + sy * (double)s.ey + sz * (double)s.ez;
+        zn = sx * (double)s.nx + sy * (double)s.ny + sz * (double)s.nz;
+        e = -0.5 * (sx * (double)s.hx + sy * (double)s.hy + sz * (double)s.hz) - a.B * zn -
+            (double)s.k * an * an;
+        if (BWD) {
+            const T g = (T)gE[b];
+            const T B = (T)a.B;
+            const T an_t = s.sx * s.ex + s.sy * s.ey + s.sz * s.ez;
+            const T two_ka = T(2) * s.k * an_t;
+            T *o = gS + (size_t)b * 3 * a.n;
+            o[i] = g * (-s.hx - B * s.nx - two_ka * s.ex);
+            o[a.n + i] = g * (-s.hy - B * s.ny - two_ka * s.ey);
+            o[2 * a.n + i] = g * (-s.hz - B * s.nz - two_ka * s.ez);
+        }
+    }
+    const double et = bsum(e, red);
+    double zt = 0.0;
+    if (BWD) zt = bsum(zn, red);
+    if (threadIdx.x == 0) {
+        const size_t t = (size_t)b * gridDim.x + blockIdx.x;
+        if (partE) partE[t] = et;
+        if (BWD) partB[t] = -gE[b] * zt;
+    }
+}
+
+// grid (site tiles, batch chunks): dE/dk_i and dE/dJ of the bonds whose lower
+// end is i, summed over the chunk's configurations.
+template <typename T>
+__global__ __launch_bounds__(kEBlock) void k_energy_params(EnergyArgs a, const double *gE,
+                                                           double *partK, double *partJ)
+{
+    const int64_t i = (int64_t)blockIdx.x * kEBlock + threadIdx.x;
+    if (i >= a.n) return;
+    const int c = blockIdx.y;
+    const int b0 = c * kEChunk, b1 = min(a.batch, b0 + kEChunk);
+    const T *ax = (const T *)a.ax;
+    const T ex = ax ? ax[i] : T(0), ey = ax ? ax[a.n + i] : T(0), ez = ax ? ax[2 * a.n + i] : T(1);
+    double gk = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        const T *S = (const T *)a.S + (size_t)b * 3 * a.n;
+        const double an = (double)S[i] * (double)ex + (double)S[a.n + i] * (double)ey +
+                          (double)S[2 * a.n + i] * (double)ez;
+        gk += gE[b] * -(an * an);
+    }
+    partK[(size_t)c * a.n + i] = gk;
+    for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+        const int64_t j = a.ci[p];
+        if (j <= i) continue;
+        double gj = 0.0;
+        for (int b = b0; b < b1; ++b) {
+            const T *S = (const T *)a.S + (size_t)b * 3 * a.n;
+            const double d = (double)S[i] * (double)S[j] + (double)S[a.n + i] * (double)S[a.n + j] +
+                             (double)S[2 * a.n + i] * (double)S[2 * a.n + j];
+            gj += gE[b] * -d;
+        }
+        partJ[(size_t)c * a.nnz + p] = gj;
+    }
+}
+
+// Sums in order: E[b] over tiles; gJ over chunks (at each bond's lower-end
+// entry); gk over chunks; gB over (config, tile) records.
+template <typename T>
+__global__ __launch_bounds__(256) void k_energy_finish(EnergyArgs a, int ntile, int nchunk,
+                                                       const double *partE, double *E,
+                                                       const double *partK, const double *partJ,
+                                                       const int32_t *fwd_entry, T *gJ, T *gk,
+                                                       const double *partB, double *gB)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (E && t < a.batch) {
+        double v = 0.0;
+        for (int k = 0; k < ntile; ++k) v += partE[(size_t)t * ntile + k];
+        E[t] = v;
+    }
+    if (gJ && t < a.nb) {
+        const int64_t p = fwd_entry[t];
+        double v = 0.0;
+        for (int c = 0; c < nchunk; ++c) v += partJ[(size_t)c * a.nnz + p];
+        gJ[t] = (T)v;
+    }
+    if (gk && t < a.n) {
+        double v = 0.0;
+        for (int c = 0; c < nchunk; ++c) v += partK[(size_t)c * a.n + t];
+        gk[t] = (T)v;
+    }
+    if (gB && t == 0) {
+        double v = 0.0;
+        for (int64_t k = 0; k < (int64_t)a.batch * ntile; ++k) v += partB[k];
+        gB[0] = v;
+    }
+}
+
+int64_t energy_scratch_doubles(int64_t n, int64_t nnz, int batch, int)
+{
+    const int64_t ntile = (n + kEBlock - 1) / kEBlock;
+    const int64_t nchunk = (batch + kEChunk - 1) / kEChunk;
+    // partE, partB: batch*ntile each; partK: nchunk*n; partJ: nchunk*nnz
+    return 2 * (int64_t)batch * ntile + nchunk * n + nchunk * nnz;
+}
+
+hipError_t launch_energy_forward(hipStream_t st, bool f64, const EnergyArgs &a, double *scratch,
+                                 int, double *E)
+{
+    const int ntile = (int)((a.n + kEBlock - 1) / kEBlock);
+    dim3 grid((unsigned)ntile, (unsigned)a.batch);
+    double *partE = scratch;
+    if (f64)
+        hipLaunchKernelGGL((k_energy_site<double, false>), grid, dim3(kEBlock), 0, st, a,
+                           (const double *)nullptr, (double *)nullptr, partE, (double *)nullptr);
+    else
+        hipLaunchKernelGGL((k_energy_site<float, false>), grid, dim3(kEBlock), 0, st, a,
+                           (const double *)nullptr, (float *)nullptr, partE, (double *)nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 g2((unsigned)((a.batch + 255) / 256));
+    if (f64)
+        hipLaunchKernelGGL((k_energy_finish<double>), g2, dim3(256), 0, st, a, ntile, 0, partE, E,
+                           (const double *)nullptr, (const double *)nullptr,
+                           (const int32_t *)nullptr, (double *)nullptr, (double *)nullptr,
+                           (const double *)nullptr, (double *)nullptr);
+    else
+        hipLaunchKernelGGL((k_energy_finish<float>), g2, dim3(256), 0, st, a, ntile, 0, partE, E,
+                           (const double *)nullptr, (const double *)nullptr,
+                           (const int32_t *)nullptr, (float *)nullptr, (float *)nullptr,
+                           (const double *)nullptr, (double *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_backward(hipStream_t st, bool f64, const EnergyArgs &a, const double *gE,
+                                  void *gS, void *gJ, void *gk, double *gB, double *scratch,
+                                  int)
+{
+    const int ntile = (int)((a.n + kEBlock - 1) / kEBlock);
+    const int nchunk = (a.batch + kEChunk - 1) / kEChunk;
+    double *partE = scratch;
+    double *partB = partE + (size_t)a.batch * ntile;
+    double *partK = partB + (size_t)a.batch * ntile;
+    double *partJ = partK + (size_t)nchunk * a.n;
+    const int32_t *fwd = a.fwd_entry;
+    dim3 grid((unsigned)ntile, (unsigned)a.batch);
+    if (gS || gB) {
+        if (f64)
+            hipLaunchKernelGGL((k_energy_site<double, true>), grid, dim3(kEBlock), 0, st, a, gE,
+                               (double *)gS, (double *)nullptr, partB);
+        else
+            hipLaunchKernelGGL((k_energy_site<float, true>), grid, dim3(kEBlock), 0, st, a, gE,
+                               (float *)gS, (double *)nullptr, partB);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (gJ || gk) {
+        dim3 g2((unsigned)ntile, (unsigned)nchunk);
+        if (f64)
+            hipLaunchKernelGGL(k_energy_params<double>, g2, dim3(kEBlock), 0, st, a, gE, partK, partJ);
+        else
+            hipLaunchKernelGGL(k_energy_params<float>, g2, dim3(kEBlock), 0, st, a, gE, partK, partJ);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    int64_t m = a.nb;
+    if (a.n > m) m = a.n;
+    if (m < 1) m = 1;
+    dim3 g3((unsigned)((m + 255) / 256));
+    if (f64)
+        hipLaunchKernelGGL((k_energy_finish<double>), g3, dim3(256), 0, st, a, ntile, nchunk,
+                           (const double *)nullptr, (double *)nullptr, partK, partJ, fwd,
+                           (double *)gJ, (double *)gk, (const double *)partB, gB);
+    else
+        hipLaunchKernelGGL((k_energy_finish<float>), g3, dim3(256), 0, st, a, ntile, nchunk,
+                           (const double *)nullptr, (double *)nullptr, partK, partJ, fwd,
+                           (float *)gJ, (float *)gk, (const double *)partB, gB);
+    return hipGetLastError();
+}
+
+// d<O>/dtheta = <dO> - beta (<O dE> - <O><dE>): one block, fixed-order sums.
+__global__ __launch_bounds__(1024) void k_fluct(int64_t n, double beta, const double *O,
+                                                const double *dE, const double *dO, double *out)
+{
+    __shared__ double red[16];
+    double so = 0.0, se = 0.0, sd = 0.0;
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+        so += O[t];
+        se += dE[t];
+        if (dO) sd += dO[t];
+    }
+    const double mo = bsum(so, red) / (double)n;
+    const double me = bsum(se, red) / (double)n;
+    const double md = bsum(sd, red) / (double)n;
+    __shared__ double mean[2];
+    if (threadIdx.x == 0) {
+        mean[0] = mo;
+        mean[1] = me;
+    }
+    __syncthreads();
+    double sc = 0.0;
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) sc += (O[t] - mean[0]) * (dE[t] - mean[1]);
+    const double cov = bsum(sc, red) / (double)n;
+    if (threadIdx.x == 0) {
+        out[0] = md - beta * cov;
+        out[1] = cov;
+    }
+}
+
+hipError_t launch_fluct(hipStream_t st, int64_t n, double beta, const double *O, const double *dE,
+                        const double *dO, double *out)
+{
+    hipLaunchKernelGGL(k_fluct, dim3(1), dim3(1024), 0, st, n, beta, O, dE, dO, out);
+    return hipGetLastError();
+}
+
+}  // namespace hsim

@@ -1,0 +1,142 @@
+// Device-visible structures of libhsim and the launchers the host code calls.
+// Shared by the host orchestration (plan.cpp, batch.cpp) and the kernels
+// (*.hip); nothing here is visible at the C-ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hsim {
+
+constexpr int kMaxColours = 32;     // colour classes per lattice
+constexpr int kSiteBlock = 256;     // threads per block of the site-lane kernels
+constexpr int kRepWaves = 4;        // waves per block of the replica-lane kernels
+constexpr int kRepSitesPerWave = 32;
+constexpr int kRepTile = kRepWaves * kRepSitesPerWave;   // sites per replica-lane tile
+constexpr int kRecSite = 8;         // doubles per site-lane partial record
+constexpr int kRecFields = 6;       // dE, Mx, My, Mz, n_acc, E_full
+
+// How the anisotropy and field-direction terms are read.
+enum KMode : int { K_NONE = 0, K_UNIFORM = 1, K_SITE = 2 };
+enum FMode : int { F_UNIFORM = 0, F_SITE = 1 };
+
+// One replica: its lattice (internal colour-sorted order) and its spins.
+struct RepDesc {
+    const int32_t *rp;        // n+1 CSR row offsets
+    const int32_t *ci;        // nnz internal column indices
+    const void *J;            // nnz constants (float or double)
+    const uint32_t *orig;     // n user index of each internal site
+    const void *k;            // n (K_SITE)
+    const void *ax;           // [3][n] (K_SITE), stride n
+    const void *nd;           // [3][n] (F_SITE), stride n
+    void *spins;              // [3][n_pad] of this replica (site and block layouts)
+    double k0, e0[3], n0[3];  // uniform values (K_UNIFORM / F_UNIFORM)
+    int64_t user_off;         // offset of this replica in replica-concatenated user arrays
+    int32_t n, n_pad;
+    uint32_t rep_id;
+    int32_t ncol;
+    int32_t cls_off[kMaxColours + 1];
+};
+
+// A block's share of one colour phase of one replica: internal sites [begin, end).
+struct Tile {
+    int32_t rep, begin, end, colour;
+};
+
+// Run-control word block at the start of the workspace.
+struct Ctl {
+    uint32_t g;          // absolute MCS counter of the MCS in progress
+    uint32_t status;     // HSIM_E_* bits seen on the device
+    uint32_t bar_arrive; // persistent-launch barrier
+    uint32_t pad[61];
+};
+
+// Constants of one run, passed by value to every kernel of the run.
+struct RunArgs {
+    Ctl *ctl;
+    const double *beta;   // [R][S_hist]
+    const double *bfield; // [R][S_hist]
+    double *ecarry;       // [R]
+    double *partials;     // records
+    double *history;      // [R][S_hist][M][5]
+    uint32_t *trace;      // NULL or [R][n_mcs_run][words]
+    uint64_t seed;
+    uint32_t g0;          // first g of the run
+    int32_t M;            // MCS per step
+    int32_t S_hist;       // steps in the bound history
+    int32_t P;            // recompute period (0: step start only)
+    int32_t n_mcs_run;    // MCS in this run
+    int32_t trace_words;  // words per replica per MCS
+    int32_t R;
+};
+
+struct RepLaneArgs {
+    const int32_t *rp, *ci;
+    const float *J;
+    const uint32_t *orig;
+    const float *k, *ax, *nd;   // per-site (K_SITE / F_SITE)
+    float *spins;               // [3][n][Rp]
+    const uint32_t *rep_id;     // [Rp]
+    float k0, e0x, e0y, e0z, n0x, n0y, n0z;
+    int32_t n, Rp, R;
+    int32_t ncol;
+    int32_t cls_off[kMaxColours + 1];
+    int32_t tile_off[kMaxColours + 1];   // first tile of each colour
+};
+
+// ------------------------------------------------------------- launchers
+// All return hipError_t of the launch.  Template choices are resolved inside.
+hipError_t launch_ctl_set(hipStream_t st, Ctl *ctl, uint32_t g);
+hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, uint32_t v, int64_t n);
+
+hipError_t launch_init_spins(hipStream_t st, bool f64, const RepDesc *reps, int R,
+                             int max_n, int mode, const double *given, const int64_t *given_off,
+                             uint64_t seed);
+hipError_t launch_init_spins_rep(hipStream_t st, const RepLaneArgs &a, int mode,
+                                 const double *given, uint64_t seed);
+hipError_t launch_to_user(hipStream_t st, bool f64, const RepDesc *reps, int rep, int n,
+                          double *out);
+hipError_t launch_to_user_rep(hipStream_t st, const RepLaneArgs &a, int rep, double *out);
+
+hipError_t launch_site_phase(hipStream_t st, bool f64, int kmode, int fmode, bool trace,
+                             const RepDesc *reps, const Tile *tiles, int tile_off, int ntiles,
+                             const RunArgs &ra);
+hipError_t launch_site_efull(hipStream_t st, bool f64, int kmode, int fmode, const RepDesc *reps,
+                             const Tile *tiles, int ntiles, const RunArgs &ra);
+hipError_t launch_site_reduce(hipStream_t st, const int32_t *rep_tiles, int ncol_max,
+                              const RunArgs &ra);
+hipError_t launch_block_sweep(hipStream_t st, bool f64, int kmode, int fmode, bool trace,
+                              bool lds, int threads, size_t lds_bytes, const RepDesc *reps,
+                              const RunArgs &ra);
+int block_sweep_max_lds(bool f64);
+
+hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour,
+                            const RepLaneArgs &a, const RunArgs &ra);
+hipError_t launch_rep_efull(hipStream_t st, int kmode, int fmode, const RepLaneArgs &a,
+                            int ntiles, const RunArgs &ra);
+hipError_t launch_rep_reduce(hipStream_t st, const RepLaneArgs &a, int ntiles,
+                             const RunArgs &ra);
+hipError_t launch_rep_persistent(hipStream_t st, int kmode, int fmode, const RepLaneArgs &a,
+                                 int ntiles, int grid, const RunArgs &ra, uint32_t spin_cap);
+int rep_persistent_blocks_per_cu(int kmode, int fmode, int lane_w);
+
+// energy
+struct EnergyArgs {
+    const int64_t *rp;      // user-order CSR (n+1)
+    const int32_t *ci;      // nnz
+    const int32_t *bond;    // nnz: bond id of each entry
+    const int32_t *fwd_entry; // nb: the CSR entry of each bond at its lower end
+    int64_t n, nnz, nb;
+    int batch;
+    const void *S, *Jb, *k, *ax, *nd;
+    double B;
+};
+hipError_t launch_energy_forward(hipStream_t st, bool f64, const EnergyArgs &a, double *partial,
+                                 int nchunk, double *E);
+hipError_t launch_energy_backward(hipStream_t st, bool f64, const EnergyArgs &a,
+                                  const double *gE, void *gS, void *gJ, void *gk, double *gB,
+                                  double *scratch, int nchunk);
+int64_t energy_scratch_doubles(int64_t n, int64_t nb, int batch, int nchunk);
+hipError_t launch_fluct(hipStream_t st, int64_t n, double beta, const double *O,
+                        const double *dE, const double *dO, double *out);
+
+}  // namespace hsim

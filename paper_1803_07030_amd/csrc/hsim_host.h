@@ -1,0 +1,139 @@
+// Host-side objects behind the C-ABI: plans (one lattice each) and batches
+// (replicas over plans, their tiles and launch state).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hsim.h"
+#include "hsim_dev.h"
+
+namespace hsim {
+
+// Error carrying an hsim_status code; caught at the C-ABI boundary.
+struct Error : std::runtime_error {
+    hsim_status code;
+    Error(hsim_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+inline void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess)
+        throw Error(HSIM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device allocation owned by a plan or batch.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T *upload(const std::vector<T> &v)
+    {
+        release();
+        bytes = v.size() * sizeof(T);
+        if (bytes == 0) bytes = sizeof(T);
+        hip_check(hipMalloc(&p, bytes), "hipMalloc");
+        if (!v.empty()) hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+        return (T *)p;
+    }
+    void *alloc(size_t b)
+    {
+        release();
+        bytes = b ? b : 16;
+        hip_check(hipMalloc(&p, bytes), "hipMalloc");
+        return p;
+    }
+};
+
+}  // namespace hsim
+
+struct hsim_plan_s {
+    int64_t n = 0, nnz = 0, nb = 0;
+    int32_t ncol = 0, maxdeg = 0;
+    std::vector<int32_t> colour;          // user order
+    std::vector<int32_t> perm;            // internal -> user
+    std::vector<int32_t> inv;             // user -> internal
+    std::vector<int32_t> cls_off;         // ncol+1
+    // internal CSR (colour-sorted rows, each row's entry order kept)
+    std::vector<int32_t> rp, ci;
+    std::vector<double> Jd;
+    std::vector<float> Jf;
+    // per-site parameters, internal order, [n] and [3][n]
+    std::vector<double> kd, axd, ndd;
+    std::vector<float> kf, axf, ndf;
+    int kmode = 0, fmode = 0;
+    double k0 = 0.0, e0[3] = {0, 0, 1}, n0[3] = {0, 0, 1};
+    // user-order CSR for the energy and its gradient
+    std::vector<int64_t> urp;
+    std::vector<int32_t> uci, ubond, fwd_entry, bond_ij;
+
+    // device copies (uploaded on first use)
+    bool sweep_on_device = false, energy_on_device = false;
+    hsim::DevBuf d_rp, d_ci, d_Jf, d_Jd, d_orig, d_kf, d_kd, d_axf, d_axd, d_ndf, d_ndd;
+    hsim::DevBuf d_urp, d_uci, d_ubond, d_fwd, d_scratch;
+
+    void upload_sweep();
+    void upload_energy();
+};
+
+struct hsim_batch_s {
+    int32_t R = 0;
+    std::vector<hsim_plan> plans;
+    std::vector<uint32_t> rep_id;
+    uint64_t seed = 0;
+    bool f64 = false;
+    int layout = HSIM_LAYOUT_SITE;
+    int kmode = 0, fmode = 0;
+    int ncol_max = 0;
+    int64_t total_sites = 0;
+    bool lds = false;
+    int block_threads = 256;
+    size_t lds_bytes = 0;
+
+    // site and block layouts
+    std::vector<hsim::RepDesc> reps;
+    std::vector<hsim::Tile> tiles;
+    std::vector<int32_t> rep_tiles;   // [R][ncol_max][2]
+    std::vector<int32_t> tile_off;    // ncol_max+1
+    std::vector<int64_t> spin_off;    // elements, per replica
+    int64_t spin_elems = 0;
+    // replica layout
+    int32_t Rp = 0;
+    int32_t rep_ntiles = 0;
+    hsim::RepLaneArgs la{};
+
+    hsim::DevBuf d_reps, d_tiles, d_rep_tiles, d_rep_id;
+    bool tables_on_device = false;
+
+    // binding
+    bool bound = false;
+    int32_t S_hist = 0, M = 0;
+    char *ws = nullptr;
+    void *spins = nullptr;
+    double *history = nullptr;
+    size_t off_ecarry = 0, off_beta = 0, off_bfield = 0, off_part = 0, ws_bytes = 0;
+    std::vector<double> h_beta, h_bfield;   // [R][S_hist]
+    double *h_stage = nullptr;              // pinned staging of beta and bfield
+    hipEvent_t stage_done = nullptr;
+
+    // tuning
+    int tuned_launch = -1;
+    int persistent_grid = 0;
+
+    ~hsim_batch_s();
+    void upload_tables();
+    hsim::RunArgs run_args(uint32_t g0, int n_mcs, int P, uint32_t *trace);
+};

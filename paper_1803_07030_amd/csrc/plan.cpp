@@ -1,0 +1,303 @@
+// Lattice ingest (host): validation, greedy breadth-first colouring,
+// colour-sorted permutation, internal CSR, bond tables; and the energy /
+// gradient entry points, which work on one plan.
+//
+// Paper: the material file of section "Material building" (sites, exchange
+// links with constants, a field axis per site) and the anisotropy file of
+// section "File Formats" (a constant and an axis per site) become CSR arrays
+// with per-entry constants and per-site parameters.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "hsim_host.h"
+
+using hsim::Error;
+
+namespace {
+
+double norm3(const double *v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+void validate(int64_t n, const int64_t *rp, const int32_t *col, const double *J, const double *k,
+              const double *axis, const double *fd)
+{
+    if (n < 0 || n > INT32_MAX - 64) throw Error(HSIM_E_ARG, "n_sites out of range");
+    if (!rp) throw Error(HSIM_E_ARG, "row_ptr is NULL");
+    if (rp[0] != 0) throw Error(HSIM_E_CSR, "row_ptr[0] != 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) throw Error(HSIM_E_CSR, "row_ptr not non-decreasing");
+    const int64_t nnz = rp[n];
+    if (nnz > INT32_MAX) throw Error(HSIM_E_ARG, "too many CSR entries");
+    if (nnz > 0 && (!col || !J)) throw Error(HSIM_E_ARG, "col or J is NULL");
+    // in range, no self loop, finite constants
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            if (col[p] < 0 || col[p] >= n) throw Error(HSIM_E_CSR, "column index out of range");
+            if (col[p] == i) throw Error(HSIM_E_CSR, "self loop");
+            if (!std::isfinite(J[p])) throw Error(HSIM_E_PARAM, "non-finite exchange constant");
+        }
+    // no duplicate link in a row; every entry has its reverse with an equal constant
+    std::vector<int64_t> mark(n, -1);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            if (mark[col[p]] == i) throw Error(HSIM_E_CSR, "duplicate link");
+            mark[col[p]] = i;
+        }
+    }
+    // every entry (i -> j) has its reverse (j -> i) with an equal constant
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            const int64_t j = col[p];
+            int64_t q = rp[j];
+            while (q < rp[j + 1] && col[q] != i) ++q;
+            if (q == rp[j + 1]) throw Error(HSIM_E_CSR, "link without its reverse entry");
+            if (J[q] != J[p]) throw Error(HSIM_E_PARAM, "exchange constants not symmetric");
+        }
+    for (int64_t i = 0; i < n; ++i) {
+        if (k && !std::isfinite(k[i])) throw Error(HSIM_E_PARAM, "non-finite anisotropy constant");
+        if (axis && !(std::fabs(norm3(axis + 3 * i) - 1.0) <= 1e-9))
+            throw Error(HSIM_E_PARAM, "anisotropy axis is not a unit vector");
+        if (fd && !(std::fabs(norm3(fd + 3 * i) - 1.0) <= 1e-9))
+            throw Error(HSIM_E_PARAM, "field direction is not a unit vector");
+    }
+}
+
+// Greedy colouring in breadth-first order: components by lowest site index,
+// neighbours queued in CSR order, each site takes the smallest colour not
+// carried by an already coloured neighbour.
+int32_t bfs_greedy(int64_t n, const int64_t *rp, const int32_t *col, std::vector<int32_t> &c,
+                   int32_t &maxdeg)
+{
+    maxdeg = 0;
+    for (int64_t i = 0; i < n; ++i) maxdeg = std::max<int32_t>(maxdeg, (int32_t)(rp[i + 1] - rp[i]));
+    c.assign(n, -1);
+    std::vector<int64_t> used(maxdeg + 2, -1), queue;
+    queue.reserve(n);
+    int32_t ncol = 0;
+    size_t head = 0;
+    for (int64_t root = 0; root < n; ++root) {
+        if (c[root] != -1) continue;
+        c[root] = -2;
+        queue.push_back(root);
+        while (head < queue.size()) {
+            const int64_t i = queue[head++];
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+                const int32_t j = col[p];
+                if (c[j] >= 0) used[c[j]] = i;
+                else if (c[j] == -1) {
+                    c[j] = -2;
+                    queue.push_back(j);
+                }
+            }
+            int32_t k = 0;
+            while (used[k] == i) ++k;
+            c[i] = k;
+            ncol = std::max(ncol, k + 1);
+        }
+    }
+    return ncol;
+}
+
+}  // namespace
+
+hsim_plan plan_create_impl(int64_t n, const int64_t *rp, const int32_t *col, const double *J,
+                           const double *k, const double *axis, const double *fd)
+{
+    validate(n, rp, col, J, k, axis, fd);
+    auto *P = new hsim_plan_s();
+    try {
+        P->n = n;
+        P->nnz = rp[n];
+        P->nb = P->nnz / 2;
+        P->ncol = bfs_greedy(n, rp, col, P->colour, P->maxdeg);
+        if (P->ncol > hsim::kMaxColours)
+            throw Error(HSIM_E_UNSUPPORTED, "lattice needs more than 32 colours");
+        // colour-sorted order, user index inside a class
+        P->perm.resize(n);
+        std::iota(P->perm.begin(), P->perm.end(), 0);
+        std::stable_sort(P->perm.begin(), P->perm.end(),
+                         [&](int32_t a, int32_t b) { return P->colour[a] < P->colour[b]; });
+        P->inv.resize(n);
+        for (int64_t t = 0; t < n; ++t) P->inv[P->perm[t]] = (int32_t)t;
+        P->cls_off.assign(P->ncol + 1, 0);
+        for (int64_t i = 0; i < n; ++i) P->cls_off[P->colour[i] + 1]++;
+        for (int c = 0; c < P->ncol; ++c) P->cls_off[c + 1] += P->cls_off[c];
+        // internal CSR
+        P->rp.resize(n + 1);
+        P->ci.resize(P->nnz);
+        P->Jd.resize(P->nnz);
+        P->rp[0] = 0;
+        for (int64_t t = 0; t < n; ++t) {
+            const int64_t i = P->perm[t];
+            int32_t q = P->rp[t];
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p, ++q) {
+                P->ci[q] = P->inv[col[p]];
+                P->Jd[q] = J[p];
+            }
+            P->rp[t + 1] = q;
+        }
+        P->Jf.assign(P->Jd.begin(), P->Jd.end());
+        // per-site parameters, internal order
+        P->kd.resize(n);
+        P->axd.resize(3 * n);
+        P->ndd.resize(3 * n);
+        for (int64_t t = 0; t < n; ++t) {
+            const int64_t i = P->perm[t];
+            P->kd[t] = k ? k[i] : 0.0;
+            for (int c = 0; c < 3; ++c) {
+                P->axd[c * n + t] = axis ? axis[3 * i + c] : (c == 2 ? 1.0 : 0.0);
+                P->ndd[c * n + t] = fd ? fd[3 * i + c] : (c == 2 ? 1.0 : 0.0);
+            }
+        }
+        P->kf.assign(P->kd.begin(), P->kd.end());
+        P->axf.assign(P->axd.begin(), P->axd.end());
+        P->ndf.assign(P->ndd.begin(), P->ndd.end());
+        bool kzero = true, kuni = true, nuni = true;
+        for (int64_t t = 0; t < n; ++t) {
+            if (P->kd[t] != 0.0) kzero = false;
+            if (P->kd[t] != P->kd[0]) kuni = false;
+            for (int c = 0; c < 3; ++c) {
+                if (P->axd[c * n + t] != P->axd[c * n]) kuni = false;
+                if (P->ndd[c * n + t] != P->ndd[c * n]) nuni = false;
+            }
+        }
+        P->kmode = kzero ? hsim::K_NONE : (kuni ? hsim::K_UNIFORM : hsim::K_SITE);
+        P->fmode = nuni ? hsim::F_UNIFORM : hsim::F_SITE;
+        if (n > 0) {
+            P->k0 = P->kd[0];
+            for (int c = 0; c < 3; ++c) {
+                P->e0[c] = P->kmode == hsim::K_NONE ? (c == 2 ? 1.0 : 0.0) : P->axd[c * n];
+                P->n0[c] = P->ndd[c * n];
+            }
+        }
+        // user-order CSR with bond ids (bond b = b-th entry with col > row)
+        P->urp.assign(rp, rp + n + 1);
+        P->uci.assign(col, col + P->nnz);
+        P->ubond.assign(P->nnz, -1);
+        P->fwd_entry.clear();
+        P->bond_ij.clear();
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+                if (col[p] > i) {
+                    P->ubond[p] = (int32_t)P->fwd_entry.size();
+                    P->fwd_entry.push_back((int32_t)p);
+                    P->bond_ij.push_back((int32_t)i);
+                    P->bond_ij.push_back(col[p]);
+                }
+        // the reverse entry of a bond gets the same id
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+                const int64_t j = col[p];
+                if (j >= i) continue;
+                int64_t q = rp[j];
+                while (col[q] != i) ++q;   // exists: validated above
+                P->ubond[p] = P->ubond[q];
+            }
+        P->nb = (int64_t)P->fwd_entry.size();
+    } catch (...) {
+        delete P;
+        throw;
+    }
+    return P;
+}
+
+void hsim_plan_s::upload_sweep()
+{
+    if (sweep_on_device) return;
+    std::vector<uint32_t> orig(perm.begin(), perm.end());
+    d_rp.upload(rp);
+    d_ci.upload(ci);
+    d_Jf.upload(Jf);
+    d_Jd.upload(Jd);
+    d_orig.upload(orig);
+    d_kf.upload(kf);
+    d_kd.upload(kd);
+    d_axf.upload(axf);
+    d_axd.upload(axd);
+    d_ndf.upload(ndf);
+    d_ndd.upload(ndd);
+    sweep_on_device = true;
+}
+
+void hsim_plan_s::upload_energy()
+{
+    if (energy_on_device) return;
+    d_urp.upload(urp);
+    d_uci.upload(uci);
+    d_ubond.upload(ubond);
+    d_fwd.upload(fwd_entry);
+    energy_on_device = true;
+}
+
+// ----------------------------------------------------------------- energy
+namespace {
+
+hsim::EnergyArgs energy_args(hsim_plan P, int32_t batch, const void *S, const void *Jb,
+                             const void *k, const void *ax, double B, const void *nd)
+{
+    P->upload_energy();
+    hsim::EnergyArgs a{};
+    a.rp = (const int64_t *)P->d_urp.p;
+    a.ci = (const int32_t *)P->d_uci.p;
+    a.bond = (const int32_t *)P->d_ubond.p;
+    a.fwd_entry = (const int32_t *)P->d_fwd.p;
+    a.n = P->n;
+    a.nnz = P->nnz;
+    a.nb = P->nb;
+    a.batch = batch;
+    a.S = S;
+    a.Jb = Jb;
+    a.k = k;
+    a.ax = ax;
+    a.nd = nd;
+    a.B = B;
+    return a;
+}
+
+double *energy_scratch(hsim_plan P, int32_t batch)
+{
+    const size_t need = (size_t)hsim::energy_scratch_doubles(P->n, P->nnz, batch, 0) * sizeof(double);
+    if (P->d_scratch.bytes < need) {
+        // a smaller scratch may still be read by queued work
+        hsim::hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        P->d_scratch.alloc(need);
+    }
+    return (double *)P->d_scratch.p;
+}
+
+}  // namespace
+
+void energy_forward_impl(hsim_plan P, int32_t batch, hsim_precision prec, const void *S,
+                         const void *Jb, const void *k, const void *ax, double B, const void *nd,
+                         double *E, hipStream_t st)
+{
+    if (!P || batch < 0 || !E || (P->n > 0 && batch > 0 && !S) || (P->nb > 0 && !Jb))
+        throw Error(HSIM_E_ARG, "energy_forward: bad argument");
+    if (prec != HSIM_FP32 && prec != HSIM_FP64_EXACT) throw Error(HSIM_E_ARG, "bad precision");
+    if (!std::isfinite(B)) throw Error(HSIM_E_PARAM, "non-finite field");
+    if (batch == 0) return;
+    const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd);
+    double *scr = energy_scratch(P, batch);
+    hsim::hip_check(hsim::launch_energy_forward(st, prec == HSIM_FP64_EXACT, a, scr, 0, E),
+                    "energy forward launch");
+}
+
+void energy_backward_impl(hsim_plan P, int32_t batch, hsim_precision prec, const void *S,
+                          const void *Jb, const void *k, const void *ax, double B,
+                          const void *nd, const double *gE, void *gS, void *gJ, void *gk,
+                          double *gB, hipStream_t st)
+{
+    if (!P || batch < 0 || (batch > 0 && !gE) || (P->n > 0 && batch > 0 && !S) ||
+        (P->nb > 0 && !Jb))
+        throw Error(HSIM_E_ARG, "energy_backward: bad argument");
+    if (prec != HSIM_FP32 && prec != HSIM_FP64_EXACT) throw Error(HSIM_E_ARG, "bad precision");
+    if (!std::isfinite(B)) throw Error(HSIM_E_PARAM, "non-finite field");
+    if (batch == 0) return;
+    const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd);
+    double *scr = energy_scratch(P, batch);
+    hsim::hip_check(hsim::launch_energy_backward(st, prec == HSIM_FP64_EXACT, a, gE, gS, gJ, gk, gB,
+                                                 scr, 0),
+                    "energy backward launch");
+}

@@ -1,0 +1,506 @@
+// Sweep kernels of the colour-ordered Metropolis Monte Carlo (gfx950, wave64,
+// no MFMA: the update is a sparse gather, not a dense contraction).
+//
+// Paper: Eq. 1-2 (energy), Eq. 4 (acceptance), one attempt per site per MCS
+// (section "Monte Carlo Metropolis algorithm"); history of E and M after every
+// MCS of every temperature/field step (section "VEGAS software package").
+//
+// All sites of one colour class have no link between them, so one class is
+// updated in parallel; classes follow each other, separated by a kernel
+// boundary (site-lane and replica-lane phases), a workgroup barrier (block
+// layout) or a device-wide barrier (persistent launch).
+//
+// History sums are deterministic: each tile (a block's share of a class)
+// reduces its sites in a fixed order (wave butterfly, then waves in order) and
+// the per-MCS reduction adds tile records in table order.
+#include "hsim_dev.h"
+#include "update.h"
+
+namespace hsim {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum NV values over the block; the result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) lds[w * NV + q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int ww = 1; ww < nw; ++ww)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[q] += lds[ww * NV + q];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool recompute_due(uint32_t m, int P)
+{
+    return m == 0 || (P > 0 && (m % (uint32_t)P) == 0);
+}
+
+template <typename T>
+__device__ __forceinline__ T as_t(double v)
+{
+    return (T)v;
+}
+
+// Site parameters: anisotropy constant and axis, field direction.
+template <typename T, int KM, int FM>
+struct SiteParams {
+    T k, ex, ey, ez, nx, ny, nz;
+    __device__ __forceinline__ SiteParams(const RepDesc &rd, int i)
+    {
+        if (KM == K_SITE) {
+            const T *kk = (const T *)rd.k;
+            const T *ax = (const T *)rd.ax;
+            k = kk[i];
+            ex = ax[i];
+            ey = ax[rd.n + i];
+            ez = ax[2 * rd.n + i];
+        } else {
+            k = (KM == K_UNIFORM) ? as_t<T>(rd.k0) : T(0);
+            ex = as_t<T>(rd.e0[0]);
+            ey = as_t<T>(rd.e0[1]);
+            ez = as_t<T>(rd.e0[2]);
+        }
+        if (FM == F_SITE) {
+            const T *nd = (const T *)rd.nd;
+            nx = nd[i];
+            ny = nd[rd.n + i];
+            nz = nd[2 * rd.n + i];
+        } else {
+            nx = as_t<T>(rd.n0[0]);
+            ny = as_t<T>(rd.n0[1]);
+            nz = as_t<T>(rd.n0[2]);
+        }
+    }
+};
+
+// One site's update in the site-lane / block layouts.  S points at the
+// replica's spins [3][n_pad] (global or LDS).  Returns the accumulators.
+template <typename T, int KM, int FM, bool TRACE>
+__device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint32_t g,
+                                            const RunArgs &ra, int rep, T beta, T b,
+                                            double (&acc)[5])
+{
+    const int np = rd.n_pad;
+    const int32_t rb = rd.rp[i], re = rd.rp[i + 1];
+    const T *J = (const T *)rd.J;
+    const SiteParams<T, KM, FM> sp(rd, i);
+    const T sx = S[i], sy = S[np + i], sz = S[2 * np + i];
+    const uint32_t orig = rd.orig[i];
+    bool acc_move;
+    T nx, ny, nz, dE;
+    if constexpr (sizeof(T) == 4) {
+        float hx = 0.0f, hy = 0.0f, hz = 0.0f;
+        for (int32_t p = rb; p < re; ++p) {
+            const int32_t j = rd.ci[p];
+            const float Jp = J[p];
+            hx = fmaf(Jp, S[j], hx);
+            hy = fmaf(Jp, S[np + j], hy);
+            hz = fmaf(Jp, S[2 * np + j], hz);
+        }
+        hx = fmaf(b, sp.nx, hx);
+        hy = fmaf(b, sp.ny, hy);
+        hz = fmaf(b, sp.nz, hz);
+        const Trial32 t = trial32(draw(ra.seed, orig, g, rd.rep_id, 0));
+        dE = (KM == K_NONE) ? delta_e32_iso(sx, sy, sz, t, hx, hy, hz)
+                            : delta_e32(sx, sy, sz, t, hx, hy, hz, sp.k, sp.ex, sp.ey, sp.ez);
+        acc_move = accept32(dE, beta, t.u);
+        nx = t.x;
+        ny = t.y;
+        nz = t.z;
+    } else {
+        double hx = 0.0, hy = 0.0, hz = 0.0;
+        for (int32_t p = rb; p < re; ++p) {
+            const int32_t j = rd.ci[p];
+            const double Jp = J[p];
+            hx = hx + Jp * S[j];
+            hy = hy + Jp * S[np + j];
+            hz = hz + Jp * S[2 * np + j];
+        }
+        hx = hx + b * sp.nx;
+        hy = hy + b * sp.ny;
+        hz = hz + b * sp.nz;
+        double dd;
+        acc_move = update64(ra.seed, orig, g, rd.rep_id, sx, sy, sz, hx, hy, hz, sp.k, sp.ex,
+                            sp.ey, sp.ez, beta, nx, ny, nz, dd);
+        dE = dd;
+    }
+    if (dE != dE) atomicOr(&ra.ctl->status, 1u);
+    if (acc_move) {
+        S[i] = nx;
+        S[np + i] = ny;
+        S[2 * np + i] = nz;
+        acc[0] += (double)dE;
+        acc[4] += 1.0;
+        if (TRACE)
+            atomicOr(&ra.trace[((size_t)rep * ra.n_mcs_run + (g - ra.g0)) * ra.trace_words +
+                               (orig >> 5)],
+                     1u << (orig & 31));
+        acc[1] += (double)nx;
+        acc[2] += (double)ny;
+        acc[3] += (double)nz;
+    } else {
+        acc[1] += (double)sx;
+        acc[2] += (double)sy;
+        acc[3] += (double)sz;
+    }
+}
+
+// Site energy in double precision, each bond counted half at either end:
+//   e_i = -1/2 S_i.sum_j J_ij S_j - B S_i.n_i - k_i (S_i.e_i)^2
+template <typename T, int KM, int FM>
+__device__ __forceinline__ double site_energy(const RepDesc &rd, const T *S, int i, double b)
+{
+    const int np = rd.n_pad;
+    const T *J = (const T *)rd.J;
+    double hx = 0.0, hy = 0.0, hz = 0.0;
+    for (int32_t p = rd.rp[i]; p < rd.rp[i + 1]; ++p) {
+        const int32_t j = rd.ci[p];
+        const double Jp = (double)J[p];
+        hx += Jp * (double)S[j];
+        hy += Jp * (double)S[np + j];
+        hz += Jp * (double)S[2 * np + j];
+    }
+    const SiteParams<T, KM, FM> sp(rd, i);
+    const double sx = S[i], sy = S[np + i], sz = S[2 * np + i];
+    const double a = sx * (double)sp.ex + sy * (double)sp.ey + sz * (double)sp.ez;
+    const double zn = sx * (double)sp.nx + sy * (double)sp.ny + sz * (double)sp.nz;
+    return -0.5 * (sx * hx + sy * hy + sz * hz) - b * zn - (double)sp.k * a * a;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ control
+__global__ void k_ctl_set(Ctl *ctl, uint32_t g)
+{
+    if (threadIdx.x == 0) {
+        ctl->g = g;
+        ctl->bar_arrive = 0;
+        ctl->pad[0] = 0;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_ctl_set(hipStream_t st, Ctl *ctl, uint32_t g)
+{
+    hipLaunchKernelGGL(k_ctl_set, dim3(1), dim3(64), 0, st, ctl, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, uint32_t v, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ initial state
+template <typename T>
+__global__ void k_init_spins(const RepDesc *reps, int mode, const double *given, uint64_t seed)
+{
+    const RepDesc &rd = reps[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rd.n) return;
+    T *S = (T *)rd.spins;
+    const uint32_t orig = rd.orig[i];
+    double x = 0.0, y = 0.0, z = 1.0;
+    if (mode == 2) {
+        sphere64(seed, orig, 0xFFFFFFFFu, rd.rep_id, x, y, z);
+    } else if (mode == 0) {
+        const double *gv = given + 3 * ((size_t)rd.user_off + orig);
+        x = gv[0];
+        y = gv[1];
+        z = gv[2];
+    }
+    S[i] = (T)x;
+    S[rd.n_pad + i] = (T)y;
+    S[2 * rd.n_pad + i] = (T)z;
+}
+
+hipError_t launch_init_spins(hipStream_t st, bool f64, const RepDesc *reps, int R, int max_n,
+                             int mode, const double *given, const int64_t *, uint64_t seed)
+{
+    dim3 grid((unsigned)((max_n + 255) / 256), (unsigned)R);
+    if (f64)
+        hipLaunchKernelGGL(k_init_spins<double>, grid, dim3(256), 0, st, reps, mode, given, seed);
+    else
+        hipLaunchKernelGGL(k_init_spins<float>, grid, dim3(256), 0, st, reps, mode, given, seed);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_to_user(const RepDesc *reps, int rep, double *out)
+{
+    const RepDesc &rd = reps[rep];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rd.n) return;
+    const T *S = (const T *)rd.spins;
+    const uint32_t o = rd.orig[i];
+    out[3 * (size_t)o] = (double)S[i];
+    out[3 * (size_t)o + 1] = (double)S[rd.n_pad + i];
+    out[3 * (size_t)o + 2] = (double)S[2 * rd.n_pad + i];
+}
+
+hipError_t launch_to_user(hipStream_t st, bool f64, const RepDesc *reps, int rep, int n,
+                          double *out)
+{
+    dim3 grid((unsigned)((n + 255) / 256));
+    if (f64)
+        hipLaunchKernelGGL(k_to_user<double>, grid, dim3(256), 0, st, reps, rep, out);
+    else
+        hipLaunchKernelGGL(k_to_user<float>, grid, dim3(256), 0, st, reps, rep, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- site-lane phases
+template <typename T, int KM, int FM, bool TRACE>
+__global__ __launch_bounds__(kSiteBlock) void k_site_phase(const RepDesc *__restrict__ reps,
+                                                           const Tile *__restrict__ tiles,
+                                                           int tile_off, RunArgs ra)
+{
+    __shared__ double red[(kSiteBlock / 64) * 5];
+    const Tile t = tiles[tile_off + blockIdx.x];
+    const RepDesc &rd = reps[t.rep];
+    const uint32_t g = ra.ctl->g;
+    const uint32_t s_abs = g / (uint32_t)ra.M;
+    const size_t sidx = (size_t)t.rep * ra.S_hist + s_abs;
+    const T beta = (T)ra.beta[sidx];
+    const T b = (T)ra.bfield[sidx];
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int i = t.begin + (int)threadIdx.x;
+    if (i < t.end)
+        site_update<T, KM, FM, TRACE>(rd, (T *)rd.spins, i, g, ra, t.rep, beta, b, acc);
+    block_sum<5>(acc, red);
+    if (threadIdx.x == 0) {
+        double *rec = ra.partials + (size_t)(tile_off + blockIdx.x) * kRecSite;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) rec[q] = acc[q];
+    }
+}
+
+template <typename T, int KM, int FM>
+__global__ __launch_bounds__(kSiteBlock) void k_site_efull(const RepDesc *__restrict__ reps,
+                                                           const Tile *__restrict__ tiles,
+                                                           RunArgs ra)
+{
+    __shared__ double red[(kSiteBlock / 64)];
+    const uint32_t g = ra.ctl->g;
+    if (!recompute_due(g % (uint32_t)ra.M, ra.P)) return;
+    const Tile t = tiles[blockIdx.x];
+    const RepDesc &rd = reps[t.rep];
+    const uint32_t s_abs = g / (uint32_t)ra.M;
+    const double b = ra.bfield[(size_t)t.rep * ra.S_hist + s_abs];
+    double e[1] = {0.0};
+    const int i = t.begin + (int)threadIdx.x;
+    if (i < t.end) e[0] = site_energy<T, KM, FM>(rd, (const T *)rd.spins, i, b);
+    block_sum<1>(e, red);
+    if (threadIdx.x == 0) ra.partials[(size_t)blockIdx.x * kRecSite + 5] = e[0];
+}
+
+// One block: replica r handled by wave (r mod 16); lanes stride its tiles.
+// rep_tiles: [R][ncol_max][2] global tile ranges per colour.
+__global__ __launch_bounds__(1024) void k_site_reduce(const int32_t *__restrict__ rep_tiles,
+                                                      int ncol_max, RunArgs ra)
+{
+    const uint32_t g = ra.ctl->g;
+    const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
+    const bool rec_due = recompute_due(m, ra.P);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int r = w; r < ra.R; r += nw) {
+        double v[6] = {0, 0, 0, 0, 0, 0};
+        for (int c = 0; c < ncol_max; ++c) {
+            const int tb = rep_tiles[(r * ncol_max + c) * 2], te = rep_tiles[(r * ncol_max + c) * 2 + 1];
+            for (int tt = tb + lane; tt < te; tt += 64) {
+                const double *rec = ra.partials + (size_t)tt * kRecSite;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) v[q] += rec[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] = wave_sum(v[q]);
+        if (lane == 0) {
+            const double E = (rec_due ? v[5] : ra.ecarry[r]) + v[0];
+            ra.ecarry[r] = E;
+            double *h = ra.history + (((size_t)r * ra.S_hist + s_abs) * ra.M + m) * 5;
+            h[0] = E;
+            h[1] = v[1];
+            h[2] = v[2];
+            h[3] = v[3];
+            h[4] = v[4];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) ra.ctl->g = g + 1;
+}
+
+#define HSIM_DISPATCH_KF(KM_, FM_, ...)                                                         \
+    do {                                                                                         \
+        if ((KM_) == K_NONE && (FM_) == F_UNIFORM) { constexpr int KM = K_NONE, FM = F_UNIFORM; __VA_ARGS__; } \
+        else if ((KM_) == K_NONE) { constexpr int KM = K_NONE, FM = F_SITE; __VA_ARGS__; }       \
+        else if ((KM_) == K_UNIFORM && (FM_) == F_UNIFORM) { constexpr int KM = K_UNIFORM, FM = F_UNIFORM; __VA_ARGS__; } \
+        else if ((KM_) == K_UNIFORM) { constexpr int KM = K_UNIFORM, FM = F_SITE; __VA_ARGS__; } \
+        else if ((FM_) == F_UNIFORM) { constexpr int KM = K_SITE, FM = F_UNIFORM; __VA_ARGS__; } \
+        else { constexpr int KM = K_SITE, FM = F_SITE; __VA_ARGS__; }                            \
+    } while (0)
+
+hipError_t launch_site_phase(hipStream_t st, bool f64, int kmode, int fmode, bool trace,
+                             const RepDesc *reps, const Tile *tiles, int tile_off, int ntiles,
+                             const RunArgs &ra)
+{
+    if (ntiles <= 0) return hipSuccess;
+    dim3 grid((unsigned)ntiles), blk(kSiteBlock);
+    HSIM_DISPATCH_KF(kmode, fmode, {
+        if (f64) {
+            if (trace) hipLaunchKernelGGL((k_site_phase<double, KM, FM, true>), grid, blk, 0, st, reps, tiles, tile_off, ra);
+            else hipLaunchKernelGGL((k_site_phase<double, KM, FM, false>), grid, blk, 0, st, reps, tiles, tile_off, ra);
+        } else {
+            if (trace) hipLaunchKernelGGL((k_site_phase<float, KM, FM, true>), grid, blk, 0, st, reps, tiles, tile_off, ra);
+            else hipLaunchKernelGGL((k_site_phase<float, KM, FM, false>), grid, blk, 0, st, reps, tiles, tile_off, ra);
+        }
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_site_efull(hipStream_t st, bool f64, int kmode, int fmode, const RepDesc *reps,
+                             const Tile *tiles, int ntiles, const RunArgs &ra)
+{
+    if (ntiles <= 0) return hipSuccess;
+    dim3 grid((unsigned)ntiles), blk(kSiteBlock);
+    HSIM_DISPATCH_KF(kmode, fmode, {
+        if (f64) hipLaunchKernelGGL((k_site_efull<double, KM, FM>), grid, blk, 0, st, reps, tiles, ra);
+        else hipLaunchKernelGGL((k_site_efull<float, KM, FM>), grid, blk, 0, st, reps, tiles, ra);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_site_reduce(hipStream_t st, const int32_t *rep_tiles, int ncol_max,
+                              const RunArgs &ra)
+{
+    hipLaunchKernelGGL(k_site_reduce, dim3(1), dim3(1024), 0, st, rep_tiles, ncol_max, ra);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------- block layout
+// One workgroup owns one replica for the whole run: colour classes are
+// separated by workgroup barriers, spins live in LDS when they fit, and the
+// per-MCS history is written directly.
+template <typename T, int KM, int FM, bool TRACE, bool LDS>
+__global__ __launch_bounds__(1024) void k_block_sweep(const RepDesc *__restrict__ reps, RunArgs ra)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[16 * 5];
+    const int rep = blockIdx.x;
+    const RepDesc &rd = reps[rep];
+    const int np = rd.n_pad, n = rd.n;
+    T *G = (T *)rd.spins;
+    T *S = LDS ? (T *)smem : G;
+    if (LDS) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            S[i] = G[i];
+            S[np + i] = G[np + i];
+            S[2 * np + i] = G[2 * np + i];
+        }
+        __syncthreads();
+    }
+    double E = 0.0;
+    for (int t = 0; t < ra.n_mcs_run; ++t) {
+        const uint32_t g = ra.g0 + (uint32_t)t;
+        const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
+        const size_t sidx = (size_t)rep * ra.S_hist + s_abs;
+        const double bd = ra.bfield[sidx];
+        if (recompute_due(m, ra.P)) {
+            double e[1] = {0.0};
+            for (int i = threadIdx.x; i < n; i += blockDim.x)
+                e[0] += site_energy<T, KM, FM>(rd, S, i, bd);
+            block_sum<1>(e, red);
+            E = e[0];
+        }
+        const T beta = (T)ra.beta[sidx];
+        const T b = (T)bd;
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < rd.ncol; ++c) {
+            const int ce = rd.cls_off[c + 1];
+            for (int i = rd.cls_off[c] + threadIdx.x; i < ce; i += blockDim.x)
+                site_update<T, KM, FM, TRACE>(rd, S, i, g, ra, rep, beta, b, acc);
+            __syncthreads();
+        }
+        block_sum<5>(acc, red);
+        if (threadIdx.x == 0) {
+            E = E + acc[0];
+            double *h = ra.history + (sidx * ra.M + m) * 5;
+            h[0] = E;
+            h[1] = acc[1];
+            h[2] = acc[2];
+            h[3] = acc[3];
+            h[4] = acc[4];
+        }
+    }
+    if (threadIdx.x == 0) ra.ecarry[rep] = E;
+    if (LDS) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            G[i] = S[i];
+            G[np + i] = S[np + i];
+            G[2 * np + i] = S[2 * np + i];
+        }
+    }
+}
+
+int block_sweep_max_lds(bool)
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    return v - 1024;   // static reduction scratch
+}
+
+hipError_t launch_block_sweep(hipStream_t st, bool f64, int kmode, int fmode, bool trace,
+                              bool lds, int threads, size_t lds_bytes, const RepDesc *reps,
+                              const RunArgs &ra)
+{
+    dim3 grid((unsigned)ra.R), blk((unsigned)threads);
+    const size_t sh = lds ? lds_bytes : 0;
+#define HSIM_BLK(T_, TR_, L_)                                                                  \
+    do {                                                                                       \
+        auto kfn = k_block_sweep<T_, KM, FM, TR_, L_>;                                         \
+        if (sh > 65536)                                                                        \
+            (void)hipFuncSetAttribute((const void *)kfn,                                       \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);    \
+        hipLaunchKernelGGL(kfn, grid, blk, sh, st, reps, ra);                                  \
+    } while (0)
+    HSIM_DISPATCH_KF(kmode, fmode, {
+        if (f64) {
+            if (trace) { if (lds) HSIM_BLK(double, true, true); else HSIM_BLK(double, true, false); }
+            else { if (lds) HSIM_BLK(double, false, true); else HSIM_BLK(double, false, false); }
+        } else {
+            if (trace) { if (lds) HSIM_BLK(float, true, true); else HSIM_BLK(float, true, false); }
+            else { if (lds) HSIM_BLK(float, false, true); else HSIM_BLK(float, false, false); }
+        }
+    });
+#undef HSIM_BLK
+    return hipGetLastError();
+}
+
+}  // namespace hsim

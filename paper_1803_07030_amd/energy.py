@@ -1,0 +1,61 @@
+"""Energy of Eq. 1 (paper, section "Classical spin Hamiltonian") as a
+differentiable function of the spins, the per-bond exchange constants, the
+per-site anisotropy constants and the field intensity, with the forward and
+the vector-Jacobian product computed by the library's HIP kernels
+(hsim_energy_forward / hsim_energy_backward), and the fluctuation estimator of
+derivatives of thermal averages (hsim_fluct_estimate)."""
+import torch
+
+from . import hsim
+
+
+class HeisenbergEnergy(torch.autograd.Function):
+    """E_b(S_b; J, k, B) for a batch of configurations S [batch, 3, n] (user
+    order) on one plan; J per bond in the plan's bond order, k [n], axis
+    [3, n], B a 0-d tensor, field_dir [3, n] or None (+z).  float32 inputs use
+    the FP32 kernels with double accumulation, float64 inputs the FP64 ones.
+    Returns E [batch] in float64."""
+
+    @staticmethod
+    def forward(ctx, spins, J_bond, k, B, plan, axis, field_dir):
+        prec = hsim.FP64_EXACT if spins.dtype == torch.float64 else hsim.FP32
+        spins = spins.contiguous()
+        J_bond, k, axis = J_bond.contiguous(), k.contiguous(), axis.contiguous()
+        fd = None if field_dir is None else field_dir.contiguous()
+        batch = spins.shape[0]
+        E = torch.empty(batch, dtype=torch.float64, device=spins.device)
+        hsim.hsim_energy_forward(plan.handle, batch, prec, spins, J_bond, k, axis, float(B), fd, E)
+        ctx.save_for_backward(spins, J_bond, k, axis)
+        ctx.fd, ctx.plan, ctx.prec, ctx.B = fd, plan, prec, float(B)
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        spins, J_bond, k, axis = ctx.saved_tensors
+        gE = gE.contiguous().to(torch.float64)
+        batch = spins.shape[0]
+        need = ctx.needs_input_grad
+        gS = torch.empty_like(spins) if need[0] else None
+        gJ = torch.empty_like(J_bond) if need[1] else None
+        gk = torch.empty_like(k) if need[2] else None
+        gB = torch.empty(1, dtype=torch.float64, device=spins.device) if need[3] else None
+        hsim.hsim_energy_backward(ctx.plan.handle, batch, ctx.prec, spins, J_bond, k, axis, ctx.B,
+                                  ctx.fd, gE, gS, gJ, gk, gB)
+        gBt = None if gB is None else gB.reshape(())
+        return gS, gJ, gk, gBt, None, None, None
+
+
+def heisenberg_energy(spins, J_bond, k, B, plan, axis, field_dir=None):
+    return HeisenbergEnergy.apply(spins, J_bond, k, B, plan, axis, field_dir)
+
+
+def fluct_estimate(beta, O, dE, dO=None):
+    """d<O>/dtheta = <dO/dtheta> - beta Cov(O, dE/dtheta) over the samples
+    (fluctuation-dissipation form of the derivative of a canonical average).
+    Returns (estimate, covariance) as a float64 tensor of 2 elements."""
+    O = O.contiguous().to(torch.float64)
+    dE = dE.contiguous().to(torch.float64)
+    dO = None if dO is None else dO.contiguous().to(torch.float64)
+    out = torch.empty(2, dtype=torch.float64, device=O.device)
+    hsim.hsim_fluct_estimate(O.numel(), beta, O, dE, dO, out)
+    return out

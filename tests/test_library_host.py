@@ -1,0 +1,120 @@
+"""Host-side checks of libhsim.so that need no GPU: the library loads and
+exports every entry point include/hsim.h declares; lattice ingest validates
+its input and its colouring and bond order equal the oracle's (independent
+implementations of the same rule: bit-exact integer parity); batch layout
+choice, sizes and call-order errors."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1803_07030_amd import hsim
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "hsim.h")).read()
+    body = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    declared = set(re.findall(r"\b(hsim_[a-z_]+)\s*\(", body))
+    assert "hsim_batch_run" in declared and len(declared) >= 20
+    L = hsim.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert set(hsim.EXPORTED) == declared
+    assert hsim.hsim_version().startswith("hsim")
+
+
+def _lat_variants():
+    return [synth.sc_periodic(8), synth.sc_periodic(5, 5, 3), synth.core_shell_ball(R=10, Rc=7),
+            synth.diluted_film(19, 4, seed=11), synth.random_tree(300, seed=5),
+            synth.open_chain(17), synth.isolated(10),
+            synth.from_bonds(5, *np.triu_indices(5, 1), np.ones(10))]
+
+
+@pytest.mark.parametrize("idx", range(8))
+def test_colouring_and_bonds_equal_oracle(idx):
+    lat = _lat_variants()[idx]
+    p = hsim.Plan(lat)
+    c_ref, nc = oracle.greedy_colour(lat)
+    assert np.array_equal(p.colouring(), c_ref)
+    assert p.info.n_colours == nc
+    assert list(p.info.colour_size[:nc]) == list(np.bincount(c_ref, minlength=nc))
+    b_ref, _ = oracle.bonds(lat)
+    assert np.array_equal(p.bonds(), b_ref)
+    assert p.info.n_bonds == lat.n_bonds
+
+
+def _expect(code, fn):
+    with pytest.raises(hsim.HsimError) as e:
+        fn()
+    assert e.value.code == code, str(e.value)
+
+
+def _copy(lat, **kw):
+    d = dict(n=lat.n, row_ptr=lat.row_ptr.copy(), col=lat.col.copy(), J=lat.J.copy(), k=lat.k,
+             axis=lat.axis, ndir=lat.ndir)
+    d.update(kw)
+    return synth.Lattice(**d)
+
+
+def test_plan_rejects_invalid_lattices():
+    lat = synth.sc_periodic(4)
+    bad = _copy(lat)
+    bad.J[3] = 1.5
+    _expect(-3, lambda: hsim.Plan(bad))
+    bad = _copy(lat)
+    bad.col[0] = 0
+    _expect(-2, lambda: hsim.Plan(bad))
+    bad = _copy(lat)
+    bad.col[1] = bad.col[0]
+    _expect(-2, lambda: hsim.Plan(bad))
+    bad = _copy(lat)
+    bad.col[0] = lat.n + 5
+    _expect(-2, lambda: hsim.Plan(bad))
+    bad = _copy(lat)
+    bad.row_ptr[0] = 1
+    _expect(-2, lambda: hsim.Plan(bad))
+    _expect(-3, lambda: hsim.Plan(_copy(lat, k=np.full(lat.n, np.inf))))
+    _expect(-3, lambda: hsim.Plan(_copy(lat, axis=np.tile([0.0, 0.6, 0.6], (lat.n, 1)))))
+    _expect(-3, lambda: hsim.Plan(_copy(lat, ndir=np.tile([0.0, 0.0, 2.0], (lat.n, 1)))))
+    # a one-way link (missing reverse entry)
+    one_way = synth.Lattice(3, np.array([0, 1, 1, 1]), np.array([1], dtype=np.int32),
+                            np.array([1.0]))
+    _expect(-2, lambda: hsim.Plan(one_way))
+    _expect(-1, lambda: hsim.hsim_plan_create(-1, lat.row_ptr, lat.col, lat.J))
+
+
+def test_plan_flags_uniform_parameters():
+    lat = synth.sc_periodic(4)
+    assert hsim.Plan(lat).info.uniform_anisotropy == 1
+    lat.k = synth.uniform01(1, lat.n)
+    assert hsim.Plan(lat).info.uniform_anisotropy == 0
+    lat.ndir = synth.unit_vectors(2, lat.n)
+    assert hsim.Plan(lat).info.uniform_field_dir == 0
+
+
+def test_batch_layouts_sizes_and_errors():
+    sc = hsim.Plan(synth.sc_periodic(8))
+    big = hsim.Plan(synth.sc_periodic(64))
+    b = hsim.Batch([sc], seed=0, precision=hsim.FP64_EXACT)
+    assert b.layout == "block" and b.info.lds_resident == 1
+    ws, sp, hi = hsim.hsim_batch_sizes(b.handle, 20, 1000)
+    assert sp == 3 * 512 * 8 and hi == 20 * 1000 * 5 * 8
+    b = hsim.Batch([big] * 64, seed=1, precision=hsim.FP32)
+    assert b.layout == "replica"
+    ws, sp, hi = hsim.hsim_batch_sizes(b.handle, 1, 10000)
+    assert sp == 3 * 64 ** 3 * 64 * 4 and hi == 64 * 10000 * 5 * 8
+    b = hsim.Batch([big], seed=1, precision=hsim.FP32)
+    assert b.layout == "site"
+    _expect(-6, lambda: hsim.Batch([big] * 4, seed=0, precision=hsim.FP64_EXACT,
+                                   layout=hsim.LAYOUT_REPLICA))
+    _expect(-6, lambda: hsim.Batch([big, sc], seed=0, layout=hsim.LAYOUT_REPLICA))
+    _expect(-1, lambda: hsim.hsim_batch_sizes(b.handle, 0, 10))
+    _expect(-4, lambda: hsim.hsim_batch_run(b.handle, 0, np.ones((1, 1)), np.zeros((1, 1))))
+    _expect(-4, lambda: hsim.hsim_batch_init_spins(b.handle, hsim.INIT_COLD_Z))
+    _expect(-1, lambda: hsim.hsim_batch_create([], 0))
