@@ -39,7 +39,22 @@ def parse():
     ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS per thread of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (HBM byte-counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of a known size: the reference for
+    scaling the HBM byte counters (FETCH_SIZE / WRITE_SIZE) of the sweep."""
+    import torch
+    n = 1 << 28                                    # 2^28 floats = 1 GiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
 
 
 def workload():
@@ -68,6 +83,9 @@ def main():
     from paper_1803_07030_amd import hsim
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     stream = torch.cuda.Stream()
     lat, T = workload()
     launch = dict(persistent=hsim.LAUNCH_PERSISTENT, graph=hsim.LAUNCH_GRAPH,

@@ -23,33 +23,34 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
           "-I", os.path.join(ROOT, "include")]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _compile(src, build_dir=BUILD, defines=()):
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = ["hipcc"] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc"] + COMMON + list(defines) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
     return obj, r.stderr
 
 
-def build(verbose=False):
-    """Compile every source and link libhsim.so; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose=False, out=OUT, build_dir=BUILD, defines=()):
+    """Compile every source and link libhsim.so; returns its path.  defines:
+    extra -D flags (e.g. tile shape), out/build_dir: where to put the result."""
+    os.makedirs(build_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(lambda src: _compile(src, build_dir, defines), SOURCES))
     if verbose:
         for _, err in results:
             if err.strip():
                 sys.stderr.write(err)
     objs = [o for o, _ in results]
-    tmp = OUT + ".tmp"
+    tmp = out + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

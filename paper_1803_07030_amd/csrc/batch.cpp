@@ -79,13 +79,20 @@ hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
                 max_cls = std::max<int64_t>(max_cls, P->cls_off[c + 1] - P->cls_off[c]);
         }
         if (b->total_sites > (int64_t)INT32_MAX) throw Error(HSIM_E_UNSUPPORTED, "batch too large");
+        b->ellw = plans[0]->ell_w;
+        for (int r = 1; r < R; ++r)
+            if (plans[r]->ell_w != b->ellw) b->ellw = 0;
         const int64_t lds_limit = device_lds_limit();
         const bool fits_lds = 3 * pad64(max_n) * (int64_t)elem <= lds_limit;
         int lay = layout;
-        if (lay == HSIM_LAYOUT_REPLICA && (b->f64 || !shared))
-            throw Error(HSIM_E_UNSUPPORTED, "replica layout needs FP32 and one shared lattice");
+        // replica layout: one spin plane (n x Rp floats) must stay below 2 GiB
+        const int64_t rp_pad = R > 32 ? (R + 63) / 64 * 64 : 32;
+        const bool plane_ok = max_n * rp_pad * 4 < ((int64_t)1 << 31);
+        if (lay == HSIM_LAYOUT_REPLICA && (b->f64 || !shared || !plane_ok))
+            throw Error(HSIM_E_UNSUPPORTED,
+                        "replica layout needs FP32, one shared lattice and a spin plane below 2 GiB");
         if (lay == HSIM_LAYOUT_AUTO) {
-            if (!b->f64 && shared && R >= 16) lay = HSIM_LAYOUT_REPLICA;
+            if (!b->f64 && shared && R >= 16 && plane_ok) lay = HSIM_LAYOUT_REPLICA;
             else if (fits_lds) lay = HSIM_LAYOUT_BLOCK;
             else lay = HSIM_LAYOUT_SITE;
         }
@@ -149,7 +156,8 @@ void batch_sizes_impl(hsim_batch b, int32_t S, int32_t M, size_t *ws, size_t *sp
     size_t part = 0;
     if (b->layout == HSIM_LAYOUT_SITE) part = b->tiles.size() * hsim::kRecSite * 8;
     else if (b->layout == HSIM_LAYOUT_REPLICA)
-        part = ((size_t)2 * b->rep_ntiles * hsim::kRecFields * b->Rp + (size_t)2 * 64 * 6 * b->Rp) * 8;
+        part = ((size_t)2 * b->rep_ntiles * hsim::kRecFields * b->Rp + (size_t)2 * 64 * 6 * b->Rp) * 8 +
+               (size_t)hsim::kMaxPersistentBlocks * 128;   // barrier flags, one 128-byte line each
     off += align_up(std::max<size_t>(part, 8));
     if (ws) *ws = off;
     const size_t elem = b->f64 ? 8 : 4;
@@ -173,6 +181,8 @@ void hsim_batch_s::upload_tables()
         la.rp = (const int32_t *)P->d_rp.p;
         la.ci = (const int32_t *)P->d_ci.p;
         la.J = (const float *)P->d_Jf.p;
+        la.ell_col = (const int32_t *)P->d_ell_col.p;
+        la.ell_J = (const float *)P->d_ell_J.p;
         la.orig = (const uint32_t *)P->d_orig.p;
         la.k = (const float *)P->d_kf.p;
         la.ax = (const float *)P->d_axf.p;
@@ -190,6 +200,7 @@ void hsim_batch_s::upload_tables()
         la.Rp = Rp;
         la.R = R;
         la.ncol = P->ncol;
+        la.ell_w = P->ell_w;
         for (int c = 0; c <= P->ncol; ++c) la.cls_off[c] = P->cls_off[c];
     } else {
         reps.assign(R, hsim::RepDesc{});
@@ -205,6 +216,9 @@ void hsim_batch_s::upload_tables()
             d.ax = f64 ? P->d_axd.p : P->d_axf.p;
             d.nd = f64 ? P->d_ndd.p : P->d_ndf.p;
             d.spins = (char *)spins + spin_off[r] * elem;
+            d.ell_w = P->ell_w;
+            d.ellT_col = (const int32_t *)P->d_ellT_col.p;
+            d.ellT_J = f64 ? P->d_ellT_Jd.p : P->d_ellT_Jf.p;
             d.k0 = P->k0;
             for (int c = 0; c < 3; ++c) {
                 d.e0[c] = P->e0[c];
@@ -330,19 +344,36 @@ void enqueue_mcs(hsim_batch b, const hsim::RunArgs &ra, bool efull, hipStream_t 
                       "efull launch");
         for (int c = 0; c < b->ncol_max; ++c)
             hip_check(hsim::launch_site_phase(st, b->f64, b->kmode, b->fmode, ra.trace != nullptr,
-                                              reps, tiles, b->tile_off[c],
+                                              b->ellw, reps, tiles, b->tile_off[c],
                                               b->tile_off[c + 1] - b->tile_off[c], ra),
                       "phase launch");
         hip_check(hsim::launch_site_reduce(st, (const int32_t *)b->d_rep_tiles.p, b->ncol_max, ra),
                   "reduce launch");
     } else {
-        if (efull)
-            hip_check(hsim::launch_rep_efull(st, b->kmode, b->fmode, b->la, b->rep_ntiles, ra),
+        throw Error(HSIM_E_STATE, "enqueue_mcs: replica layout uses enqueue_rep_sequence");
+    }
+}
+
+// Replica layout: MCS t_off = 0..count-1 of a launch sequence starting at
+// ctl->g.  The history of each MCS is reduced inside the next MCS's colour-0
+// launch; the last one by a closing reduction that also moves ctl->g on.
+// efull_mask(t): whether MCS t may need the energy recompute.
+template <typename F>
+void enqueue_rep_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F efull_mask,
+                          hipStream_t st)
+{
+    for (int t = 0; t < count; ++t) {
+        if (efull_mask(t))
+            hip_check(hsim::launch_rep_efull(st, b->kmode, b->fmode, b->la, b->rep_ntiles, t, ra),
                       "efull launch");
         for (int c = 0; c < b->la.ncol; ++c)
-            hip_check(hsim::launch_rep_phase(st, b->kmode, b->fmode, c, b->la, ra), "phase launch");
-        hip_check(hsim::launch_rep_reduce(st, b->la, b->rep_ntiles, ra), "reduce launch");
+            hip_check(hsim::launch_rep_phase(st, b->kmode, b->fmode, c, t, c == 0 && t > 0, b->la,
+                                             b->rep_ntiles, ra),
+                      "phase launch");
     }
+    if (count > 0)
+        hip_check(hsim::launch_rep_reduce(st, b->la, b->rep_ntiles, count - 1, count, ra),
+                  "reduce launch");
 }
 
 bool due(uint32_t g, int M, int P)
@@ -353,6 +384,13 @@ bool due(uint32_t g, int M, int P)
 
 void run_plain(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st, int from, int to)
 {
+    if (b->layout == HSIM_LAYOUT_REPLICA) {
+        // ctl->g is at g0 + from here
+        const uint32_t gb = ra.g0 + (uint32_t)from;
+        enqueue_rep_sequence(b, ra, to - from,
+                             [&](int t) { return due(gb + (uint32_t)t, ra.M, ra.P); }, st);
+        return;
+    }
     for (int t = from; t < to; ++t) enqueue_mcs(b, ra, due(ra.g0 + t, ra.M, ra.P), st);
 }
 
@@ -390,7 +428,10 @@ void run_graph(hsim_batch b, const hsim::RunArgs &ra, hipStream_t user_st)
     hipGraphExec_t exec = nullptr;
     hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
-        for (int t = 0; t < U; ++t) enqueue_mcs(b, ra, efull_each || t == 0, st);
+        if (b->layout == HSIM_LAYOUT_REPLICA)
+            enqueue_rep_sequence(b, ra, U, [&](int t) { return efull_each || t == 0; }, st);
+        else
+            for (int t = 0; t < U; ++t) enqueue_mcs(b, ra, efull_each || t == 0, st);
     } catch (...) {
         (void)hipStreamEndCapture(st, &graph);
         if (graph) (void)hipGraphDestroy(graph);
@@ -417,15 +458,19 @@ void run_graph(hsim_batch b, const hsim::RunArgs &ra, hipStream_t user_st)
 
 bool run_persistent(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st)
 {
-    const int bpc = hsim::rep_persistent_blocks_per_cu(b->kmode, b->fmode, b->Rp % 64 == 0 ? 64 : 32);
+    const int bpc = hsim::rep_persistent_blocks_per_cu(b->kmode, b->fmode, b->Rp % 64 == 0 ? 64 : 32, b->la.ell_w);
     const int cus = device_cus();
     if (bpc <= 0 || cus <= 0) return false;
     const int groups = b->Rp / (b->Rp % 64 == 0 ? 64 : 32);
     int grid = b->persistent_grid > 0 ? b->persistent_grid : bpc * cus;
     grid = std::min(grid, bpc * cus);   // every block must be resident at once
     grid = std::min(grid, std::max(1, b->rep_ntiles * groups));
+    grid = std::min(grid, hsim::kMaxPersistentBlocks);
+    // barrier flags follow the tile records and chunk sums
+    const size_t rec = ((size_t)2 * b->rep_ntiles * hsim::kRecFields * b->Rp + (size_t)2 * 64 * 6 * b->Rp) * 8;
+    auto *flags = (uint32_t *)(b->ws + b->off_part + rec);
     hip_check(hsim::launch_rep_persistent(st, b->kmode, b->fmode, b->la, b->rep_ntiles, grid, ra,
-                                          1u << 25),
+                                          flags, 1u << 24),
               "persistent launch");
     return true;
 }
@@ -474,7 +519,7 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
     hip_check(hsim::launch_ctl_set(st, ra.ctl, g0), "control launch");
 
     if (b->layout == HSIM_LAYOUT_BLOCK) {
-        hip_check(hsim::launch_block_sweep(st, b->f64, b->kmode, b->fmode, want_trace, b->lds,
+        hip_check(hsim::launch_block_sweep(st, b->f64, b->kmode, b->fmode, want_trace, b->ellw, b->lds,
                                            b->block_threads, b->lds_bytes,
                                            (const hsim::RepDesc *)b->d_reps.p, ra),
                   "block sweep launch");
@@ -593,7 +638,7 @@ void autotune_impl(hsim_batch b, const char *cache_path, int32_t trial_mcs, hipS
     struct Cand { int mode, grid; };
     std::vector<Cand> cands = {{HSIM_LAUNCH_PLAIN, 0}, {HSIM_LAUNCH_GRAPH, 0}};
     if (b->layout == HSIM_LAYOUT_REPLICA) {
-        const int bpc = hsim::rep_persistent_blocks_per_cu(b->kmode, b->fmode, b->Rp % 64 == 0 ? 64 : 32);
+        const int bpc = hsim::rep_persistent_blocks_per_cu(b->kmode, b->fmode, b->Rp % 64 == 0 ? 64 : 32, b->la.ell_w);
         const int cus = device_cus();
         for (int f : {1, 2, 4, 8})
             if (bpc >= f && cus > 0) cands.push_back({HSIM_LAUNCH_PERSISTENT, f * cus});

@@ -9,8 +9,16 @@ namespace hsim {
 
 constexpr int kMaxColours = 32;     // colour classes per lattice
 constexpr int kSiteBlock = 256;     // threads per block of the site-lane kernels
-constexpr int kRepWaves = 4;        // waves per block of the replica-lane kernels
-constexpr int kRepSitesPerWave = 32;
+#ifndef HSIM_REP_WAVES
+#define HSIM_REP_WAVES 4
+#endif
+#ifndef HSIM_REP_SITES_PER_WAVE
+#define HSIM_REP_SITES_PER_WAVE 32
+#endif
+constexpr int kRepWaves = HSIM_REP_WAVES;                    // waves per replica-lane block
+constexpr int kRepSitesPerWave = HSIM_REP_SITES_PER_WAVE;    // sites per wave of a tile
+constexpr int kRepThreads = kRepWaves * 64;
+constexpr int kMaxPersistentBlocks = 4096;   // barrier flags reserved in the workspace
 constexpr int kRepTile = kRepWaves * kRepSitesPerWave;   // sites per replica-lane tile
 constexpr int kRecSite = 8;         // doubles per site-lane partial record
 constexpr int kRecFields = 6;       // dE, Mx, My, Mz, n_acc, E_full
@@ -29,11 +37,13 @@ struct RepDesc {
     const void *ax;           // [3][n] (K_SITE), stride n
     const void *nd;           // [3][n] (F_SITE), stride n
     void *spins;              // [3][n_pad] of this replica (site and block layouts)
+    const int32_t *ellT_col;  // [ell_w][n] padded rows, slot-major (NULL: use the CSR)
+    const void *ellT_J;       // [ell_w][n] (float or double)
     double k0, e0[3], n0[3];  // uniform values (K_UNIFORM / F_UNIFORM)
     int64_t user_off;         // offset of this replica in replica-concatenated user arrays
     int32_t n, n_pad;
     uint32_t rep_id;
-    int32_t ncol;
+    int32_t ncol, ell_w;
     int32_t cls_off[kMaxColours + 1];
 };
 
@@ -44,7 +54,7 @@ struct Tile {
 
 // Run-control word block at the start of the workspace.
 struct Ctl {
-    uint32_t g;          // absolute MCS counter of the MCS in progress
+    uint32_t g;          // site layout: MCS in progress; replica layout: first MCS of the launch sequence
     uint32_t status;     // HSIM_E_* bits seen on the device
     uint32_t bar_arrive; // persistent-launch barrier
     uint32_t pad[61];
@@ -72,13 +82,15 @@ struct RunArgs {
 struct RepLaneArgs {
     const int32_t *rp, *ci;
     const float *J;
+    const int32_t *ell_col;     // [n][maxd] padded rows, site-major
+    const float *ell_J;
     const uint32_t *orig;
     const float *k, *ax, *nd;   // per-site (K_SITE / F_SITE)
     float *spins;               // [3][n][Rp]
     const uint32_t *rep_id;     // [Rp]
     float k0, e0x, e0y, e0z, n0x, n0y, n0z;
     int32_t n, Rp, R;
-    int32_t ncol;
+    int32_t ncol, ell_w;        // ell_w: padded row width (6 or 8), 0 = CSR walk
     int32_t cls_off[kMaxColours + 1];
     int32_t tile_off[kMaxColours + 1];   // first tile of each colour
 };
@@ -97,7 +109,7 @@ hipError_t launch_to_user(hipStream_t st, bool f64, const RepDesc *reps, int rep
                           double *out);
 hipError_t launch_to_user_rep(hipStream_t st, const RepLaneArgs &a, int rep, double *out);
 
-hipError_t launch_site_phase(hipStream_t st, bool f64, int kmode, int fmode, bool trace,
+hipError_t launch_site_phase(hipStream_t st, bool f64, int kmode, int fmode, bool trace, int ellw,
                              const RepDesc *reps, const Tile *tiles, int tile_off, int ntiles,
                              const RunArgs &ra);
 hipError_t launch_site_efull(hipStream_t st, bool f64, int kmode, int fmode, const RepDesc *reps,
@@ -105,19 +117,20 @@ hipError_t launch_site_efull(hipStream_t st, bool f64, int kmode, int fmode, con
 hipError_t launch_site_reduce(hipStream_t st, const int32_t *rep_tiles, int ncol_max,
                               const RunArgs &ra);
 hipError_t launch_block_sweep(hipStream_t st, bool f64, int kmode, int fmode, bool trace,
-                              bool lds, int threads, size_t lds_bytes, const RepDesc *reps,
+                              int ellw, bool lds, int threads, size_t lds_bytes, const RepDesc *reps,
                               const RunArgs &ra);
 int block_sweep_max_lds(bool f64);
 
-hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour,
-                            const RepLaneArgs &a, const RunArgs &ra);
+hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour, int t_off,
+                            bool reduce_prev, const RepLaneArgs &a, int ntiles, const RunArgs &ra);
 hipError_t launch_rep_efull(hipStream_t st, int kmode, int fmode, const RepLaneArgs &a,
-                            int ntiles, const RunArgs &ra);
-hipError_t launch_rep_reduce(hipStream_t st, const RepLaneArgs &a, int ntiles,
-                             const RunArgs &ra);
+                            int ntiles, int t_off, const RunArgs &ra);
+hipError_t launch_rep_reduce(hipStream_t st, const RepLaneArgs &a, int ntiles, int t_off,
+                             int advance, const RunArgs &ra);
 hipError_t launch_rep_persistent(hipStream_t st, int kmode, int fmode, const RepLaneArgs &a,
-                                 int ntiles, int grid, const RunArgs &ra, uint32_t spin_cap);
-int rep_persistent_blocks_per_cu(int kmode, int fmode, int lane_w);
+                                 int ntiles, int grid, const RunArgs &ra, uint32_t *flags,
+                                 uint32_t spin_cap);
+int rep_persistent_blocks_per_cu(int kmode, int fmode, int lane_w, int ell_w);
 
 // energy
 struct EnergyArgs {

@@ -76,6 +76,13 @@ struct hsim_plan_s {
     std::vector<float> kf, axf, ndf;
     int kmode = 0, fmode = 0;
     double k0 = 0.0, e0[3] = {0, 0, 1}, n0[3] = {0, 0, 1};
+    // padded rows (ELL) of the internal CSR when every row has <= 8 entries:
+    // slot s of site i holds (col, J), or (i, 0) past the row's end;
+    // site-major [n][ell_w] and slot-major [ell_w][n] copies
+    int ell_w = 0;
+    std::vector<int32_t> ell_col, ellT_col;
+    std::vector<float> ell_Jf, ellT_Jf;
+    std::vector<double> ellT_Jd;
     // user-order CSR for the energy and its gradient
     std::vector<int64_t> urp;
     std::vector<int32_t> uci, ubond, fwd_entry, bond_ij;
@@ -83,6 +90,7 @@ struct hsim_plan_s {
     // device copies (uploaded on first use)
     bool sweep_on_device = false, energy_on_device = false;
     hsim::DevBuf d_rp, d_ci, d_Jf, d_Jd, d_orig, d_kf, d_kd, d_axf, d_axd, d_ndf, d_ndd;
+    hsim::DevBuf d_ell_col, d_ell_J, d_ellT_col, d_ellT_Jf, d_ellT_Jd;
     hsim::DevBuf d_urp, d_uci, d_ubond, d_fwd, d_scratch;
 
     void upload_sweep();
@@ -98,6 +106,7 @@ struct hsim_batch_s {
     int layout = HSIM_LAYOUT_SITE;
     int kmode = 0, fmode = 0;
     int ncol_max = 0;
+    int ellw = 0;                     // common padded row width of the plans (0: CSR walk)
     int64_t total_sites = 0;
     bool lds = false;
     int block_threads = 256;

@@ -139,6 +139,28 @@ hsim_plan plan_create_impl(int64_t n, const int64_t *rp, const int32_t *col, con
             P->rp[t + 1] = q;
         }
         P->Jf.assign(P->Jd.begin(), P->Jd.end());
+        // padded rows for the fixed-width kernels
+        if (P->maxdeg <= 8) {
+            const int W = P->maxdeg <= 6 ? 6 : 8;
+            P->ell_w = W;
+            P->ell_col.assign((size_t)n * W, 0);
+            P->ell_Jf.assign((size_t)n * W, 0.0f);
+            P->ellT_col.assign((size_t)n * W, 0);
+            P->ellT_Jf.assign((size_t)n * W, 0.0f);
+            P->ellT_Jd.assign((size_t)n * W, 0.0);
+            for (int64_t t = 0; t < n; ++t)
+                for (int sl = 0; sl < W; ++sl) {
+                    const int32_t p = P->rp[t] + sl;
+                    const bool in = p < P->rp[t + 1];
+                    const int32_t c = in ? P->ci[p] : (int32_t)t;
+                    const double J = in ? P->Jd[p] : 0.0;
+                    P->ell_col[t * W + sl] = c;
+                    P->ell_Jf[t * W + sl] = (float)J;
+                    P->ellT_col[(size_t)sl * n + t] = c;
+                    P->ellT_Jf[(size_t)sl * n + t] = (float)J;
+                    P->ellT_Jd[(size_t)sl * n + t] = J;
+                }
+        }
         // per-site parameters, internal order
         P->kd.resize(n);
         P->axd.resize(3 * n);
@@ -218,6 +240,13 @@ void hsim_plan_s::upload_sweep()
     d_axd.upload(axd);
     d_ndf.upload(ndf);
     d_ndd.upload(ndd);
+    if (ell_w > 0) {
+        d_ell_col.upload(ell_col);
+        d_ell_J.upload(ell_Jf);
+        d_ellT_col.upload(ellT_col);
+        d_ellT_Jf.upload(ellT_Jf);
+        d_ellT_Jd.upload(ellT_Jd);
+    }
     sweep_on_device = true;
 }
 

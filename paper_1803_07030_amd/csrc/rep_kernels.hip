@@ -10,7 +10,7 @@
 // with its own temperature and field schedule.
 //
 // A tile is kRepTile consecutive sites of one colour class; wave w of the
-// tile's block takes 32 of them, in order.  Per-MCS history: every tile writes
+// tile's block takes kRepSitesPerWave of them, two at a time, in order.  Per-MCS history: every tile writes
 // one record per replica; records are summed in 64 fixed chunks of tiles, and
 // the chunks in order, the same way in every launch mode.
 #include "hsim_dev.h"
@@ -21,22 +21,44 @@ namespace hsim {
 namespace {
 
 constexpr int kChunks = 64;
+// LDS of a replica-lane block: the tile sums ([kRepWaves][64][5]) and, reused,
+// the history reductions (chunk quarters [4][6][32], final eighths [8][6][32]).
+constexpr int kRedDoubles = kRepWaves * 64 * 5 > 8 * 6 * 32 ? kRepWaves * 64 * 5 : 8 * 6 * 32;
 
 __device__ __forceinline__ bool rep_recompute_due(uint32_t m, int P)
 {
     return m == 0 || (P > 0 && (m % (uint32_t)P) == 0);
 }
 
-template <int KM, int FM>
+// History accumulators of one lane without branches: energy change and count
+// of accepted moves, and the final spin of every live site.
+__device__ __forceinline__ void accumulate(double (&acc)[5], bool ok, bool live, float dE, float x,
+                                           float y, float z)
+{
+    acc[0] += ok ? (double)dE : 0.0;
+    acc[4] += ok ? 1.0 : 0.0;
+    acc[1] += live ? (double)x : 0.0;
+    acc[2] += live ? (double)y : 0.0;
+    acc[3] += live ? (double)z : 0.0;
+}
+
+// Per-site parameters; UNI: the site index is wave-uniform (scalar loads).
+template <int KM, int FM, bool UNI = false>
 struct RepSite {
     float k, ex, ey, ez, nx, ny, nz;
+    template <typename T>
+    __device__ __forceinline__ static T ld(const T *p, int64_t i)
+    {
+        if constexpr (UNI) return ((const __attribute__((address_space(4))) T *)p)[i];
+        else return p[i];
+    }
     __device__ __forceinline__ RepSite(const RepLaneArgs &a, int i)
     {
         if (KM == K_SITE) {
-            k = a.k[i];
-            ex = a.ax[i];
-            ey = a.ax[a.n + i];
-            ez = a.ax[2 * a.n + i];
+            k = ld(a.k, i);
+            ex = ld(a.ax, i);
+            ey = ld(a.ax, (int64_t)a.n + i);
+            ez = ld(a.ax, 2 * (int64_t)a.n + i);
         } else {
             k = (KM == K_UNIFORM) ? a.k0 : 0.0f;
             ex = a.e0x;
@@ -44,9 +66,9 @@ struct RepSite {
             ez = a.e0z;
         }
         if (FM == F_SITE) {
-            nx = a.nd[i];
-            ny = a.nd[a.n + i];
-            nz = a.nd[2 * a.n + i];
+            nx = ld(a.nd, i);
+            ny = ld(a.nd, (int64_t)a.n + i);
+            nz = ld(a.nd, 2 * (int64_t)a.n + i);
         } else {
             nx = a.n0x;
             ny = a.n0y;
@@ -55,7 +77,8 @@ struct RepSite {
     }
 };
 
-// Update site i for replica lane r (spin column r of the [3][n][Rp] array).
+// Update site i for replica lane r (spin column r of the [3][n][Rp] array),
+// generic CSR row walk (rows of any degree).
 template <int KM, int FM>
 __device__ __forceinline__ void rep_site_update(const RepLaneArgs &a, int i, int r, uint32_t g,
                                                 float beta, float b, uint32_t rid, bool active,
@@ -87,15 +110,154 @@ __device__ __forceinline__ void rep_site_update(const RepLaneArgs &a, int i, int
         S[oi] = t.x;
         S[plane + oi] = t.y;
         S[2 * plane + oi] = t.z;
-        acc[0] += (double)dE;
-        acc[4] += 1.0;
-        acc[1] += (double)t.x;
-        acc[2] += (double)t.y;
-        acc[3] += (double)t.z;
-    } else if (active) {
-        acc[1] += (double)sx;
-        acc[2] += (double)sy;
-        acc[3] += (double)sz;
+    }
+    accumulate(acc, ok, active, dE, ok ? t.x : sx, ok ? t.y : sy, ok ? t.z : sz);
+}
+
+// Read-only lattice tables seen through the constant address space: with a
+// wave-uniform index the compiler loads them with scalar loads.
+template <typename T>
+__device__ __forceinline__ T cload(const T *p, int64_t i)
+{
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
+// Fixed-width rows: the plan pads every row to MAXD slots (ell_col, ell_J,
+// site-major); a slot past the row's end holds the site itself with constant
+// 0, which leaves the fused multiply-add chain of the field unchanged
+// (h + 0*S == h), so the padded walk gives the same bits as the CSR walk.
+// Buffer resources over the three spin planes (raw buffers; the host keeps a
+// plane below 2 GiB so that byte offsets fit the 32-bit offset fields).
+struct SpinPlanes {
+    __amdgpu_buffer_rsrc_t x, y, z;
+    __device__ __forceinline__ SpinPlanes(const RepLaneArgs &a)
+    {
+        const size_t plane = (size_t)a.n * a.Rp;
+        const int bytes = (int)(plane * 4);
+        x = __builtin_amdgcn_make_buffer_rsrc(a.spins, 0, bytes, 0x00020000);
+        y = __builtin_amdgcn_make_buffer_rsrc(a.spins + plane, 0, bytes, 0x00020000);
+        z = __builtin_amdgcn_make_buffer_rsrc(a.spins + 2 * plane, 0, bytes, 0x00020000);
+    }
+};
+
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t rs, int32_t lane_b, int32_t row_b)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lane_b, row_b, 0));
+}
+
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t rs, int32_t lane_b, int32_t row_b,
+                                       float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, lane_b, row_b, 0);
+}
+
+template <int KM, int FM, int MAXD>
+__device__ __forceinline__ void rep_pair_uniform(const RepLaneArgs &a, const SpinPlanes &sp3,
+                                                 int i0, int ce, int r, uint32_t g, float beta,
+                                                 float b, uint32_t rid, bool active,
+                                                 const RunArgs &ra, double (&acc)[5])
+{
+    const int32_t lane_b = r * 4;        // byte offset of this replica inside a row
+    float hx[2], hy[2], hz[2], sx[2], sy[2], sz[2];
+    int ic[2];
+    bool valid[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        valid[u] = i0 + u < ce;
+        ic[u] = valid[u] ? i0 + u : ce - 1;
+        hx[u] = 0.0f;
+        hy[u] = 0.0f;
+        hz[u] = 0.0f;
+#pragma unroll
+        for (int sl = 0; sl < MAXD; ++sl) {
+            const int32_t ob = cload(a.ell_col, ic[u] * MAXD + sl) * a.Rp * 4;   // row byte offset
+            const float Jp = cload(a.ell_J, ic[u] * MAXD + sl);
+            hx[u] = fmaf(Jp, bload(sp3.x, lane_b, ob), hx[u]);
+            hy[u] = fmaf(Jp, bload(sp3.y, lane_b, ob), hy[u]);
+            hz[u] = fmaf(Jp, bload(sp3.z, lane_b, ob), hz[u]);
+        }
+        const int32_t oi = ic[u] * a.Rp * 4;
+        sx[u] = bload(sp3.x, lane_b, oi);
+        sy[u] = bload(sp3.y, lane_b, oi);
+        sz[u] = bload(sp3.z, lane_b, oi);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = ic[u];
+        const RepSite<KM, FM, true> sp(a, i);
+        const float fx = fmaf(b, sp.nx, hx[u]);
+        const float fy = fmaf(b, sp.ny, hy[u]);
+        const float fz = fmaf(b, sp.nz, hz[u]);
+        const Trial32 t = trial32(draw(ra.seed, cload(a.orig, i), g, rid, 0));
+        const float dE = (KM == K_NONE) ? delta_e32_iso(sx[u], sy[u], sz[u], t, fx, fy, fz)
+                                        : delta_e32(sx[u], sy[u], sz[u], t, fx, fy, fz, sp.k, sp.ex,
+                                                    sp.ey, sp.ez);
+        const bool live = active && valid[u];
+        const bool ok = accept32(dE, beta, t.u) && live;
+        if (live && dE != dE) atomicOr(&ra.ctl->status, 1u);
+        const int32_t oi = i * a.Rp * 4;
+        if (ok) {
+            bstore(sp3.x, lane_b, oi, t.x);
+            bstore(sp3.y, lane_b, oi, t.y);
+            bstore(sp3.z, lane_b, oi, t.z);
+        }
+        accumulate(acc, ok, live, dE, ok ? t.x : sx[u], ok ? t.y : sy[u], ok ? t.z : sz[u]);
+    }
+}
+
+// Two sites of one lane group at once: all loads of both sites are issued
+// before either stores (sites of one colour class are never neighbours).
+template <int KM, int FM, int MAXD>
+__device__ __forceinline__ void rep_pair_update(const RepLaneArgs &a, int i0, int ce, int r,
+                                                uint32_t g, float beta, float b, uint32_t rid,
+                                                bool active, const RunArgs &ra, double (&acc)[5])
+{
+    const size_t plane = (size_t)a.n * a.Rp;
+    float *S = a.spins + r;
+    float hx[2], hy[2], hz[2], sx[2], sy[2], sz[2];
+    int ic[2];
+    bool valid[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        valid[u] = i0 + u < ce;
+        ic[u] = valid[u] ? i0 + u : ce - 1;
+        hx[u] = 0.0f;
+        hy[u] = 0.0f;
+        hz[u] = 0.0f;
+#pragma unroll
+        for (int sl = 0; sl < MAXD; ++sl) {
+            const size_t o = (size_t)a.ell_col[ic[u] * MAXD + sl] * a.Rp;
+            const float Jp = valid[u] ? a.ell_J[ic[u] * MAXD + sl] : 0.0f;
+            hx[u] = fmaf(Jp, S[o], hx[u]);
+            hy[u] = fmaf(Jp, S[plane + o], hy[u]);
+            hz[u] = fmaf(Jp, S[2 * plane + o], hz[u]);
+        }
+        const size_t oi = (size_t)ic[u] * a.Rp;
+        sx[u] = S[oi];
+        sy[u] = S[plane + oi];
+        sz[u] = S[2 * plane + oi];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = ic[u];
+        const RepSite<KM, FM> sp(a, i);
+        const float fx = fmaf(b, sp.nx, hx[u]);
+        const float fy = fmaf(b, sp.ny, hy[u]);
+        const float fz = fmaf(b, sp.nz, hz[u]);
+        const Trial32 t = trial32(draw(ra.seed, a.orig[i], g, rid, 0));
+        const float dE = (KM == K_NONE) ? delta_e32_iso(sx[u], sy[u], sz[u], t, fx, fy, fz)
+                                        : delta_e32(sx[u], sy[u], sz[u], t, fx, fy, fz, sp.k, sp.ex,
+                                                    sp.ey, sp.ez);
+        const bool live = active && valid[u];
+        const bool ok = accept32(dE, beta, t.u) && live;
+        if (live && dE != dE) atomicOr(&ra.ctl->status, 1u);
+        const size_t oi = (size_t)i * a.Rp;
+        if (ok) {
+            S[oi] = t.x;
+            S[plane + oi] = t.y;
+            S[2 * plane + oi] = t.z;
+        }
+        accumulate(acc, ok, live, dE, ok ? t.x : sx[u], ok ? t.y : sy[u], ok ? t.z : sz[u]);
     }
 }
 
@@ -134,9 +296,19 @@ struct Lanes {
     }
 };
 
+// XCD-aware bijection of [0, nt): blocks are dispatched round-robin over the
+// 8 XCDs, so block b runs on XCD b % 8; give each XCD a contiguous range of
+// tiles, so that a tile and the tiles holding its neighbours share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nt)
+{
+    const int q = nt >> 3, rm = nt & 7, x = b & 7, k = b >> 3;
+    return x * q + min(x, rm) + k;
+}
+
 // One tile of one colour phase: the body shared by the per-phase kernel and
-// the persistent kernel.  red: LDS [kRepWaves][64][5].
-template <int KM, int FM, int W>
+// the persistent kernel.  red: LDS [kRepWaves][64][5].  MAXD > 0: rows of at
+// most MAXD entries staged in LDS; MAXD == 0: generic row walk.
+template <int KM, int FM, int W, int MAXD>
 __device__ __forceinline__ void rep_tile(const RepLaneArgs &a, int colour, int tile, int group,
                                          uint32_t g, const RunArgs &ra, double *part,
                                          double *red)
@@ -144,7 +316,8 @@ __device__ __forceinline__ void rep_tile(const RepLaneArgs &a, int colour, int t
     constexpr int SPL = kRepSitesPerWave * W / 64;   // sites per lane group
     const Lanes<W> L(group);
     const int ce = a.cls_off[colour + 1];
-    const int base = a.cls_off[colour] + tile * kRepTile + L.w * kRepSitesPerWave + L.sub * SPL;
+    const int wbase = a.cls_off[colour] + tile * kRepTile + L.w * kRepSitesPerWave;
+    const int base = wbase + L.sub * SPL;
     const bool active = L.r < a.R;
     const uint32_t s_abs = g / (uint32_t)ra.M;
     float beta = 0.0f, b = 0.0f;
@@ -156,10 +329,22 @@ __device__ __forceinline__ void rep_tile(const RepLaneArgs &a, int colour, int t
         rid = a.rep_id[L.r];
     }
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int j = 0; j < SPL; ++j) {
-        const int i = base + j;
-        if (i >= ce) break;
-        rep_site_update<KM, FM>(a, i, L.r, g, beta, b, rid, active, ra, acc);
+    if constexpr (MAXD > 0) {
+        const SpinPlanes sp3(a);
+        for (int j = 0; j < SPL && base + j < ce; j += 2) {
+            if constexpr (W == 64)
+                rep_pair_uniform<KM, FM, MAXD>(a, sp3, base + j, ce, L.r, g, beta, b, rid, active,
+                                               ra, acc);
+            else
+                rep_pair_update<KM, FM, MAXD>(a, base + j, ce, L.r, g, beta, b, rid, active, ra,
+                                              acc);
+        }
+    } else {
+        for (int j = 0; j < SPL; ++j) {
+            const int i = base + j;
+            if (i >= ce) break;
+            rep_site_update<KM, FM>(a, i, L.r, g, beta, b, rid, active, ra, acc);
+        }
     }
 #pragma unroll
     for (int q = 0; q < 5; ++q) red[(L.w * 64 + L.lane) * 5 + q] = acc[q];
@@ -211,112 +396,234 @@ __device__ __forceinline__ void rep_tile_energy(const RepLaneArgs &a, int tg, in
     __syncthreads();
 }
 
-// Chunk k of the tile records: sequential sum over its tiles, per replica.
-__device__ __forceinline__ void rep_chunk_sum(const RepLaneArgs &a, int ntiles, int k, int rr,
-                                              const double *part, double *chunk)
+// Chunk k of the tile records, per (field, replica): the chunk's tiles are
+// cut into four fixed quarters, each summed in order by one thread, and the
+// quarters added in order, so one load latency covers a quarter.  Replicas
+// are handled 32 at a time through buf (LDS, >= 4 * 6 * 32 doubles).
+__device__ __forceinline__ void rep_chunk_sum(const RepLaneArgs &a, int ntiles, int k,
+                                              const double *part, double *chunk, double *buf)
 {
+    constexpr int G = 32;
     const int tb = (int)((int64_t)ntiles * k / kChunks), te = (int)((int64_t)ntiles * (k + 1) / kChunks);
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int t = tb; t < te; ++t)
+    const size_t stride = (size_t)kRecFields * a.Rp;
+    for (int r0 = 0; r0 < a.Rp; r0 += G) {
+        for (int e = threadIdx.x; e < 4 * 6 * G; e += blockDim.x) {
+            const int s = e / (6 * G), q = (e / G) % 6, rr = r0 + e % G;
+            const int t0 = tb + (te - tb) * s / 4, t1 = tb + (te - tb) * (s + 1) / 4;
+            double v = 0.0;
+            if (rr < a.Rp) {
+                const double *p = part + (size_t)q * a.Rp + rr;
+                int t = t0;
+                for (; t + 8 <= t1; t += 8) {
+                    double x[8];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) v[q] += part[((size_t)t * kRecFields + q) * a.Rp + rr];
+                    for (int u = 0; u < 8; ++u) x[u] = p[(size_t)(t + u) * stride];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) chunk[((size_t)k * 6 + q) * a.Rp + rr] = v[q];
+                    for (int u = 0; u < 8; ++u) v += x[u];
+                }
+                for (; t < t1; ++t) v += p[(size_t)t * stride];
+            }
+            buf[e] = v;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 6 * G; e += blockDim.x) {
+            const int q = e / G, rr = r0 + e % G;
+            if (rr < a.Rp)
+                chunk[((size_t)k * 6 + q) * a.Rp + rr] =
+                    ((buf[e] + buf[6 * G + e]) + buf[12 * G + e]) + buf[18 * G + e];
+        }
+        __syncthreads();
+    }
 }
 
-// Final sum over chunks in order; writes history and the carried energy.
-__device__ __forceinline__ void rep_final(const RepLaneArgs &a, int rr, uint32_t g,
-                                          const RunArgs &ra, const double *chunk)
+// Final sum over the chunks: eight fixed groups of eight chunks, each summed
+// in order by one thread, then the groups in order; then the history record
+// and the carried energy of those replicas.  buf: LDS, >= 8 * 6 * 32 doubles.
+__device__ __forceinline__ void rep_final(const RepLaneArgs &a, uint32_t g, const RunArgs &ra,
+                                          const double *chunk, double *buf)
 {
-    if (rr >= a.R) return;
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < kChunks; ++k)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) v[q] += chunk[((size_t)k * 6 + q) * a.Rp + rr];
+    constexpr int G = 32;
     const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
-    const double E = (rep_recompute_due(m, ra.P) ? v[5] : ra.ecarry[rr]) + v[0];
-    ra.ecarry[rr] = E;
-    double *h = ra.history + (((size_t)rr * ra.S_hist + s_abs) * ra.M + m) * 5;
-    h[0] = E;
-    h[1] = v[1];
-    h[2] = v[2];
-    h[3] = v[3];
-    h[4] = v[4];
+    const bool due = rep_recompute_due(m, ra.P);
+    const size_t stride = (size_t)6 * a.Rp;
+    for (int r0 = 0; r0 < a.Rp; r0 += G) {
+        for (int e = threadIdx.x; e < 8 * 6 * G; e += blockDim.x) {
+            const int s = e / (6 * G), q = (e / G) % 6, rr = r0 + e % G;
+            double v = 0.0;
+            if (rr < a.Rp) {
+                const double *p = chunk + (size_t)q * a.Rp + rr;   // chunk layout [k][6][Rp]
+                double x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = p[(size_t)(8 * s + u) * stride];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v += x[u];
+            }
+            buf[e] = v;
+        }
+        __syncthreads();
+        for (int rl = threadIdx.x; rl < G; rl += blockDim.x) {
+            const int rr = r0 + rl;
+            if (rr >= a.R) continue;
+            double v[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                double t = 0.0;
+                for (int s = 0; s < 8; ++s) t += buf[(s * 6 + q) * G + rl];
+                v[q] = t;
+            }
+            const double E = (due ? v[5] : ra.ecarry[rr]) + v[0];
+            ra.ecarry[rr] = E;
+            double *h = ra.history + (((size_t)rr * ra.S_hist + s_abs) * ra.M + m) * 5;
+            h[0] = E;
+            h[1] = v[1];
+            h[2] = v[2];
+            h[3] = v[3];
+            h[4] = v[4];
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace
 
-// Per-phase kernel: grid (tiles of the colour, replica groups).
-template <int KM, int FM, int W>
-__global__ __launch_bounds__(256) void k_rep_phase(RepLaneArgs a, int colour, RunArgs ra)
+// MCS numbering of the per-phase launches: g = ctl->g + t_off, where ctl->g
+// is the first MCS of the current launch sequence (a captured graph replays
+// one such sequence) and t_off the launch's position in it.  Tile records of
+// MCS g go to parity g & 1 of the record buffer.
+__device__ __forceinline__ double *rep_part(const RunArgs &ra, const RepLaneArgs &a, int ntiles,
+                                            uint32_t g)
 {
-    __shared__ double red[kRepWaves * 64 * 5];
-    rep_tile<KM, FM, W>(a, colour, blockIdx.x, blockIdx.y, ra.ctl->g, ra, ra.partials, red);
+    return ra.partials + (size_t)(g & 1u) * ntiles * kRecFields * a.Rp;
 }
 
-template <int KM, int FM, int W>
-__global__ __launch_bounds__(256) void k_rep_efull(RepLaneArgs a, RunArgs ra)
-{
-    __shared__ double red[kRepWaves * 64 * 5];
-    const uint32_t g = ra.ctl->g;
-    if (!rep_recompute_due(g % (uint32_t)ra.M, ra.P)) return;
-    rep_tile_energy<KM, FM, W>(a, blockIdx.x, blockIdx.y, g, ra, ra.partials, red);
-}
-
-// Reduction: block k (k < 64) sums chunk k for all replicas; the last block to
-// finish adds the chunks in order, writes the history and advances g.
-__global__ __launch_bounds__(256) void k_rep_reduce(RepLaneArgs a, int ntiles, RunArgs ra,
-                                                    double *chunk)
+// Sum the records of MCS g in 64 chunks (block k < 64 takes chunk k); the
+// last block to finish adds the chunks in order and writes the history of g.
+// Returns true in the block that wrote it.
+__device__ __forceinline__ bool rep_reduce_blocks(const RepLaneArgs &a, int ntiles, uint32_t g,
+                                                  const RunArgs &ra, double *buf)
 {
     __shared__ int last;
-    const uint32_t g = ra.ctl->g;
-    for (int rr = threadIdx.x; rr < a.Rp; rr += blockDim.x)
-        rep_chunk_sum(a, ntiles, blockIdx.x, rr, ra.partials, chunk);
+    double *chunk = ra.partials + (size_t)2 * ntiles * kRecFields * a.Rp;
+    rep_chunk_sum(a, ntiles, blockIdx.x, rep_part(ra, a, ntiles, g), chunk, buf);
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) last = (atomicAdd(&ra.ctl->pad[0], 1u) == gridDim.x - 1);
+    if (threadIdx.x == 0) last = (atomicAdd(&ra.ctl->pad[0], 1u) == kChunks - 1);
     __syncthreads();
-    if (!last) return;
+    if (!last) return false;
     __threadfence();
-    for (int rr = threadIdx.x; rr < a.Rp; rr += blockDim.x) rep_final(a, rr, g, ra, chunk);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        ra.ctl->pad[0] = 0;
-        ra.ctl->g = g + 1;
-    }
+    rep_final(a, g, ra, chunk, buf);
+    if (threadIdx.x == 0) ra.ctl->pad[0] = 0;
+    return true;
+}
+
+// Per-phase kernel: grid (tiles of the colour, replica groups).  With
+// reduce_prev (colour 0 of every MCS but the first of a sequence), the first
+// 64 blocks also reduce the previous MCS's records, off the critical path of
+// a separate launch.
+template <int KM, int FM, int W, int MAXD>
+__global__ __launch_bounds__(kRepThreads) void k_rep_phase(RepLaneArgs a, int colour, int t_off,
+                                                           int reduce_prev, int ntiles, RunArgs ra)
+{
+    __shared__ double red[kRedDoubles];
+    const uint32_t g = ra.ctl->g + (uint32_t)t_off;
+    if (reduce_prev && blockIdx.x < kChunks && blockIdx.y == 0)
+        rep_reduce_blocks(a, ntiles, g - 1, ra, red);
+    const int nt = a.tile_off[colour + 1] - a.tile_off[colour];
+    if ((int)blockIdx.x < nt)   // extra blocks exist only to carry the folded reduction
+        rep_tile<KM, FM, W, MAXD>(a, colour, xcd_tile(blockIdx.x, nt), blockIdx.y, g, ra,
+                                  rep_part(ra, a, ntiles, g), red);
+}
+
+template <int KM, int FM, int W>
+__global__ __launch_bounds__(kRepThreads) void k_rep_efull(RepLaneArgs a, int t_off, int ntiles,
+                                                           RunArgs ra)
+{
+    __shared__ double red[kRedDoubles];
+    const uint32_t g = ra.ctl->g + (uint32_t)t_off;
+    if (!rep_recompute_due(g % (uint32_t)ra.M, ra.P)) return;
+    rep_tile_energy<KM, FM, W>(a, blockIdx.x, blockIdx.y, g, ra, rep_part(ra, a, ntiles, g), red);
+}
+
+// End of a launch sequence: reduce its last MCS (ctl->g + t_off) and move
+// ctl->g on by `advance`.
+__global__ __launch_bounds__(1024) void k_rep_reduce(RepLaneArgs a, int ntiles, int t_off,
+                                                     int advance, RunArgs ra)
+{
+    __shared__ double buf[8 * 6 * 32];
+    const uint32_t g0 = ra.ctl->g;
+    if (rep_reduce_blocks(a, ntiles, g0 + (uint32_t)t_off, ra, buf) && threadIdx.x == 0)
+        ra.ctl->g = g0 + (uint32_t)advance;
 }
 
 // ------------------------------------------------------------- persistent
-// One launch for the whole run.  Device-wide barrier: a monotone arrival
-// counter; every wait is bounded (spin_cap sleeps) and any timeout, once
-// flagged, releases every later wait at once, so the grid always drains.
-__device__ __forceinline__ void grid_barrier(Ctl *ctl, uint32_t &epoch, uint32_t cap)
+// One launch for the whole run.  Device-wide barrier without a contended
+// counter: every block publishes the barrier's epoch in its own 128-byte flag
+// (after a release fence); block 0 waits for all flags, then publishes the
+// epoch in one generation word, which the other blocks wait for (then an
+// acquire fence).  All polls are relaxed loads; every wait is bounded (cap
+// sleeps) and a timeout, once flagged, releases every later wait at once, so
+// the grid always drains.
+__device__ __forceinline__ bool barrier_wait(const uint32_t *w, uint32_t epoch, Ctl *ctl,
+                                             uint32_t cap)
+{
+    uint32_t n = 0;
+    while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++n > cap ||
+            (__hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2u)) {
+            atomicOr(&ctl->status, 2u);
+            return false;
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ void grid_barrier(Ctl *ctl, uint32_t *flags, uint32_t &epoch,
+                                             uint32_t cap)
 {
     __syncthreads();
+    ++epoch;
     if (threadIdx.x == 0) {
-        ++epoch;
-        const uint32_t target = epoch * gridDim.x;
-        __threadfence();
-        __hip_atomic_fetch_add(&ctl->bar_arrive, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t n = 0;
-        while (__hip_atomic_load(&ctl->bar_arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++n > cap ||
-                (__hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2u)) {
-                atomicOr(&ctl->status, 2u);
-                break;
-            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&flags[blockIdx.x * 32], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (blockIdx.x == 0) {
+        for (int j = threadIdx.x; j < (int)gridDim.x; j += blockDim.x)
+            barrier_wait(&flags[j * 32], epoch, ctl, cap);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_store(&ctl->bar_arrive, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __threadfence();
+    }
+    if (threadIdx.x == 0) {
+        barrier_wait(&ctl->bar_arrive, epoch, ctl, cap);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
 
-template <int KM, int FM, int W>
-__global__ __launch_bounds__(256) void k_rep_persistent(RepLaneArgs a, int ntiles, RunArgs ra,
-                                                        double *chunk, uint32_t cap)
+// Work items [0, NT) of one phase split XCD by XCD into contiguous ranges;
+// the blocks of an XCD stride through its range.
+struct XcdRange {
+    int u, end, step;
+    __device__ __forceinline__ XcdRange(int NT)
+    {
+        const int G = gridDim.x, b = blockIdx.x, x = b & 7;
+        const int q = NT >> 3, rm = NT & 7;
+        const int start = x * q + min(x, rm);
+        end = start + q + (x < rm ? 1 : 0);
+        step = (G >> 3) + (x < (G & 7) ? 1 : 0);
+        u = start + (b >> 3);
+    }
+};
+
+template <int KM, int FM, int W, int MAXD>
+__global__ __launch_bounds__(kRepThreads) void k_rep_persistent(RepLaneArgs a, int ntiles,
+                                                                RunArgs ra, double *chunk,
+                                                                uint32_t *flags, uint32_t cap)
 {
-    __shared__ double red[kRepWaves * 64 * 5];
+    __shared__ double red[kRedDoubles];   // tile sums, reused by the reductions
     uint32_t epoch = 0;
     const int groups = (a.Rp + W - 1) / W;
     for (int t = 0; t < ra.n_mcs_run; ++t) {
@@ -327,29 +634,24 @@ __global__ __launch_bounds__(256) void k_rep_persistent(RepLaneArgs a, int ntile
             for (int u = blockIdx.x; u < ntiles * groups; u += gridDim.x)
                 rep_tile_energy<KM, FM, W>(a, u % ntiles, u / ntiles, g, ra, part, red);
             // the energy reads spins that colour 0 is about to change
-            grid_barrier(ra.ctl, epoch, cap);
+            grid_barrier(ra.ctl, flags, epoch, cap);
         }
         for (int c = 0; c < a.ncol; ++c) {
             const int nt = a.tile_off[c + 1] - a.tile_off[c];
-            for (int u = blockIdx.x; u < nt * groups; u += gridDim.x)
-                rep_tile<KM, FM, W>(a, c, u % nt, u / nt, g, ra, part, red);
-            grid_barrier(ra.ctl, epoch, cap);
+            for (XcdRange it(nt * groups); it.u < it.end; it.u += it.step)
+                rep_tile<KM, FM, W, MAXD>(a, c, it.u % nt, it.u / nt, g, ra, part, red);
+            grid_barrier(ra.ctl, flags, epoch, cap);
             // the chunk sums of the previous MCS are complete once colour 0
-            // of this one is: add them in order and write its history
-            if (c == 0 && t > 0 && blockIdx.x == 0)
-                for (int rr = threadIdx.x; rr < a.Rp; rr += blockDim.x)
-                    rep_final(a, rr, g - 1, ra, chunk + (size_t)((t - 1) & 1) * kChunks * 6 * a.Rp);
+            // of this one is: the last block adds them and writes its history
+            if (c == 0 && t > 0 && blockIdx.x == gridDim.x - 1)
+                rep_final(a, g - 1, ra, chunk + (size_t)((t - 1) & 1) * kChunks * 6 * a.Rp, red);
         }
-        for (int k = blockIdx.x; k < kChunks; k += gridDim.x)
-            for (int rr = threadIdx.x; rr < a.Rp; rr += blockDim.x)
-                rep_chunk_sum(a, ntiles, k, rr, part, chk);
+        for (int k = blockIdx.x; k < kChunks; k += gridDim.x) rep_chunk_sum(a, ntiles, k, part, chk, red);
     }
-    grid_barrier(ra.ctl, epoch, cap);
-    if (blockIdx.x == 0 && ra.n_mcs_run > 0) {
+    grid_barrier(ra.ctl, flags, epoch, cap);
+    if (blockIdx.x == gridDim.x - 1 && ra.n_mcs_run > 0) {
         const int t = ra.n_mcs_run - 1;
-        for (int rr = threadIdx.x; rr < a.Rp; rr += blockDim.x)
-            rep_final(a, rr, ra.g0 + (uint32_t)t, ra, chunk + (size_t)(t & 1) * kChunks * 6 * a.Rp);
-        __syncthreads();
+        rep_final(a, ra.g0 + (uint32_t)t, ra, chunk + (size_t)(t & 1) * kChunks * 6 * a.Rp, red);
         if (threadIdx.x == 0) ra.ctl->g = ra.g0 + (uint32_t)ra.n_mcs_run;
     }
 }
@@ -421,57 +723,74 @@ hipError_t launch_to_user_rep(hipStream_t st, const RepLaneArgs &a, int rep, dou
 
 static int lane_width(const RepLaneArgs &a) { return a.Rp % 64 == 0 ? 64 : 32; }
 
-hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour,
-                            const RepLaneArgs &a, const RunArgs &ra)
+// Rows padded to 6 or 8 slots use the fixed-width pair updates (the plan
+// pads to 6 when every row has at most 6 entries, else to 8); wider rows the
+// generic row walk.
+#define HSIM_DISPATCH_D(ELLW_, ...)                                                             \
+    do {                                                                                         \
+        if ((ELLW_) == 6) { constexpr int MAXD = 6; __VA_ARGS__; }                               \
+        else if ((ELLW_) == 8) { constexpr int MAXD = 8; __VA_ARGS__; }                          \
+        else { constexpr int MAXD = 0; __VA_ARGS__; }                                            \
+    } while (0)
+
+hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour, int t_off,
+                            bool reduce_prev, const RepLaneArgs &a, int ntiles, const RunArgs &ra)
 {
     const int nt = a.tile_off[colour + 1] - a.tile_off[colour];
     if (nt <= 0) return hipSuccess;
     const int Wd = lane_width(a);
-    dim3 grid((unsigned)nt, (unsigned)(a.Rp / Wd)), blk(256);
-    HSIM_DISPATCH_KFW(kmode, fmode, Wd, {
-        hipLaunchKernelGGL((k_rep_phase<KM, FM, W>), grid, blk, 0, st, a, colour, ra);
-    });
+    // the folded reduction needs at least kChunks blocks
+    dim3 grid((unsigned)(reduce_prev ? std::max(nt, kChunks) : nt), (unsigned)(a.Rp / Wd));
+    dim3 blk(kRepThreads);
+    HSIM_DISPATCH_KFW(kmode, fmode, Wd, HSIM_DISPATCH_D(a.ell_w, {
+        hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD>), grid, blk, 0, st, a, colour, t_off,
+                           reduce_prev ? 1 : 0, ntiles, ra);
+    }));
     return hipGetLastError();
 }
 
 hipError_t launch_rep_efull(hipStream_t st, int kmode, int fmode, const RepLaneArgs &a,
-                            int ntiles, const RunArgs &ra)
+                            int ntiles, int t_off, const RunArgs &ra)
 {
     const int Wd = lane_width(a);
-    dim3 grid((unsigned)ntiles, (unsigned)(a.Rp / Wd)), blk(256);
+    dim3 grid((unsigned)ntiles, (unsigned)(a.Rp / Wd)), blk(kRepThreads);
     HSIM_DISPATCH_KFW(kmode, fmode, Wd, {
-        hipLaunchKernelGGL((k_rep_efull<KM, FM, W>), grid, blk, 0, st, a, ra);
+        hipLaunchKernelGGL((k_rep_efull<KM, FM, W>), grid, blk, 0, st, a, t_off, ntiles, ra);
     });
     return hipGetLastError();
 }
 
-hipError_t launch_rep_reduce(hipStream_t st, const RepLaneArgs &a, int ntiles, const RunArgs &ra)
+hipError_t launch_rep_reduce(hipStream_t st, const RepLaneArgs &a, int ntiles, int t_off,
+                             int advance, const RunArgs &ra)
 {
-    // chunk sums live right after the tile records (two parities) in the workspace
-    double *chunk = ra.partials + (size_t)2 * ntiles * kRecFields * a.Rp;
-    hipLaunchKernelGGL(k_rep_reduce, dim3(kChunks), dim3(256), 0, st, a, ntiles, ra, chunk);
+    hipLaunchKernelGGL(k_rep_reduce, dim3(kChunks), dim3(1024), 0, st, a, ntiles, t_off, advance,
+                       ra);
     return hipGetLastError();
 }
 
 hipError_t launch_rep_persistent(hipStream_t st, int kmode, int fmode, const RepLaneArgs &a,
-                                 int ntiles, int grid, const RunArgs &ra, uint32_t spin_cap)
+                                 int ntiles, int grid, const RunArgs &ra, uint32_t *flags,
+                                 uint32_t spin_cap)
 {
+    if (grid > kMaxPersistentBlocks) return hipErrorInvalidValue;
     double *chunk = ra.partials + (size_t)2 * ntiles * kRecFields * a.Rp;
+    hipError_t e = launch_fill_u32(st, flags, 0u, (int64_t)grid * 32);
+    if (e != hipSuccess) return e;
     const int Wd = lane_width(a);
-    HSIM_DISPATCH_KFW(kmode, fmode, Wd, {
-        hipLaunchKernelGGL((k_rep_persistent<KM, FM, W>), dim3((unsigned)grid), dim3(256), 0, st,
-                           a, ntiles, ra, chunk, spin_cap);
-    });
+    HSIM_DISPATCH_KFW(kmode, fmode, Wd, HSIM_DISPATCH_D(a.ell_w, {
+        hipLaunchKernelGGL((k_rep_persistent<KM, FM, W, MAXD>), dim3((unsigned)grid),
+                           dim3(kRepThreads), 0, st, a, ntiles, ra, chunk, flags, spin_cap);
+    }));
     return hipGetLastError();
 }
 
-int rep_persistent_blocks_per_cu(int kmode, int fmode, int lane_w)
+int rep_persistent_blocks_per_cu(int kmode, int fmode, int lane_w, int ell_w)
 {
     int nb = 0;
-    HSIM_DISPATCH_KFW(kmode, fmode, lane_w, {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rep_persistent<KM, FM, W>, 256, 0) != hipSuccess)
+    HSIM_DISPATCH_KFW(kmode, fmode, lane_w, HSIM_DISPATCH_D(ell_w, {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rep_persistent<KM, FM, W, MAXD>, kRepThreads, 0) != hipSuccess)
             nb = 0;
-    });
+    }));
     return nb;
 }
 

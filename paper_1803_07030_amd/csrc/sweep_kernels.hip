@@ -92,28 +92,66 @@ struct SiteParams {
 
 // One site's update in the site-lane / block layouts.  S points at the
 // replica's spins [3][n_pad] (global or LDS).  Returns the accumulators.
-template <typename T, int KM, int FM, bool TRACE>
+// Exchange field of site i: the CSR row walk (MAXD == 0) or the padded row of
+// MAXD slots (slot-major copy, coalesced across the lanes of a wave).  A
+// padding slot holds the site itself with constant 0 and leaves every sum
+// unchanged, so both walks give the same bits.
+template <typename T, int MAXD>
+__device__ __forceinline__ void exchange_field(const RepDesc &rd, const T *S, int i, T &hx, T &hy,
+                                               T &hz)
+{
+    const int np = rd.n_pad;
+    hx = T(0);
+    hy = T(0);
+    hz = T(0);
+    if constexpr (MAXD > 0) {
+        const T *EJ = (const T *)rd.ellT_J;
+#pragma unroll
+        for (int sl = 0; sl < MAXD; ++sl) {
+            const int32_t j = rd.ellT_col[sl * rd.n + i];
+            const T Jp = EJ[sl * rd.n + i];
+            if constexpr (sizeof(T) == 4) {
+                hx = fmaf(Jp, S[j], hx);
+                hy = fmaf(Jp, S[np + j], hy);
+                hz = fmaf(Jp, S[2 * np + j], hz);
+            } else {
+                hx = hx + Jp * S[j];
+                hy = hy + Jp * S[np + j];
+                hz = hz + Jp * S[2 * np + j];
+            }
+        }
+    } else {
+        const T *J = (const T *)rd.J;
+        for (int32_t p = rd.rp[i]; p < rd.rp[i + 1]; ++p) {
+            const int32_t j = rd.ci[p];
+            const T Jp = J[p];
+            if constexpr (sizeof(T) == 4) {
+                hx = fmaf(Jp, S[j], hx);
+                hy = fmaf(Jp, S[np + j], hy);
+                hz = fmaf(Jp, S[2 * np + j], hz);
+            } else {
+                hx = hx + Jp * S[j];
+                hy = hy + Jp * S[np + j];
+                hz = hz + Jp * S[2 * np + j];
+            }
+        }
+    }
+}
+
+template <typename T, int KM, int FM, bool TRACE, int MAXD>
 __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint32_t g,
                                             const RunArgs &ra, int rep, T beta, T b,
                                             double (&acc)[5])
 {
     const int np = rd.n_pad;
-    const int32_t rb = rd.rp[i], re = rd.rp[i + 1];
-    const T *J = (const T *)rd.J;
     const SiteParams<T, KM, FM> sp(rd, i);
     const T sx = S[i], sy = S[np + i], sz = S[2 * np + i];
     const uint32_t orig = rd.orig[i];
     bool acc_move;
     T nx, ny, nz, dE;
+    T hx, hy, hz;
+    exchange_field<T, MAXD>(rd, S, i, hx, hy, hz);
     if constexpr (sizeof(T) == 4) {
-        float hx = 0.0f, hy = 0.0f, hz = 0.0f;
-        for (int32_t p = rb; p < re; ++p) {
-            const int32_t j = rd.ci[p];
-            const float Jp = J[p];
-            hx = fmaf(Jp, S[j], hx);
-            hy = fmaf(Jp, S[np + j], hy);
-            hz = fmaf(Jp, S[2 * np + j], hz);
-        }
         hx = fmaf(b, sp.nx, hx);
         hy = fmaf(b, sp.ny, hy);
         hz = fmaf(b, sp.nz, hz);
@@ -125,14 +163,6 @@ __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint
         ny = t.y;
         nz = t.z;
     } else {
-        double hx = 0.0, hy = 0.0, hz = 0.0;
-        for (int32_t p = rb; p < re; ++p) {
-            const int32_t j = rd.ci[p];
-            const double Jp = J[p];
-            hx = hx + Jp * S[j];
-            hy = hy + Jp * S[np + j];
-            hz = hz + Jp * S[2 * np + j];
-        }
         hx = hx + b * sp.nx;
         hy = hy + b * sp.ny;
         hz = hz + b * sp.nz;
@@ -146,20 +176,17 @@ __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint
         S[i] = nx;
         S[np + i] = ny;
         S[2 * np + i] = nz;
-        acc[0] += (double)dE;
-        acc[4] += 1.0;
         if (TRACE)
             atomicOr(&ra.trace[((size_t)rep * ra.n_mcs_run + (g - ra.g0)) * ra.trace_words +
                                (orig >> 5)],
                      1u << (orig & 31));
-        acc[1] += (double)nx;
-        acc[2] += (double)ny;
-        acc[3] += (double)nz;
-    } else {
-        acc[1] += (double)sx;
-        acc[2] += (double)sy;
-        acc[3] += (double)sz;
     }
+    // branch-free accumulation of the history sums
+    acc[0] += acc_move ? (double)dE : 0.0;
+    acc[4] += acc_move ? 1.0 : 0.0;
+    acc[1] += (double)(acc_move ? nx : sx);
+    acc[2] += (double)(acc_move ? ny : sy);
+    acc[3] += (double)(acc_move ? nz : sz);
 }
 
 // Site energy in double precision, each bond counted half at either end:
@@ -274,7 +301,7 @@ hipError_t launch_to_user(hipStream_t st, bool f64, const RepDesc *reps, int rep
 }
 
 // ------------------------------------------------------- site-lane phases
-template <typename T, int KM, int FM, bool TRACE>
+template <typename T, int KM, int FM, bool TRACE, int MAXD>
 __global__ __launch_bounds__(kSiteBlock) void k_site_phase(const RepDesc *__restrict__ reps,
                                                            const Tile *__restrict__ tiles,
                                                            int tile_off, RunArgs ra)
@@ -290,7 +317,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_phase(const RepDesc *__rest
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const int i = t.begin + (int)threadIdx.x;
     if (i < t.end)
-        site_update<T, KM, FM, TRACE>(rd, (T *)rd.spins, i, g, ra, t.rep, beta, b, acc);
+        site_update<T, KM, FM, TRACE, MAXD>(rd, (T *)rd.spins, i, g, ra, t.rep, beta, b, acc);
     block_sum<5>(acc, red);
     if (threadIdx.x == 0) {
         double *rec = ra.partials + (size_t)(tile_off + blockIdx.x) * kRecSite;
@@ -364,21 +391,28 @@ __global__ __launch_bounds__(1024) void k_site_reduce(const int32_t *__restrict_
         else { constexpr int KM = K_SITE, FM = F_SITE; __VA_ARGS__; }                            \
     } while (0)
 
-hipError_t launch_site_phase(hipStream_t st, bool f64, int kmode, int fmode, bool trace,
+#define HSIM_DISPATCH_W(ELLW_, ...)                                                             \
+    do {                                                                                         \
+        if ((ELLW_) == 6) { constexpr int MAXD = 6; __VA_ARGS__; }                               \
+        else if ((ELLW_) == 8) { constexpr int MAXD = 8; __VA_ARGS__; }                          \
+        else { constexpr int MAXD = 0; __VA_ARGS__; }                                            \
+    } while (0)
+
+hipError_t launch_site_phase(hipStream_t st, bool f64, int kmode, int fmode, bool trace, int ellw,
                              const RepDesc *reps, const Tile *tiles, int tile_off, int ntiles,
                              const RunArgs &ra)
 {
     if (ntiles <= 0) return hipSuccess;
     dim3 grid((unsigned)ntiles), blk(kSiteBlock);
-    HSIM_DISPATCH_KF(kmode, fmode, {
+    HSIM_DISPATCH_KF(kmode, fmode, HSIM_DISPATCH_W(ellw, {
         if (f64) {
-            if (trace) hipLaunchKernelGGL((k_site_phase<double, KM, FM, true>), grid, blk, 0, st, reps, tiles, tile_off, ra);
-            else hipLaunchKernelGGL((k_site_phase<double, KM, FM, false>), grid, blk, 0, st, reps, tiles, tile_off, ra);
+            if (trace) hipLaunchKernelGGL((k_site_phase<double, KM, FM, true, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, ra);
+            else hipLaunchKernelGGL((k_site_phase<double, KM, FM, false, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, ra);
         } else {
-            if (trace) hipLaunchKernelGGL((k_site_phase<float, KM, FM, true>), grid, blk, 0, st, reps, tiles, tile_off, ra);
-            else hipLaunchKernelGGL((k_site_phase<float, KM, FM, false>), grid, blk, 0, st, reps, tiles, tile_off, ra);
+            if (trace) hipLaunchKernelGGL((k_site_phase<float, KM, FM, true, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, ra);
+            else hipLaunchKernelGGL((k_site_phase<float, KM, FM, false, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, ra);
         }
-    });
+    }));
     return hipGetLastError();
 }
 
@@ -405,7 +439,7 @@ hipError_t launch_site_reduce(hipStream_t st, const int32_t *rep_tiles, int ncol
 // One workgroup owns one replica for the whole run: colour classes are
 // separated by workgroup barriers, spins live in LDS when they fit, and the
 // per-MCS history is written directly.
-template <typename T, int KM, int FM, bool TRACE, bool LDS>
+template <typename T, int KM, int FM, bool TRACE, bool LDS, int MAXD>
 __global__ __launch_bounds__(1024) void k_block_sweep(const RepDesc *__restrict__ reps, RunArgs ra)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -442,7 +476,7 @@ __global__ __launch_bounds__(1024) void k_block_sweep(const RepDesc *__restrict_
         for (int c = 0; c < rd.ncol; ++c) {
             const int ce = rd.cls_off[c + 1];
             for (int i = rd.cls_off[c] + threadIdx.x; i < ce; i += blockDim.x)
-                site_update<T, KM, FM, TRACE>(rd, S, i, g, ra, rep, beta, b, acc);
+                site_update<T, KM, FM, TRACE, MAXD>(rd, S, i, g, ra, rep, beta, b, acc);
             __syncthreads();
         }
         block_sum<5>(acc, red);
@@ -477,20 +511,20 @@ int block_sweep_max_lds(bool)
 }
 
 hipError_t launch_block_sweep(hipStream_t st, bool f64, int kmode, int fmode, bool trace,
-                              bool lds, int threads, size_t lds_bytes, const RepDesc *reps,
-                              const RunArgs &ra)
+                              int ellw, bool lds, int threads, size_t lds_bytes,
+                              const RepDesc *reps, const RunArgs &ra)
 {
     dim3 grid((unsigned)ra.R), blk((unsigned)threads);
     const size_t sh = lds ? lds_bytes : 0;
 #define HSIM_BLK(T_, TR_, L_)                                                                  \
     do {                                                                                       \
-        auto kfn = k_block_sweep<T_, KM, FM, TR_, L_>;                                         \
+        auto kfn = k_block_sweep<T_, KM, FM, TR_, L_, MAXD>;                                         \
         if (sh > 65536)                                                                        \
             (void)hipFuncSetAttribute((const void *)kfn,                                       \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);    \
         hipLaunchKernelGGL(kfn, grid, blk, sh, st, reps, ra);                                  \
     } while (0)
-    HSIM_DISPATCH_KF(kmode, fmode, {
+    HSIM_DISPATCH_KF(kmode, fmode, HSIM_DISPATCH_W(ellw, {
         if (f64) {
             if (trace) { if (lds) HSIM_BLK(double, true, true); else HSIM_BLK(double, true, false); }
             else { if (lds) HSIM_BLK(double, false, true); else HSIM_BLK(double, false, false); }
@@ -498,7 +532,7 @@ hipError_t launch_block_sweep(hipStream_t st, bool f64, int kmode, int fmode, bo
             if (trace) { if (lds) HSIM_BLK(float, true, true); else HSIM_BLK(float, true, false); }
             else { if (lds) HSIM_BLK(float, false, true); else HSIM_BLK(float, false, false); }
         }
-    });
+    }));
 #undef HSIM_BLK
     return hipGetLastError();
 }

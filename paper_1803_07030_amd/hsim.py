@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhsim.so")
+LIB_PATH = os.environ.get("HSIM_LIBRARY", os.path.join(_HERE, "libhsim.so"))
 
 FP32, FP64_EXACT = 0, 1
 LAYOUT_AUTO, LAYOUT_SITE, LAYOUT_REPLICA, LAYOUT_BLOCK = 0, 1, 2, 3
