@@ -332,26 +332,28 @@ void batch_init_impl(hsim_batch b, int32_t mode, const double *host, hipStream_t
 
 namespace {
 
-// Launches of one MCS in the site and replica layouts.
-void enqueue_mcs(hsim_batch b, const hsim::RunArgs &ra, bool efull, hipStream_t st)
+// Site layout: MCS t_off = 0..count-1 of a launch sequence starting at
+// ctl->g (efull, colour phases, per-MCS reduction), then ctl->g moves on.
+template <typename F>
+void enqueue_site_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F efull_mask,
+                           hipStream_t st)
 {
-    if (b->layout == HSIM_LAYOUT_SITE) {
-        const auto *reps = (const hsim::RepDesc *)b->d_reps.p;
-        const auto *tiles = (const hsim::Tile *)b->d_tiles.p;
-        if (efull)
+    const auto *reps = (const hsim::RepDesc *)b->d_reps.p;
+    const auto *tiles = (const hsim::Tile *)b->d_tiles.p;
+    for (int t = 0; t < count; ++t) {
+        if (efull_mask(t))
             hip_check(hsim::launch_site_efull(st, b->f64, b->kmode, b->fmode, reps, tiles,
-                                              (int)b->tiles.size(), ra),
+                                              (int)b->tiles.size(), t, ra),
                       "efull launch");
         for (int c = 0; c < b->ncol_max; ++c)
             hip_check(hsim::launch_site_phase(st, b->f64, b->kmode, b->fmode, ra.trace != nullptr,
                                               b->ellw, reps, tiles, b->tile_off[c],
-                                              b->tile_off[c + 1] - b->tile_off[c], ra),
+                                              b->tile_off[c + 1] - b->tile_off[c], t, ra),
                       "phase launch");
-        hip_check(hsim::launch_site_reduce(st, (const int32_t *)b->d_rep_tiles.p, b->ncol_max, ra),
+        hip_check(hsim::launch_site_reduce(st, (const int32_t *)b->d_rep_tiles.p, b->ncol_max, t, ra),
                   "reduce launch");
-    } else {
-        throw Error(HSIM_E_STATE, "enqueue_mcs: replica layout uses enqueue_rep_sequence");
     }
+    if (count > 0) hip_check(hsim::launch_ctl_advance(st, ra.ctl, (uint32_t)count), "control launch");
 }
 
 // Replica layout: MCS t_off = 0..count-1 of a launch sequence starting at
@@ -384,14 +386,11 @@ bool due(uint32_t g, int M, int P)
 
 void run_plain(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st, int from, int to)
 {
-    if (b->layout == HSIM_LAYOUT_REPLICA) {
-        // ctl->g is at g0 + from here
-        const uint32_t gb = ra.g0 + (uint32_t)from;
-        enqueue_rep_sequence(b, ra, to - from,
-                             [&](int t) { return due(gb + (uint32_t)t, ra.M, ra.P); }, st);
-        return;
-    }
-    for (int t = from; t < to; ++t) enqueue_mcs(b, ra, due(ra.g0 + t, ra.M, ra.P), st);
+    // ctl->g is at g0 + from here
+    const uint32_t gb = ra.g0 + (uint32_t)from;
+    auto mask = [&](int t) { return due(gb + (uint32_t)t, ra.M, ra.P); };
+    if (b->layout == HSIM_LAYOUT_REPLICA) enqueue_rep_sequence(b, ra, to - from, mask, st);
+    else enqueue_site_sequence(b, ra, to - from, mask, st);
 }
 
 void run_graph(hsim_batch b, const hsim::RunArgs &ra, hipStream_t user_st)
@@ -428,10 +427,9 @@ void run_graph(hsim_batch b, const hsim::RunArgs &ra, hipStream_t user_st)
     hipGraphExec_t exec = nullptr;
     hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
-        if (b->layout == HSIM_LAYOUT_REPLICA)
-            enqueue_rep_sequence(b, ra, U, [&](int t) { return efull_each || t == 0; }, st);
-        else
-            for (int t = 0; t < U; ++t) enqueue_mcs(b, ra, efull_each || t == 0, st);
+        auto mask = [&](int t) { return efull_each || t == 0; };
+        if (b->layout == HSIM_LAYOUT_REPLICA) enqueue_rep_sequence(b, ra, U, mask, st);
+        else enqueue_site_sequence(b, ra, U, mask, st);
     } catch (...) {
         (void)hipStreamEndCapture(st, &graph);
         if (graph) (void)hipGraphDestroy(graph);

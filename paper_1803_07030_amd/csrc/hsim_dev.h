@@ -54,7 +54,7 @@ struct Tile {
 
 // Run-control word block at the start of the workspace.
 struct Ctl {
-    uint32_t g;          // site layout: MCS in progress; replica layout: first MCS of the launch sequence
+    uint32_t g;          // first MCS of the current launch sequence
     uint32_t status;     // HSIM_E_* bits seen on the device
     uint32_t bar_arrive; // persistent-launch barrier
     uint32_t pad[61];
@@ -111,11 +111,12 @@ hipError_t launch_to_user_rep(hipStream_t st, const RepLaneArgs &a, int rep, dou
 
 hipError_t launch_site_phase(hipStream_t st, bool f64, int kmode, int fmode, bool trace, int ellw,
                              const RepDesc *reps, const Tile *tiles, int tile_off, int ntiles,
-                             const RunArgs &ra);
+                             int t_off, const RunArgs &ra);
 hipError_t launch_site_efull(hipStream_t st, bool f64, int kmode, int fmode, const RepDesc *reps,
-                             const Tile *tiles, int ntiles, const RunArgs &ra);
-hipError_t launch_site_reduce(hipStream_t st, const int32_t *rep_tiles, int ncol_max,
+                             const Tile *tiles, int ntiles, int t_off, const RunArgs &ra);
+hipError_t launch_site_reduce(hipStream_t st, const int32_t *rep_tiles, int ncol_max, int t_off,
                               const RunArgs &ra);
+hipError_t launch_ctl_advance(hipStream_t st, Ctl *ctl, uint32_t n);
 hipError_t launch_block_sweep(hipStream_t st, bool f64, int kmode, int fmode, bool trace,
                               int ellw, bool lds, int threads, size_t lds_bytes, const RepDesc *reps,
                               const RunArgs &ra);

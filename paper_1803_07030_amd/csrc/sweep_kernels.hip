@@ -301,15 +301,18 @@ hipError_t launch_to_user(hipStream_t st, bool f64, const RepDesc *reps, int rep
 }
 
 // ------------------------------------------------------- site-lane phases
+// MCS numbering of the site-lane launches: g = ctl->g + t_off, where ctl->g is
+// the first MCS of the current launch sequence (a captured graph replays one
+// sequence; k_ctl_advance moves ctl->g on at its end).
 template <typename T, int KM, int FM, bool TRACE, int MAXD>
 __global__ __launch_bounds__(kSiteBlock) void k_site_phase(const RepDesc *__restrict__ reps,
                                                            const Tile *__restrict__ tiles,
-                                                           int tile_off, RunArgs ra)
+                                                           int tile_off, int t_off, RunArgs ra)
 {
     __shared__ double red[(kSiteBlock / 64) * 5];
     const Tile t = tiles[tile_off + blockIdx.x];
     const RepDesc &rd = reps[t.rep];
-    const uint32_t g = ra.ctl->g;
+    const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     const uint32_t s_abs = g / (uint32_t)ra.M;
     const size_t sidx = (size_t)t.rep * ra.S_hist + s_abs;
     const T beta = (T)ra.beta[sidx];
@@ -329,10 +332,10 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_phase(const RepDesc *__rest
 template <typename T, int KM, int FM>
 __global__ __launch_bounds__(kSiteBlock) void k_site_efull(const RepDesc *__restrict__ reps,
                                                            const Tile *__restrict__ tiles,
-                                                           RunArgs ra)
+                                                           int t_off, RunArgs ra)
 {
     __shared__ double red[(kSiteBlock / 64)];
-    const uint32_t g = ra.ctl->g;
+    const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     if (!recompute_due(g % (uint32_t)ra.M, ra.P)) return;
     const Tile t = tiles[blockIdx.x];
     const RepDesc &rd = reps[t.rep];
@@ -345,40 +348,50 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_efull(const RepDesc *__rest
     if (threadIdx.x == 0) ra.partials[(size_t)blockIdx.x * kRecSite + 5] = e[0];
 }
 
-// One block: replica r handled by wave (r mod 16); lanes stride its tiles.
+// Per-MCS history: one wave per replica (four per block); lanes stride the
+// replica's tiles colour by colour in table order, then a wave butterfly.
 // rep_tiles: [R][ncol_max][2] global tile ranges per colour.
-__global__ __launch_bounds__(1024) void k_site_reduce(const int32_t *__restrict__ rep_tiles,
-                                                      int ncol_max, RunArgs ra)
+__global__ __launch_bounds__(256) void k_site_reduce(const int32_t *__restrict__ rep_tiles,
+                                                     int ncol_max, int t_off, RunArgs ra)
 {
-    const uint32_t g = ra.ctl->g;
+    const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
     const bool rec_due = recompute_due(m, ra.P);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int r = w; r < ra.R; r += nw) {
-        double v[6] = {0, 0, 0, 0, 0, 0};
-        for (int c = 0; c < ncol_max; ++c) {
-            const int tb = rep_tiles[(r * ncol_max + c) * 2], te = rep_tiles[(r * ncol_max + c) * 2 + 1];
-            for (int tt = tb + lane; tt < te; tt += 64) {
-                const double *rec = ra.partials + (size_t)tt * kRecSite;
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (r >= ra.R) return;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int c = 0; c < ncol_max; ++c) {
+        const int tb = rep_tiles[(r * ncol_max + c) * 2], te = rep_tiles[(r * ncol_max + c) * 2 + 1];
+        for (int tt = tb + lane; tt < te; tt += 64) {
+            const double *rec = ra.partials + (size_t)tt * kRecSite;
 #pragma unroll
-                for (int q = 0; q < 6; ++q) v[q] += rec[q];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 6; ++q) v[q] = wave_sum(v[q]);
-        if (lane == 0) {
-            const double E = (rec_due ? v[5] : ra.ecarry[r]) + v[0];
-            ra.ecarry[r] = E;
-            double *h = ra.history + (((size_t)r * ra.S_hist + s_abs) * ra.M + m) * 5;
-            h[0] = E;
-            h[1] = v[1];
-            h[2] = v[2];
-            h[3] = v[3];
-            h[4] = v[4];
+            for (int q = 0; q < 6; ++q) v[q] += rec[q];
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) ra.ctl->g = g + 1;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+        const double E = (rec_due ? v[5] : ra.ecarry[r]) + v[0];
+        ra.ecarry[r] = E;
+        double *h = ra.history + (((size_t)r * ra.S_hist + s_abs) * ra.M + m) * 5;
+        h[0] = E;
+        h[1] = v[1];
+        h[2] = v[2];
+        h[3] = v[3];
+        h[4] = v[4];
+    }
+}
+
+__global__ void k_ctl_advance(Ctl *ctl, uint32_t n)
+{
+    if (threadIdx.x == 0) ctl->g += n;
+}
+
+hipError_t launch_ctl_advance(hipStream_t st, Ctl *ctl, uint32_t n)
+{
+    hipLaunchKernelGGL(k_ctl_advance, dim3(1), dim3(64), 0, st, ctl, n);
+    return hipGetLastError();
 }
 
 #define HSIM_DISPATCH_KF(KM_, FM_, ...)                                                         \
@@ -400,38 +413,39 @@ __global__ __launch_bounds__(1024) void k_site_reduce(const int32_t *__restrict_
 
 hipError_t launch_site_phase(hipStream_t st, bool f64, int kmode, int fmode, bool trace, int ellw,
                              const RepDesc *reps, const Tile *tiles, int tile_off, int ntiles,
-                             const RunArgs &ra)
+                             int t_off, const RunArgs &ra)
 {
     if (ntiles <= 0) return hipSuccess;
     dim3 grid((unsigned)ntiles), blk(kSiteBlock);
     HSIM_DISPATCH_KF(kmode, fmode, HSIM_DISPATCH_W(ellw, {
         if (f64) {
-            if (trace) hipLaunchKernelGGL((k_site_phase<double, KM, FM, true, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, ra);
-            else hipLaunchKernelGGL((k_site_phase<double, KM, FM, false, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, ra);
+            if (trace) hipLaunchKernelGGL((k_site_phase<double, KM, FM, true, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, t_off, ra);
+            else hipLaunchKernelGGL((k_site_phase<double, KM, FM, false, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, t_off, ra);
         } else {
-            if (trace) hipLaunchKernelGGL((k_site_phase<float, KM, FM, true, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, ra);
-            else hipLaunchKernelGGL((k_site_phase<float, KM, FM, false, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, ra);
+            if (trace) hipLaunchKernelGGL((k_site_phase<float, KM, FM, true, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, t_off, ra);
+            else hipLaunchKernelGGL((k_site_phase<float, KM, FM, false, MAXD>), grid, blk, 0, st, reps, tiles, tile_off, t_off, ra);
         }
     }));
     return hipGetLastError();
 }
 
 hipError_t launch_site_efull(hipStream_t st, bool f64, int kmode, int fmode, const RepDesc *reps,
-                             const Tile *tiles, int ntiles, const RunArgs &ra)
+                             const Tile *tiles, int ntiles, int t_off, const RunArgs &ra)
 {
     if (ntiles <= 0) return hipSuccess;
     dim3 grid((unsigned)ntiles), blk(kSiteBlock);
     HSIM_DISPATCH_KF(kmode, fmode, {
-        if (f64) hipLaunchKernelGGL((k_site_efull<double, KM, FM>), grid, blk, 0, st, reps, tiles, ra);
-        else hipLaunchKernelGGL((k_site_efull<float, KM, FM>), grid, blk, 0, st, reps, tiles, ra);
+        if (f64) hipLaunchKernelGGL((k_site_efull<double, KM, FM>), grid, blk, 0, st, reps, tiles, t_off, ra);
+        else hipLaunchKernelGGL((k_site_efull<float, KM, FM>), grid, blk, 0, st, reps, tiles, t_off, ra);
     });
     return hipGetLastError();
 }
 
-hipError_t launch_site_reduce(hipStream_t st, const int32_t *rep_tiles, int ncol_max,
+hipError_t launch_site_reduce(hipStream_t st, const int32_t *rep_tiles, int ncol_max, int t_off,
                               const RunArgs &ra)
 {
-    hipLaunchKernelGGL(k_site_reduce, dim3(1), dim3(1024), 0, st, rep_tiles, ncol_max, ra);
+    hipLaunchKernelGGL(k_site_reduce, dim3((unsigned)((ra.R + 3) / 4)), dim3(256), 0, st, rep_tiles,
+                       ncol_max, t_off, ra);
     return hipGetLastError();
 }
 

@@ -1,0 +1,272 @@
+"""The five workloads on the GPU, at (or close to) their full sizes, checked
+against the CPU oracle on sampled outputs, on statistics, or on properties that
+hold at any size.  All calls go through the C-ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_1803_07030_amd import hsim
+from _stats import block_mean_se, langevin_var
+
+pytestmark = pytest.mark.gpu
+
+
+def _start_fp32(lat, seed, rep):
+    """The random start of replica rep, computed by the oracle in double and
+    rounded to single precision (what the FP32 path starts from)."""
+    r = oracle.run(lat, [1.0], [0.0], 0, seed=seed, replica=rep, init="random")
+    return r["spins"].astype(np.float32).astype(np.float64)
+
+
+def _one_mcs_agreement(lat, start, T, Bf, seed, rep, got, k_tol=2e-6):
+    ref = oracle.run(lat, [T], [Bf], 1, seed=seed, replica=rep, init="given", spins=start,
+                     proposal=oracle.PROPOSAL_F32MAP, trace_accepts=True)
+    moved = np.any(got != start, axis=1)
+    diff = moved != ref["accept"][0].astype(bool)
+    same = ~diff
+    err = np.max(np.abs(got[same] - ref["spins"][same])) if same.any() else 0.0
+    return int(diff.sum()), err
+
+
+# ------------------------------------------------------------------ C1
+@pytest.mark.parametrize("launch", [hsim.LAUNCH_GRAPH, hsim.LAUNCH_PERSISTENT])
+def test_c1_full_size_start_and_one_mcs(launch):
+    """SC 64^3, K = 0.1 z, 64 replicas at T = 0.1..3.0, FP32, replica-lane
+    layout, in the launch modes bench.py times: the device's random start
+    equals the oracle's (rounded to single precision) bit for bit, and one MCS
+    agrees site by site on sampled replicas."""
+    lat = synth.sc_periodic(64)
+    lat.k = np.full(lat.n, 0.1)
+    R, seed = 64, 1
+    T = synth.replica_temperatures(R, 0.1, 3.0)
+    plan = hsim.Plan(lat)
+    b = hsim.Batch([plan] * R, seed=seed, precision=hsim.FP32, layout=hsim.LAYOUT_REPLICA).bind(1, 1)
+    assert b.layout == "replica"
+    b.init_spins(hsim.INIT_RANDOM)
+    torch.cuda.synchronize()
+    sampled = (0, 31, 63)
+    starts = {r: _start_fp32(lat, seed, r) for r in sampled}
+    for r in sampled:
+        assert np.array_equal(b.spins_user(r).cpu().numpy(), starts[r])
+    b.run(T[:, None], 0.0, launch=launch)
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    h = b.history.cpu().numpy()
+    for r in sampled:
+        got = b.spins_user(r).cpu().numpy()
+        nd, err = _one_mcs_agreement(lat, starts[r], T[r], 0.0, seed, r, got)
+        assert nd <= 8 and err <= 2e-6, (r, nd, err)
+        assert abs(h[r, 0, 0, 4] - np.sum(np.any(got != starts[r], axis=1))) == 0
+        ef = oracle.energy(lat, 0.0, got)["E"]
+        assert abs(h[r, 0, 0, 0] - ef) <= 1e-5 * 3 * lat.n
+
+
+# --------------------------------------------------------- FP32 statistics
+def test_fp32_statistics_match_oracle_sampler():
+    """FP32 replica-lane chains vs independent FP64 oracle chains (other
+    replica ids): per-temperature <E>/N, <|M|>/N and acceptance within 4
+    combined standard errors (block means, then the spread of replicas)."""
+    lat = synth.sc_periodic(8)
+    lat.k = np.full(lat.n, 0.1)
+    N = lat.n
+    temps = [0.6, 1.0, 2.0, 3.0]
+    per = 4
+    T = np.repeat(temps, per)
+    R, M = T.size, 3000
+    plan = hsim.Plan(lat)
+    b = hsim.Batch([plan] * R, seed=5, precision=hsim.FP32, layout=hsim.LAYOUT_REPLICA).bind(1, M)
+    b.init_spins(hsim.INIT_COLD_Z)
+    b.run(T[:, None], 0.0, launch=hsim.LAUNCH_GRAPH)
+    torch.cuda.synchronize()
+    hg = b.history.cpu().numpy()[:, 0, M // 5:, :]
+    jobs = [dict(lat=lat, T=[t], B=[0.0], mcs_per_step=M, seed=5, replica=1000 + i, init="cold")
+            for i, t in enumerate(T)]
+    res, _ = oracle.run_replicas(jobs)
+    ho = np.stack([x["history"][0, M // 5:, :] for x in res])
+
+    def obs(h):
+        return {"E": h[..., 0] / N, "absM": np.linalg.norm(h[..., 1:4], axis=-1) / N,
+                "acc": h[..., 4] / N}
+
+    og, oo = obs(hg), obs(ho)
+    worst = 0.0
+    for ti, t in enumerate(temps):
+        sl = slice(ti * per, (ti + 1) * per)
+        for key in og:
+            mg = [block_mean_se(x) for x in og[key][sl]]
+            mo = [block_mean_se(x) for x in oo[key][sl]]
+            mu_g, se_g = np.mean([m for m, _ in mg]), np.sqrt(np.sum([s ** 2 for _, s in mg])) / per
+            mu_o, se_o = np.mean([m for m, _ in mo]), np.sqrt(np.sum([s ** 2 for _, s in mo])) / per
+            z = abs(mu_g - mu_o) / np.sqrt(se_g ** 2 + se_o ** 2 + 1e-30)
+            worst = max(worst, z)
+            assert z <= 4.0, (t, key, mu_g, mu_o, se_g, se_o)
+    assert worst <= 4.0
+
+
+# ------------------------------------------------------------------ C2
+def test_c2_sphere_full_size():
+    """Core/shell sphere R = 20 (33,401 sites; 2 colours), 32 seeds, FP32,
+    lane width 32: the accept count of the first MCS from the aligned start at
+    B = +2 matches the oracle's on sampled seeds (up to near-tie decisions); a
+    short field sweep keeps unit spins, a magnetisation equal to the spin sum
+    and an incremental energy that matches a double-precision recompute."""
+    lat = synth.core_shell_ball()
+    plan = hsim.Plan(lat)
+    assert plan.info.n_colours == 2
+    R = 32
+    ids = np.arange(R, dtype=np.uint32)
+    B_sweep = np.array([2.0, 1.0, 0.0, -1.0, -2.0])
+    b = hsim.Batch([plan] * R, seed=2, replica_ids=ids, precision=hsim.FP32,
+                   layout=hsim.LAYOUT_REPLICA).bind(len(B_sweep), 40)
+    b.init_spins(hsim.INIT_COLD_Z)
+    cold = np.tile([0.0, 0.0, 1.0], (lat.n, 1))
+    # first step only, then compare one MCS
+    b.run(np.full((R, 1), 0.1), B_sweep[:1][None, :].repeat(R, 0), recompute_every=10)
+    torch.cuda.synchronize()
+    h = b.history.cpu().numpy()
+    assert b.status() == 0
+    for r in (0, 17):
+        ref = oracle.run(lat, [0.1], [2.0], 1, seed=2, replica=r, init="cold",
+                         proposal=oracle.PROPOSAL_F32MAP, trace_accepts=True)
+        assert int(ref["accept"][0].sum()) == int(h[r, 0, 0, 4]) or abs(
+            int(ref["accept"][0].sum()) - int(h[r, 0, 0, 4])) <= 2
+    b.run(np.full((R, 4), 0.1), B_sweep[1:][None, :].repeat(R, 0), first_step=1,
+          recompute_every=10)
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    h = b.history.cpu().numpy()
+    for r in (0, 9, 31):
+        s = b.spins_user(r).cpu().numpy()
+        assert np.allclose(np.linalg.norm(s, axis=1), 1.0, atol=2e-6)
+        assert np.allclose(h[r, -1, -1, 1:4], s.sum(axis=0), rtol=0, atol=1e-6 * lat.n)
+        e = oracle.energy(lat, -2.0, s)
+        assert abs(h[r, -1, -1, 0] - e["E"]) <= 1e-5 * e["scale"]
+    assert np.all(h[:, 0, -1, 3] > 0)
+    del cold
+
+
+# ------------------------------------------------------------------ C3
+def test_c3_uneven_film_batch_fp64_bit_exact():
+    """An uneven batch of diluted films (odd and even L: 2 to 6 colours, one
+    batch, site layout, FP64): every film equals its own oracle run bit for
+    bit."""
+    films = [synth.diluted_film(L, d, seed=100 + i)
+             for i, (L, d) in enumerate([(16, 2), (17, 3), (23, 5), (30, 2), (19, 4), (40, 3)])]
+    plans = [hsim.Plan(f) for f in films]
+    Ts = np.array([0.3, 0.9, 1.4, 2.0, 0.6, 1.1])
+    b = hsim.Batch(plans, seed=3, precision=hsim.FP64_EXACT, layout=hsim.LAYOUT_SITE).bind(1, 6)
+    b.init_spins(hsim.INIT_COLD_Z)
+    b.run(Ts[:, None], 0.0)
+    torch.cuda.synchronize()
+    H = b.history.cpu().numpy()
+    for r, f in enumerate(films):
+        ref = oracle.run(f, [Ts[r]], [0.0], 6, seed=3, replica=r, init="cold")
+        assert np.array_equal(b.spins_user(r).cpu().numpy(), ref["spins"])
+        assert np.array_equal(H[r][..., 4], ref["history"][..., 4])
+
+
+def test_c3_full_batch_fp32():
+    """All 256 films (8.6M sites) in one site-layout batch, FP32, graph
+    launch: unit spins, incremental vs full energy and one-MCS site agreement
+    on sampled films."""
+    films, Ts = synth.film_batch()
+    plans = [hsim.Plan(f) for f in films]
+    b = hsim.Batch(plans, seed=3, precision=hsim.FP32, layout=hsim.LAYOUT_SITE).bind(1, 1)
+    assert b.info.total_sites == sum(f.n for f in films)
+    b.init_spins(hsim.INIT_COLD_Z)
+    b.run(Ts[:, None], 0.0, launch=hsim.LAUNCH_GRAPH)
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    h = b.history.cpu().numpy()
+    for r in (0, 77, 255):
+        f = films[r]
+        got = b.spins_user(r).cpu().numpy()
+        start = np.tile([0.0, 0.0, 1.0], (f.n, 1))
+        nd, err = _one_mcs_agreement(f, start, Ts[r], 0.0, 3, r, got)
+        assert nd <= 3 and err <= 2e-6, (r, nd, err)
+        e = oracle.energy(f, 0.0, got)
+        assert abs(h[r, 0, 0, 0] - e["E"]) <= 1e-5 * e["scale"]
+
+
+# ------------------------------------------------------------------ C4
+def test_c4_energy_gradients_full_size():
+    """SC 32^3 with per-bond J ~ N(1, 0.1), per-site K and axes, B = 0.5 z;
+    a batch of 1024 configurations: FP32 energies of sampled configurations
+    and the weighted gradients against the FP64 oracle; FP64 gradients against
+    FP64 central differences of the device's own energy."""
+    from paper_1803_07030_amd.energy import heisenberg_energy
+    lat = synth.gradient_lattice(L=32, seed=4)
+    plan = hsim.Plan(lat)
+    Bn = 1024
+    S = synth.random_spins(44, lat.n, batch=Bn).astype(np.float32)
+    _, _, Jb = lat.bonds()
+    dev = "cuda"
+    St = torch.tensor(S.transpose(0, 2, 1).copy(), device=dev, requires_grad=True)
+    Jt = torch.tensor(Jb, dtype=torch.float32, device=dev, requires_grad=True)
+    kt = torch.tensor(lat.k, dtype=torch.float32, device=dev, requires_grad=True)
+    Bt = torch.tensor(0.5, dtype=torch.float64, device=dev, requires_grad=True)
+    ax = torch.tensor(lat.axis.T.copy(), dtype=torch.float32, device=dev)
+    E = heisenberg_energy(St, Jt, kt, Bt, plan, ax)
+    w = torch.zeros(Bn, dtype=torch.float64, device=dev)
+    picked = [0, 5, 100, 511, 512, 900, 1000, 1023]
+    w[picked] = torch.linspace(0.5, 1.5, len(picked), dtype=torch.float64, device=dev)
+    (E * w).sum().backward()
+    Sd = S.astype(np.float64)
+    Jf = Jb.astype(np.float32).astype(np.float64)
+    lat32 = lat.with_bond_J(Jf)
+    lat32.k = lat.k.astype(np.float32).astype(np.float64)
+    lat32.axis = lat.axis.astype(np.float32).astype(np.float64)
+    gJ_ref = np.zeros(Jb.size)
+    gk_ref = np.zeros(lat.n)
+    gB_ref = 0.0
+    for i, c in enumerate(picked):
+        e = oracle.energy(lat32, 0.5, Sd[c])
+        assert abs(E[c].item() - e["E"]) <= 2e-6 * e["scale"]
+        gS, gJ, gk, gB = oracle.energy_grad(lat32, 0.5, Sd[c], g=float(w[c]))
+        gs = St.grad[c].detach().cpu().numpy().T
+        assert np.max(np.abs(gs - gS)) <= 2e-5 * max(1.0, float(w[c]))
+        gJ_ref += gJ
+        gk_ref += gk
+        gB_ref += gB
+    assert np.max(np.abs(Jt.grad.cpu().numpy() - gJ_ref)) <= 1e-4
+    assert np.max(np.abs(kt.grad.cpu().numpy() - gk_ref)) <= 1e-4
+    assert abs(Bt.grad.item() - gB_ref) <= 1e-7 * lat.n * len(picked)
+    unpicked = np.setdiff1d(np.arange(Bn), picked)[:4]
+    assert float(St.grad[unpicked].abs().max()) == 0.0
+    # FP64 mode: gradients vs central differences of the device energy
+    S64 = torch.tensor(Sd[:4].transpose(0, 2, 1).copy(), device=dev)
+    J64 = torch.tensor(Jb, device=dev, requires_grad=True)
+    k64 = torch.tensor(lat.k, device=dev, requires_grad=True)
+    ax64 = torch.tensor(lat.axis.T.copy(), device=dev)
+    B64 = torch.tensor(0.5, dtype=torch.float64, device=dev)
+    E64 = heisenberg_energy(S64, J64, k64, B64, plan, ax64)
+    E64.sum().backward()
+    h = 0.25                           # E is linear in J: any step is exact up to rounding
+    for bidx in (0, 4097, 98303):
+        Jp, Jm = J64.detach().clone(), J64.detach().clone()
+        Jp[bidx] += h
+        Jm[bidx] -= h
+        fd = (heisenberg_energy(S64, Jp, k64.detach(), B64, plan, ax64).sum()
+              - heisenberg_energy(S64, Jm, k64.detach(), B64, plan, ax64).sum()) / (2 * h)
+        assert abs(fd.item() - J64.grad[bidx].item()) <= 1e-9 * max(1.0, abs(fd.item()))
+
+
+def test_fluctuation_estimator_isolated_spins():
+    """d<M_z>/dB = beta Var(M_z) from the FP32 chain and the estimator kernel,
+    against the closed form beta N (1/x^2 - 1/sinh^2 x)."""
+    from paper_1803_07030_amd.energy import fluct_estimate
+    N, R, M, x = 4096, 16, 800, 2.0
+    lat = synth.isolated(N)
+    plan = hsim.Plan(lat)
+    b = hsim.Batch([plan] * R, seed=8, precision=hsim.FP32, layout=hsim.LAYOUT_REPLICA).bind(1, M)
+    b.init_spins(hsim.INIT_RANDOM)
+    b.run(np.ones((R, 1)), x)
+    torch.cuda.synchronize()
+    h = b.history[:, 0, 50:, :]                        # drop the start
+    Mz = h[..., 3].reshape(-1).contiguous()
+    dEdB = -Mz                                         # dE/dB = -sum_i S_i.n_i
+    out = fluct_estimate(1.0, Mz, dEdB).cpu().numpy()
+    exact = N * langevin_var(x)
+    assert abs(out[0] - exact) <= 0.08 * exact, (out, exact)
