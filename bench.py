@@ -5,14 +5,17 @@ Workload (one "step" = one whole run of the hot path): periodic simple-cubic
 K = 0.1 along z, B = 0; 64 replicas at temperatures 0.1 -> 3.0 (one per
 replica), cold start, seed 1, 10^4 MCS per replica, single-precision spins and
 fields with a double-precision history of (E, M, accepted) after every MCS;
-all replicas in one persistent launch (replica-lane layout).
+all replicas in one batch (replica-lane layout), one launch per colour phase.
 
 Printed: one JSON line with the throughput (attempted spin updates per second,
 inputs resident in HBM), the per-replica plain-launch rate on a bounded sample,
-the roofline of the dominant kernel (HBM, algorithmic bytes per update) and
-the CPU oracle's rate on a bounded sample.
+the roofline of the dominant kernel (one colour phase of all replicas: HBM,
+algorithmic bytes per update over its average launch duration, timed with HIP
+events on the stream it runs on, every n-th MCS of the timed region) and the
+CPU oracle's rate on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,7 +37,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mcs", type=int, default=MCS, help="MCS per replica per step")
-    ap.add_argument("--launch", default="persistent", choices=["persistent", "graph", "plain", "auto"])
+    ap.add_argument("--launch", default="plain", choices=["persistent", "graph", "plain", "auto"])
+    ap.add_argument("--time-every", type=int, default=10,
+                    help="plain launch: time every n-th MCS's colour-phase launches with HIP events")
     ap.add_argument("--plain-mcs", type=int, default=8, help="MCS per replica of the plain-launch sample")
     ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS per thread of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -55,6 +60,35 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
+
+
+# Sources of the dominant kernel; the committed byte counts in
+# profiles/rep_phase_traffic.json are used only while these hash the same.
+KERNEL_SOURCES = ["paper_1803_07030_amd/csrc/rep_kernels.hip", "paper_1803_07030_amd/csrc/update.h",
+                  "paper_1803_07030_amd/csrc/hsim_dev.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rep_phase_traffic.json")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per colour-phase launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None if the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t
 
 
 def workload():
@@ -95,6 +129,7 @@ def main():
         batch = hsim.Batch([plan] * R, seed=SEED, precision=hsim.FP32,
                            layout=hsim.LAYOUT_REPLICA).bind(1, args.mcs)
         Tm = T[:, None]
+        timed_phases = args.launch == "plain" and args.time_every > 0
 
         def one_step():
             batch.init_spins(hsim.INIT_COLD_Z)
@@ -110,21 +145,37 @@ def main():
         stream.synchronize()
         assert batch.status() == 0
         torch.cuda.synchronize()
+        if timed_phases:
+            batch.phase_times()                  # drop anything recorded before
+            batch.time_phases(args.time_every)
         t0 = time.perf_counter()
         evs = [one_step() for _ in range(args.steps)]
         stream.synchronize()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         assert batch.status() == 0
-        kern_ms = [a.elapsed_time(b) for a, b in evs]
+        step_ms = [a.elapsed_time(b) for a, b in evs]
+        if timed_phases:
+            ph_ms, ph_n, ph_upd = batch.phase_times()
+            batch.time_phases(0)
         hist = batch.history.cpu().numpy()
     n_upd_step = R * lat.n * args.mcs
     value = n_upd_step * args.steps / wall
     acc = float(hist[..., 4].mean() / lat.n)
     zbar = lat.mean_degree
     balg = b_alg_replica_lane(zbar, acc, 64)
-    avg_launch_s = float(np.mean(kern_ms)) / 1e3
-    achieved = balg * n_upd_step / avg_launch_s / 1e9
+    if timed_phases:
+        # dominant kernel: one colour phase of all replicas (k_rep_phase)
+        kernel = "k_rep_phase"
+        launch_ms = ph_ms / ph_n
+        upd_per_launch = ph_upd / ph_n
+    else:
+        # persistent: one launch per step; graph: the step's launches together
+        kernel = "k_rep_persistent" if args.launch == "persistent" else "step"
+        launch_ms = float(np.mean(step_ms))
+        upd_per_launch = n_upd_step
+    achieved = balg * upd_per_launch / (launch_ms / 1e3) / 1e9
+    tr = measured_traffic() if kernel == "k_rep_phase" else None
     out = {
         "metric": METRIC, "value": value, "unit": "spin updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
@@ -137,9 +188,14 @@ def main():
                    "updates_per_step": n_upd_step, "launch": args.launch},
         "acceptance": acc,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_update": balg, "kernel_ms": float(np.mean(kern_ms))},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if tr is None else tr["bytes_per_launch"],
+                     "kernel": kernel, "launch_ms": launch_ms,
+                     "updates_per_launch": upd_per_launch, "bytes_per_update": balg,
+                     "timed_launches": ph_n if timed_phases else args.steps},
     }
+    if tr is not None:
+        out["roofline"]["traffic_vs_algorithmic"] = tr["bytes_per_launch"] / (balg * upd_per_launch)
     if not args.no_plain:
         out["plain_launch"] = plain_launch(lat, T, args.plain_mcs, stream)
         out["vs_plain_launch"] = value / out["plain_launch"]["value"]

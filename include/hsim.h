@@ -163,6 +163,16 @@ hsim_status hsim_batch_init_spins(hsim_batch b, int32_t mode, const double *host
 hsim_status hsim_batch_run(hsim_batch b, int32_t first_step, int32_t n_steps, const double *T,
                            const double *B, int32_t recompute_every, hsim_launch launch,
                            uint32_t run_flags, uint32_t *d_trace, void *stream);
+/* Launch timing of the colour phases (the dominant kernels).  With every > 0,
+ * plain-launch runs record a HIP event pair around each colour-phase launch
+ * of every `every`-th MCS, on the run's stream; 0 switches it off.  GRAPH
+ * and AUTO runs of a batch with timing on are enqueued as plain launches. */
+hsim_status hsim_batch_time_phases(hsim_batch b, int32_t every);
+/* Waits for the recorded events and returns their total: summed launch
+ * duration in ms, number of timed launches, and attempted spin updates those
+ * launches processed; then clears the record. */
+hsim_status hsim_batch_phase_times(hsim_batch b, double *total_ms, int64_t *launches,
+                                   int64_t *updates);
 /* Replica rep's spins in user order, double [n][3], into device memory. */
 hsim_status hsim_batch_spins_to_user(hsim_batch b, int32_t rep, double *d_out, void *stream);
 /* Device status word after the stream has been synchronised: 0, or

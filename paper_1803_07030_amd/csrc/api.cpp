@@ -24,6 +24,8 @@ void batch_run_impl(hsim_batch, int32_t, int32_t, const double *, const double *
 void batch_to_user_impl(hsim_batch, int32_t, double *, hipStream_t);
 int32_t batch_status_impl(hsim_batch);
 void autotune_impl(hsim_batch, const char *, int32_t, hipStream_t);
+void batch_time_phases_impl(hsim_batch, int32_t);
+void batch_phase_times_impl(hsim_batch, double *, int64_t *, int64_t *);
 
 namespace {
 
@@ -154,6 +156,16 @@ hsim_status hsim_batch_run(hsim_batch b, int32_t first_step, int32_t n_steps, co
         batch_run_impl(b, first_step, n_steps, T, B, recompute_every, launch, run_flags, d_trace,
                        S(stream));
     });
+}
+
+hsim_status hsim_batch_time_phases(hsim_batch b, int32_t every)
+{
+    return guarded([&] { batch_time_phases_impl(b, every); });
+}
+
+hsim_status hsim_batch_phase_times(hsim_batch b, double *total_ms, int64_t *launches, int64_t *updates)
+{
+    return guarded([&] { batch_phase_times_impl(b, total_ms, launches, updates); });
 }
 
 hsim_status hsim_batch_spins_to_user(hsim_batch b, int32_t rep, double *d_out, void *stream)

@@ -41,6 +41,7 @@ int device_cus()
 
 hsim_batch_s::~hsim_batch_s()
 {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (stage_done) {
         (void)hipEventSynchronize(stage_done);
         (void)hipEventDestroy(stage_done);
@@ -330,7 +331,49 @@ void batch_init_impl(hsim_batch b, int32_t mode, const double *host, hipStream_t
     if (given.p) hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
 }
 
+int64_t hsim_batch_s::phase_updates(int colour) const
+{
+    int64_t u = 0;
+    if (layout == HSIM_LAYOUT_REPLICA) {
+        const hsim_plan P = plans[0];
+        if (colour < P->ncol) u = (int64_t)(P->cls_off[colour + 1] - P->cls_off[colour]) * R;
+    } else {
+        for (auto P : plans)
+            if (colour < P->ncol) u += P->cls_off[colour + 1] - P->cls_off[colour];
+    }
+    return u;
+}
+
 namespace {
+
+// Event pair around one colour-phase launch when this MCS is sampled.
+struct PhaseTimer {
+    hsim_batch b;
+    hipStream_t st;
+    hipEvent_t e1 = nullptr;
+    int64_t units = 0;
+    PhaseTimer(hsim_batch b_, hipStream_t st_, bool on, int colour) : b(b_), st(st_)
+    {
+        if (!on) return;
+        if (b->ev_used + 2 > b->ev_pool.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                hip_check(hipEventCreate(&e), "hipEventCreate");
+                b->ev_pool.push_back(e);
+            }
+        }
+        hipEvent_t e0 = b->ev_pool[b->ev_used++];
+        e1 = b->ev_pool[b->ev_used++];
+        units = b->phase_updates(colour);
+        hip_check(hipEventRecord(e0, st), "hipEventRecord");
+    }
+    ~PhaseTimer() noexcept(false)
+    {
+        if (!e1) return;
+        hip_check(hipEventRecord(e1, st), "hipEventRecord");
+        b->ev_units.push_back(units);
+    }
+};
 
 // Site layout: MCS t_off = 0..count-1 of a launch sequence starting at
 // ctl->g (efull, colour phases, per-MCS reduction), then ctl->g moves on.
@@ -345,11 +388,14 @@ void enqueue_site_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F e
             hip_check(hsim::launch_site_efull(st, b->f64, b->kmode, b->fmode, reps, tiles,
                                               (int)b->tiles.size(), t, ra),
                       "efull launch");
-        for (int c = 0; c < b->ncol_max; ++c)
+        const bool timed = b->time_every > 0 && t % b->time_every == 0;
+        for (int c = 0; c < b->ncol_max; ++c) {
+            PhaseTimer pt(b, st, timed, c);
             hip_check(hsim::launch_site_phase(st, b->f64, b->kmode, b->fmode, ra.trace != nullptr,
                                               b->ellw, reps, tiles, b->tile_off[c],
                                               b->tile_off[c + 1] - b->tile_off[c], t, ra),
                       "phase launch");
+        }
         hip_check(hsim::launch_site_reduce(st, (const int32_t *)b->d_rep_tiles.p, b->ncol_max, t, ra),
                   "reduce launch");
     }
@@ -368,10 +414,13 @@ void enqueue_rep_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F ef
         if (efull_mask(t))
             hip_check(hsim::launch_rep_efull(st, b->kmode, b->fmode, b->la, b->rep_ntiles, t, ra),
                       "efull launch");
-        for (int c = 0; c < b->la.ncol; ++c)
+        const bool timed = b->time_every > 0 && t % b->time_every == 0;
+        for (int c = 0; c < b->la.ncol; ++c) {
+            PhaseTimer pt(b, st, timed, c);
             hip_check(hsim::launch_rep_phase(st, b->kmode, b->fmode, c, t, c == 0 && t > 0, b->la,
                                              b->rep_ntiles, ra),
                       "phase launch");
+        }
     }
     if (count > 0)
         hip_check(hsim::launch_rep_reduce(st, b->la, b->rep_ntiles, count - 1, count, ra),
@@ -462,7 +511,10 @@ bool run_persistent(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st)
     const int groups = b->Rp / (b->Rp % 64 == 0 ? 64 : 32);
     int grid = b->persistent_grid > 0 ? b->persistent_grid : bpc * cus;
     grid = std::min(grid, bpc * cus);   // every block must be resident at once
-    grid = std::min(grid, std::max(1, b->rep_ntiles * groups));
+    int max_phase_tiles = 1;            // more blocks than tiles of a phase would only wait
+    for (int c = 0; c < b->la.ncol; ++c)
+        max_phase_tiles = std::max(max_phase_tiles, b->la.tile_off[c + 1] - b->la.tile_off[c]);
+    grid = std::min(grid, max_phase_tiles * groups);
     grid = std::min(grid, hsim::kMaxPersistentBlocks);
     // barrier flags follow the tile records and chunk sums
     const size_t rec = ((size_t)2 * b->rep_ntiles * hsim::kRecFields * b->Rp + (size_t)2 * 64 * 6 * b->Rp) * 8;
@@ -535,7 +587,7 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
             throw Error(HSIM_E_UNSUPPORTED, "persistent launch cannot be made co-resident");
         return;
     }
-    if (mode == HSIM_LAUNCH_GRAPH) run_graph(b, ra, st);
+    if (mode == HSIM_LAUNCH_GRAPH && b->time_every == 0) run_graph(b, ra, st);
     else run_plain(b, ra, st, 0, n_mcs);
 }
 
@@ -685,4 +737,32 @@ void autotune_impl(hsim_batch b, const char *cache_path, int32_t trial_mcs, hipS
         std::ofstream out(cache_path, std::ios::app);
         out << key << " " << win.mode << " " << win.grid << "\n";
     }
+}
+
+// ------------------------------------------------------------ launch timing
+void batch_time_phases_impl(hsim_batch b, int32_t every)
+{
+    if (!b || every < 0) throw Error(HSIM_E_ARG, "time_phases: bad argument");
+    b->time_every = every;
+}
+
+void batch_phase_times_impl(hsim_batch b, double *total_ms, int64_t *launches, int64_t *updates)
+{
+    if (!b) throw Error(HSIM_E_ARG, "phase_times: NULL batch");
+    double sum = 0.0;
+    int64_t upd = 0;
+    const size_t pairs = b->ev_units.size();
+    for (size_t k = 0; k < pairs; ++k) {
+        hip_check(hipEventSynchronize(b->ev_pool[2 * k + 1]), "hipEventSynchronize");
+        float ms = 0.0f;
+        hip_check(hipEventElapsedTime(&ms, b->ev_pool[2 * k], b->ev_pool[2 * k + 1]),
+                  "hipEventElapsedTime");
+        sum += ms;
+        upd += b->ev_units[k];
+    }
+    if (total_ms) *total_ms = sum;
+    if (launches) *launches = (int64_t)pairs;
+    if (updates) *updates = upd;
+    b->ev_units.clear();
+    b->ev_used = 0;
 }

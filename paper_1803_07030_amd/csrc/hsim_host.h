@@ -141,6 +141,13 @@ struct hsim_batch_s {
     // tuning
     int tuned_launch = -1;
     int persistent_grid = 0;
+    // sampled launch timing of the colour phases: event pairs and the updates
+    // each timed launch processed
+    int time_every = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<int64_t> ev_units;
+    int64_t phase_updates(int colour) const;
 
     ~hsim_batch_s();
     void upload_tables();

@@ -588,8 +588,27 @@ __device__ __forceinline__ void grid_barrier(Ctl *ctl, uint32_t *flags, uint32_t
         __hip_atomic_store(&flags[blockIdx.x * 32], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (blockIdx.x == 0) {
-        for (int j = threadIdx.x; j < (int)gridDim.x; j += blockDim.x)
-            barrier_wait(&flags[j * 32], epoch, ctl, cap);
+        // each thread watches up to kFlagsPerThread flags, all loaded in one
+        // round trip per poll
+        constexpr int kFlagsPerThread = kMaxPersistentBlocks / kRepThreads;
+        uint32_t n = 0;
+        for (;;) {
+            bool all = true;
+#pragma unroll
+            for (int u = 0; u < kFlagsPerThread; ++u) {
+                const int j = threadIdx.x + u * kRepThreads;
+                if (j < (int)gridDim.x &&
+                    __hip_atomic_load(&flags[j * 32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch)
+                    all = false;
+            }
+            if (all) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++n > cap ||
+                (__hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2u)) {
+                atomicOr(&ctl->status, 2u);
+                break;
+            }
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");

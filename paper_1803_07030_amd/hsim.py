@@ -64,6 +64,8 @@ _SIGNATURES = {
     "hsim_batch_spins_to_user": [_vp, _i32, _vp, _vp],
     "hsim_batch_status": [_vp, _vp],
     "hsim_autotune": [_vp, ctypes.c_char_p, _i32, _vp],
+    "hsim_batch_time_phases": [_vp, _i32],
+    "hsim_batch_phase_times": [_vp, _vp, _vp, _vp],
     "hsim_energy_forward": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp],
     "hsim_energy_backward": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp,
                              _vp, _vp],
@@ -203,6 +205,16 @@ def hsim_autotune(batch, cache_path=None, trial_mcs=20):
     _check(lib().hsim_autotune(batch, cp, trial_mcs, _stream()))
 
 
+def hsim_batch_time_phases(batch, every):
+    _check(lib().hsim_batch_time_phases(batch, every))
+
+
+def hsim_batch_phase_times(batch):
+    ms, n, u = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().hsim_batch_phase_times(batch, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(u)))
+    return ms.value, n.value, u.value
+
+
 def hsim_batch_destroy(batch):
     lib().hsim_batch_destroy(batch)
 
@@ -314,6 +326,13 @@ class Batch:
 
     def autotune(self, cache_path=None, trial_mcs=20):
         hsim_autotune(self.handle, cache_path, trial_mcs)
+
+    def time_phases(self, every):
+        hsim_batch_time_phases(self.handle, every)
+
+    def phase_times(self):
+        """(total ms, timed launches, updates of those launches)."""
+        return hsim_batch_phase_times(self.handle)
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -293,3 +293,37 @@ def test_fluct_estimate_formula():
     cov = np.mean((o - o.mean()) * (d - d.mean()))
     assert abs(out[1] - cov) <= 1e-14
     assert abs(out[0] - (dd.mean() - 0.7 * cov)) <= 1e-14
+
+
+@pytest.mark.parametrize("layout", [hsim.LAYOUT_SITE, hsim.LAYOUT_REPLICA])
+def test_phase_timing_counts_and_leaves_results_unchanged(layout):
+    """Sampled timing of the colour-phase launches (every 3rd MCS of a plain
+    run, graph requests fall back to plain) counts one launch per colour of
+    each sampled MCS and that colour's updates, and changes no result."""
+    lat = synth.sc_periodic(10)
+    plan = hsim.Plan(lat)
+    ncol = int(plan.info.n_colours)
+    sizes = list(plan.info.colour_size)[:ncol]
+    R, M, every = 20, 11, 3
+    T = np.linspace(0.3, 2.5, R)[:, None]
+    res = {}
+    for timed in (False, True):
+        b = hsim.Batch([plan] * R, seed=5, precision=hsim.FP32, layout=layout).bind(1, M)
+        b.init_spins(hsim.INIT_RANDOM)
+        if timed:
+            b.time_phases(every)
+        b.run(T, 0.2, recompute_every=4, launch=hsim.LAUNCH_GRAPH)
+        torch.cuda.synchronize()
+        assert b.status() == 0
+        ms, n, upd = b.phase_times()
+        sampled = len(range(0, M, every))
+        if timed:
+            assert n == sampled * ncol
+            assert upd == sampled * R * sum(sizes)
+            assert ms > 0.0
+            assert b.phase_times() == (0.0, 0, 0)          # read-out clears
+        else:
+            assert (ms, n, upd) == (0.0, 0, 0)
+        res[timed] = (np.stack([_fp32_spins(b, r) for r in range(R)]), b.history.cpu().numpy())
+    assert np.array_equal(res[False][0], res[True][0])
+    assert np.array_equal(res[False][1], res[True][1])
