@@ -107,6 +107,9 @@ hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
                 b->la.tile_off[c + 1] = b->la.tile_off[c] + (sz + hsim::kRepTile - 1) / hsim::kRepTile;
             }
             b->rep_ntiles = b->la.tile_off[P->ncol];
+            // records of up to 64 MCS, about 256 MiB at most (2 at least)
+            const size_t per_mcs = (size_t)b->rep_ntiles * hsim::kRecFields * b->Rp * 8;
+            b->rec_win = (int32_t)std::max<size_t>(2, std::min<size_t>(64, (256u << 20) / std::max<size_t>(per_mcs, 1)));
         } else {
             b->spin_off.resize(R);
             int64_t off = 0;
@@ -157,7 +160,7 @@ void batch_sizes_impl(hsim_batch b, int32_t S, int32_t M, size_t *ws, size_t *sp
     size_t part = 0;
     if (b->layout == HSIM_LAYOUT_SITE) part = b->tiles.size() * hsim::kRecSite * 8;
     else if (b->layout == HSIM_LAYOUT_REPLICA)
-        part = ((size_t)2 * b->rep_ntiles * hsim::kRecFields * b->Rp + (size_t)2 * 64 * 6 * b->Rp) * 8 +
+        part = b->rep_rec_bytes() +
                (size_t)hsim::kMaxPersistentBlocks * 128;   // barrier flags, one 128-byte line each
     off += align_up(std::max<size_t>(part, 8));
     if (ws) *ws = off;
@@ -288,6 +291,11 @@ hsim::RunArgs hsim_batch_s::run_args(uint32_t g0, int n_mcs, int P, uint32_t *tr
     a.bfield = (const double *)(ws + off_bfield);
     a.ecarry = (double *)(ws + off_ecarry);
     a.partials = (double *)(ws + off_part);
+    if (layout == HSIM_LAYOUT_REPLICA) {
+        a.chunks = a.partials + (size_t)rec_win * rep_ntiles * hsim::kRecFields * Rp;
+        a.carry = a.chunks + (size_t)rec_win * hsim::kChunks * 6 * Rp;
+    }
+    a.rec_win = rec_win;
     a.history = history;
     a.trace = trace;
     a.seed = seed;
@@ -403,13 +411,15 @@ void enqueue_site_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F e
 }
 
 // Replica layout: MCS t_off = 0..count-1 of a launch sequence starting at
-// ctl->g.  The history of each MCS is reduced inside the next MCS's colour-0
-// launch; the last one by a closing reduction that also moves ctl->g on.
-// efull_mask(t): whether MCS t may need the energy recompute.
+// ctl->g.  Records of MCS t go to slot t % rec_win; each full window (and the
+// last, partial one) is reduced by its own two launches, the last of which
+// also moves ctl->g on.  efull_mask(t): whether MCS t may need the energy
+// recompute.
 template <typename F>
 void enqueue_rep_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F efull_mask,
                           hipStream_t st)
 {
+    const int W = b->rec_win;
     for (int t = 0; t < count; ++t) {
         if (efull_mask(t))
             hip_check(hsim::launch_rep_efull(st, b->kmode, b->fmode, b->la, b->rep_ntiles, t, ra),
@@ -417,14 +427,16 @@ void enqueue_rep_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F ef
         const bool timed = b->time_every > 0 && t % b->time_every == 0;
         for (int c = 0; c < b->la.ncol; ++c) {
             PhaseTimer pt(b, st, timed, c);
-            hip_check(hsim::launch_rep_phase(st, b->kmode, b->fmode, c, t, c == 0 && t > 0, b->la,
-                                             b->rep_ntiles, ra),
+            hip_check(hsim::launch_rep_phase(st, b->kmode, b->fmode, c, t, b->la, b->rep_ntiles, ra),
                       "phase launch");
         }
+        if ((t + 1) % W == 0 || t == count - 1) {
+            const int first = t - t % W;
+            hip_check(hsim::launch_rep_reduce(st, b->la, b->rep_ntiles, first, t - first + 1,
+                                              t == count - 1 ? count : 0, ra),
+                      "reduce launch");
+        }
     }
-    if (count > 0)
-        hip_check(hsim::launch_rep_reduce(st, b->la, b->rep_ntiles, count - 1, count, ra),
-                  "reduce launch");
 }
 
 bool due(uint32_t g, int M, int P)
@@ -516,9 +528,8 @@ bool run_persistent(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st)
         max_phase_tiles = std::max(max_phase_tiles, b->la.tile_off[c + 1] - b->la.tile_off[c]);
     grid = std::min(grid, max_phase_tiles * groups);
     grid = std::min(grid, hsim::kMaxPersistentBlocks);
-    // barrier flags follow the tile records and chunk sums
-    const size_t rec = ((size_t)2 * b->rep_ntiles * hsim::kRecFields * b->Rp + (size_t)2 * 64 * 6 * b->Rp) * 8;
-    auto *flags = (uint32_t *)(b->ws + b->off_part + rec);
+    // barrier flags follow the record window
+    auto *flags = (uint32_t *)(b->ws + b->off_part + b->rep_rec_bytes());
     hip_check(hsim::launch_rep_persistent(st, b->kmode, b->fmode, b->la, b->rep_ntiles, grid, ra,
                                           flags, 1u << 24),
               "persistent launch");

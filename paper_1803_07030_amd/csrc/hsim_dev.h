@@ -22,6 +22,7 @@ constexpr int kMaxPersistentBlocks = 4096;   // barrier flags reserved in the wo
 constexpr int kRepTile = kRepWaves * kRepSitesPerWave;   // sites per replica-lane tile
 constexpr int kRecSite = 8;         // doubles per site-lane partial record
 constexpr int kRecFields = 6;       // dE, Mx, My, Mz, n_acc, E_full
+constexpr int kChunks = 64;         // replica layout: chunks of the per-MCS record sum
 
 // How the anisotropy and field-direction terms are read.
 enum KMode : int { K_NONE = 0, K_UNIFORM = 1, K_SITE = 2 };
@@ -66,7 +67,9 @@ struct RunArgs {
     const double *beta;   // [R][S_hist]
     const double *bfield; // [R][S_hist]
     double *ecarry;       // [R]
-    double *partials;     // records
+    double *partials;     // records (replica layout: [rec_win][tiles][6][Rp])
+    double *chunks;       // replica layout: chunk sums [rec_win][64][6][Rp]
+    double *carry;        // replica layout: per-MCS totals [rec_win][6][Rp]
     double *history;      // [R][S_hist][M][5]
     uint32_t *trace;      // NULL or [R][n_mcs_run][words]
     uint64_t seed;
@@ -77,6 +80,7 @@ struct RunArgs {
     int32_t n_mcs_run;    // MCS in this run
     int32_t trace_words;  // words per replica per MCS
     int32_t R;
+    int32_t rec_win;      // replica layout: MCS per record window (>= 2)
 };
 
 struct RepLaneArgs {
@@ -123,11 +127,13 @@ hipError_t launch_block_sweep(hipStream_t st, bool f64, int kmode, int fmode, bo
 int block_sweep_max_lds(bool f64);
 
 hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour, int t_off,
-                            bool reduce_prev, const RepLaneArgs &a, int ntiles, const RunArgs &ra);
+                            const RepLaneArgs &a, int ntiles, const RunArgs &ra);
 hipError_t launch_rep_efull(hipStream_t st, int kmode, int fmode, const RepLaneArgs &a,
                             int ntiles, int t_off, const RunArgs &ra);
-hipError_t launch_rep_reduce(hipStream_t st, const RepLaneArgs &a, int ntiles, int t_off,
-                             int advance, const RunArgs &ra);
+// Reduction of the record window holding MCS t_first .. t_first + count - 1
+// of the current sequence (count <= rec_win); advance > 0 closes the sequence.
+hipError_t launch_rep_reduce(hipStream_t st, const RepLaneArgs &a, int ntiles, int t_first,
+                             int count, int advance, const RunArgs &ra);
 hipError_t launch_rep_persistent(hipStream_t st, int kmode, int fmode, const RepLaneArgs &a,
                                  int ntiles, int grid, const RunArgs &ra, uint32_t *flags,
                                  uint32_t spin_cap);

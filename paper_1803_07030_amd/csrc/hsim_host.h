@@ -122,6 +122,12 @@ struct hsim_batch_s {
     // replica layout
     int32_t Rp = 0;
     int32_t rep_ntiles = 0;
+    int32_t rec_win = 2;              // replica layout: MCS per record window
+    // replica layout: bytes of the record window, its chunk sums and totals
+    size_t rep_rec_bytes() const
+    {
+        return (size_t)rec_win * ((size_t)rep_ntiles * hsim::kRecFields + (size_t)hsim::kChunks * 6 + 6) * Rp * 8;
+    }
     hsim::RepLaneArgs la{};
 
     hsim::DevBuf d_reps, d_tiles, d_rep_tiles, d_rep_id;

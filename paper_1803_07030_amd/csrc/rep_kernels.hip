@@ -10,9 +10,12 @@
 // with its own temperature and field schedule.
 //
 // A tile is kRepTile consecutive sites of one colour class; wave w of the
-// tile's block takes kRepSitesPerWave of them, two at a time, in order.  Per-MCS history: every tile writes
-// one record per replica; records are summed in 64 fixed chunks of tiles, and
-// the chunks in order, the same way in every launch mode.
+// tile's block takes kRepSitesPerWave of them, two at a time, in order.
+// Per-MCS history: every tile writes one record per replica; records are
+// summed in 64 fixed chunks of tiles, and the chunks in order, the same way in
+// every launch mode.  Plain and graph launches keep the records of a window of
+// MCS and reduce the window in two launches of its own, so no sweep launch
+// waits on a reduction.
 #include "hsim_dev.h"
 #include "update.h"
 
@@ -20,7 +23,6 @@ namespace hsim {
 
 namespace {
 
-constexpr int kChunks = 64;
 // LDS of a replica-lane block: the tile sums ([kRepWaves][64][5]) and, reused,
 // the history reductions (chunk quarters [4][6][32], final eighths [8][6][32]).
 constexpr int kRedDoubles = kRepWaves * 64 * 5 > 8 * 6 * 32 ? kRepWaves * 64 * 5 : 8 * 6 * 32;
@@ -437,101 +439,95 @@ __device__ __forceinline__ void rep_chunk_sum(const RepLaneArgs &a, int ntiles, 
 }
 
 // Final sum over the chunks: eight fixed groups of eight chunks, each summed
-// in order by one thread, then the groups in order; then the history record
-// and the carried energy of those replicas.  buf: LDS, >= 8 * 6 * 32 doubles.
-__device__ __forceinline__ void rep_final(const RepLaneArgs &a, uint32_t g, const RunArgs &ra,
-                                          const double *chunk, double *buf)
+// in order by one thread, then the groups in order.  v (LDS or global,
+// [6][Rp]) receives the six totals of every replica.  buf: LDS, >= 8 * 6 * 32
+// doubles.
+__device__ __forceinline__ void rep_final_sums(const RepLaneArgs &a, const double *chunk,
+                                               double *buf, double *v)
 {
     constexpr int G = 32;
-    const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
-    const bool due = rep_recompute_due(m, ra.P);
     const size_t stride = (size_t)6 * a.Rp;
     for (int r0 = 0; r0 < a.Rp; r0 += G) {
         for (int e = threadIdx.x; e < 8 * 6 * G; e += blockDim.x) {
             const int s = e / (6 * G), q = (e / G) % 6, rr = r0 + e % G;
-            double v = 0.0;
+            double x = 0.0;
             if (rr < a.Rp) {
                 const double *p = chunk + (size_t)q * a.Rp + rr;   // chunk layout [k][6][Rp]
-                double x[8];
+                double y[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = p[(size_t)(8 * s + u) * stride];
+                for (int u = 0; u < 8; ++u) y[u] = p[(size_t)(8 * s + u) * stride];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v += x[u];
+                for (int u = 0; u < 8; ++u) x += y[u];
             }
-            buf[e] = v;
+            buf[e] = x;
         }
         __syncthreads();
-        for (int rl = threadIdx.x; rl < G; rl += blockDim.x) {
-            const int rr = r0 + rl;
-            if (rr >= a.R) continue;
-            double v[6];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                double t = 0.0;
-                for (int s = 0; s < 8; ++s) t += buf[(s * 6 + q) * G + rl];
-                v[q] = t;
-            }
-            const double E = (due ? v[5] : ra.ecarry[rr]) + v[0];
-            ra.ecarry[rr] = E;
-            double *h = ra.history + (((size_t)rr * ra.S_hist + s_abs) * ra.M + m) * 5;
-            h[0] = E;
-            h[1] = v[1];
-            h[2] = v[2];
-            h[3] = v[3];
-            h[4] = v[4];
+        for (int e = threadIdx.x; e < 6 * G; e += blockDim.x) {
+            const int q = e / G, rl = e % G, rr = r0 + rl;
+            if (rr >= a.Rp) continue;
+            double t = 0.0;
+            for (int s = 0; s < 8; ++s) t += buf[(s * 6 + q) * G + rl];
+            v[(size_t)q * a.Rp + rr] = t;
         }
         __syncthreads();
     }
+}
+
+// History record of MCS g from its six totals v ([6][Rp]) and the carried
+// energy: at a recompute the energy restarts from the full energy (field 5),
+// otherwise from the carried value; the energy change of g (field 0) is added.
+__device__ __forceinline__ void rep_write_history(const RepLaneArgs &a, uint32_t g,
+                                                  const RunArgs &ra, const double *v)
+{
+    const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
+    const bool due = rep_recompute_due(m, ra.P);
+    for (int rr = threadIdx.x; rr < a.R; rr += blockDim.x) {
+        const double E = (due ? v[5 * (size_t)a.Rp + rr] : ra.ecarry[rr]) + v[rr];
+        ra.ecarry[rr] = E;
+        double *h = ra.history + (((size_t)rr * ra.S_hist + s_abs) * ra.M + m) * 5;
+        h[0] = E;
+#pragma unroll
+        for (int q = 1; q < 5; ++q) h[q] = v[(size_t)q * a.Rp + rr];
+    }
+}
+
+// Both steps in one block (persistent kernel).  v: global [6][Rp].
+__device__ __forceinline__ void rep_final(const RepLaneArgs &a, uint32_t g, const RunArgs &ra,
+                                          const double *chunk, double *v, double *buf)
+{
+    rep_final_sums(a, chunk, buf, v);
+    rep_write_history(a, g, ra, v);
+    __syncthreads();
 }
 
 }  // namespace
 
 // MCS numbering of the per-phase launches: g = ctl->g + t_off, where ctl->g
 // is the first MCS of the current launch sequence (a captured graph replays
-// one such sequence) and t_off the launch's position in it.  Tile records of
-// MCS g go to parity g & 1 of the record buffer.
-__device__ __forceinline__ double *rep_part(const RunArgs &ra, const RepLaneArgs &a, int ntiles,
-                                            uint32_t g)
+// one such sequence) and t_off the launch's position in it.  The tile records
+// of MCS t_off go to slot t_off % rec_win of the record window; one reduction
+// per window of rec_win MCS sums them (the persistent kernel uses slots 0, 1).
+__device__ __forceinline__ double *rep_slot(const RunArgs &ra, const RepLaneArgs &a, int ntiles,
+                                            int slot)
 {
-    return ra.partials + (size_t)(g & 1u) * ntiles * kRecFields * a.Rp;
+    return ra.partials + (size_t)slot * ntiles * kRecFields * a.Rp;
 }
 
-// Sum the records of MCS g in 64 chunks (block k < 64 takes chunk k); the
-// last block to finish adds the chunks in order and writes the history of g.
-// Returns true in the block that wrote it.
-__device__ __forceinline__ bool rep_reduce_blocks(const RepLaneArgs &a, int ntiles, uint32_t g,
-                                                  const RunArgs &ra, double *buf)
+__device__ __forceinline__ double *rep_chunk_slot(const RunArgs &ra, const RepLaneArgs &a, int slot)
 {
-    __shared__ int last;
-    double *chunk = ra.partials + (size_t)2 * ntiles * kRecFields * a.Rp;
-    rep_chunk_sum(a, ntiles, blockIdx.x, rep_part(ra, a, ntiles, g), chunk, buf);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = (atomicAdd(&ra.ctl->pad[0], 1u) == kChunks - 1);
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    rep_final(a, g, ra, chunk, buf);
-    if (threadIdx.x == 0) ra.ctl->pad[0] = 0;
-    return true;
+    return ra.chunks + (size_t)slot * kChunks * 6 * a.Rp;
 }
 
-// Per-phase kernel: grid (tiles of the colour, replica groups).  With
-// reduce_prev (colour 0 of every MCS but the first of a sequence), the first
-// 64 blocks also reduce the previous MCS's records, off the critical path of
-// a separate launch.
+// Per-phase kernel: grid (tiles of the colour, replica groups).
 template <int KM, int FM, int W, int MAXD>
 __global__ __launch_bounds__(kRepThreads) void k_rep_phase(RepLaneArgs a, int colour, int t_off,
-                                                           int reduce_prev, int ntiles, RunArgs ra)
+                                                           int ntiles, RunArgs ra)
 {
     __shared__ double red[kRedDoubles];
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
-    if (reduce_prev && blockIdx.x < kChunks && blockIdx.y == 0)
-        rep_reduce_blocks(a, ntiles, g - 1, ra, red);
     const int nt = a.tile_off[colour + 1] - a.tile_off[colour];
-    if ((int)blockIdx.x < nt)   // extra blocks exist only to carry the folded reduction
-        rep_tile<KM, FM, W, MAXD>(a, colour, xcd_tile(blockIdx.x, nt), blockIdx.y, g, ra,
-                                  rep_part(ra, a, ntiles, g), red);
+    rep_tile<KM, FM, W, MAXD>(a, colour, xcd_tile(blockIdx.x, nt), blockIdx.y, g, ra,
+                              rep_slot(ra, a, ntiles, t_off % ra.rec_win), red);
 }
 
 template <int KM, int FM, int W>
@@ -541,18 +537,84 @@ __global__ __launch_bounds__(kRepThreads) void k_rep_efull(RepLaneArgs a, int t_
     __shared__ double red[kRedDoubles];
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     if (!rep_recompute_due(g % (uint32_t)ra.M, ra.P)) return;
-    rep_tile_energy<KM, FM, W>(a, blockIdx.x, blockIdx.y, g, ra, rep_part(ra, a, ntiles, g), red);
+    rep_tile_energy<KM, FM, W>(a, blockIdx.x, blockIdx.y, g, ra,
+                               rep_slot(ra, a, ntiles, t_off % ra.rec_win), red);
 }
 
-// End of a launch sequence: reduce its last MCS (ctl->g + t_off) and move
-// ctl->g on by `advance`.
-__global__ __launch_bounds__(1024) void k_rep_reduce(RepLaneArgs a, int ntiles, int t_off,
-                                                     int advance, RunArgs ra)
+// Reduction of a window of MCS t_first .. t_first + count - 1 of the current
+// sequence, step 1: chunk k (blockIdx.x) of MCS t_first + blockIdx.y.
+__global__ __launch_bounds__(1024) void k_rep_chunks(RepLaneArgs a, int ntiles, int t_first,
+                                                     RunArgs ra)
 {
+    __shared__ double buf[4 * 6 * 32];
+    const int slot = (t_first + (int)blockIdx.y) % ra.rec_win;
+    rep_chunk_sum(a, ntiles, blockIdx.x, rep_slot(ra, a, ntiles, slot), rep_chunk_slot(ra, a, slot),
+                  buf);
+}
+
+// Step 2: block j adds the chunks of MCS t_first + j and writes the fields
+// that need no carry (M, accepted); the last block to finish runs the energy
+// carry through the window in MCS order and, with advance > 0, moves ctl->g
+// on by advance (end of the sequence).
+__global__ __launch_bounds__(256) void k_rep_finals(RepLaneArgs a, int t_first, int count,
+                                                    int advance, RunArgs ra)
+{
+    constexpr int kStage = 16;          // MCS of the window staged in LDS at a time
     __shared__ double buf[8 * 6 * 32];
+    __shared__ double stage[kStage * 2 * 64];
+    __shared__ int last;
     const uint32_t g0 = ra.ctl->g;
-    if (rep_reduce_blocks(a, ntiles, g0 + (uint32_t)t_off, ra, buf) && threadIdx.x == 0)
-        ra.ctl->g = g0 + (uint32_t)advance;
+    {
+        const int t = t_first + (int)blockIdx.x;
+        const int slot = t % ra.rec_win;
+        double *v = ra.carry + (size_t)slot * 6 * a.Rp;
+        rep_final_sums(a, rep_chunk_slot(ra, a, slot), buf, v);
+        const uint32_t g = g0 + (uint32_t)t;
+        const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
+        for (int rr = threadIdx.x; rr < a.R; rr += blockDim.x) {
+            double *h = ra.history + (((size_t)rr * ra.S_hist + s_abs) * ra.M + m) * 5;
+#pragma unroll
+            for (int q = 1; q < 5; ++q) h[q] = v[(size_t)q * a.Rp + rr];
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(&ra.ctl->pad[1], 1u) == (uint32_t)count - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // carry: replicas 64 at a time, the window kStage MCS at a time through LDS
+    for (int r0 = 0; r0 < a.R; r0 += 64) {
+        const int nr = min(64, a.R - r0);
+        double E = threadIdx.x < nr ? ra.ecarry[r0 + threadIdx.x] : 0.0;
+        for (int j0 = 0; j0 < count; j0 += kStage) {
+            const int nj = min(kStage, count - j0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < nj * 2 * 64; e += blockDim.x) {
+                const int j = e / 128, f = (e / 64) % 2, rl = e % 64;
+                const int slot = (t_first + j0 + j) % ra.rec_win;
+                stage[e] = rl < nr ? ra.carry[((size_t)slot * 6 + (f ? 5 : 0)) * a.Rp + r0 + rl] : 0.0;
+            }
+            __syncthreads();
+            if ((int)threadIdx.x < nr) {
+                const int rr = r0 + threadIdx.x;
+                for (int j = 0; j < nj; ++j) {
+                    const uint32_t g = g0 + (uint32_t)(t_first + j0 + j);
+                    const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
+                    const double de = stage[(j * 2) * 64 + threadIdx.x];
+                    const double ef = stage[(j * 2 + 1) * 64 + threadIdx.x];
+                    E = (rep_recompute_due(m, ra.P) ? ef : E) + de;
+                    ra.history[(((size_t)rr * ra.S_hist + s_abs) * ra.M + m) * 5] = E;
+                }
+            }
+        }
+        if ((int)threadIdx.x < nr) ra.ecarry[r0 + threadIdx.x] = E;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ra.ctl->pad[1] = 0;
+        if (advance > 0) ra.ctl->g = g0 + (uint32_t)advance;
+    }
 }
 
 // ------------------------------------------------------------- persistent
@@ -639,16 +701,16 @@ struct XcdRange {
 
 template <int KM, int FM, int W, int MAXD>
 __global__ __launch_bounds__(kRepThreads) void k_rep_persistent(RepLaneArgs a, int ntiles,
-                                                                RunArgs ra, double *chunk,
-                                                                uint32_t *flags, uint32_t cap)
+                                                                RunArgs ra, uint32_t *flags,
+                                                                uint32_t cap)
 {
     __shared__ double red[kRedDoubles];   // tile sums, reused by the reductions
     uint32_t epoch = 0;
     const int groups = (a.Rp + W - 1) / W;
     for (int t = 0; t < ra.n_mcs_run; ++t) {
         const uint32_t g = ra.g0 + (uint32_t)t;
-        double *part = ra.partials + (size_t)(t & 1) * ntiles * kRecFields * a.Rp;
-        double *chk = chunk + (size_t)(t & 1) * kChunks * 6 * a.Rp;
+        double *part = rep_slot(ra, a, ntiles, t & 1);
+        double *chk = rep_chunk_slot(ra, a, t & 1);
         if (rep_recompute_due(g % (uint32_t)ra.M, ra.P)) {
             for (int u = blockIdx.x; u < ntiles * groups; u += gridDim.x)
                 rep_tile_energy<KM, FM, W>(a, u % ntiles, u / ntiles, g, ra, part, red);
@@ -663,14 +725,16 @@ __global__ __launch_bounds__(kRepThreads) void k_rep_persistent(RepLaneArgs a, i
             // the chunk sums of the previous MCS are complete once colour 0
             // of this one is: the last block adds them and writes its history
             if (c == 0 && t > 0 && blockIdx.x == gridDim.x - 1)
-                rep_final(a, g - 1, ra, chunk + (size_t)((t - 1) & 1) * kChunks * 6 * a.Rp, red);
+                rep_final(a, g - 1, ra, rep_chunk_slot(ra, a, (t - 1) & 1),
+                          ra.carry + (size_t)((t - 1) & 1) * 6 * a.Rp, red);
         }
         for (int k = blockIdx.x; k < kChunks; k += gridDim.x) rep_chunk_sum(a, ntiles, k, part, chk, red);
     }
     grid_barrier(ra.ctl, flags, epoch, cap);
     if (blockIdx.x == gridDim.x - 1 && ra.n_mcs_run > 0) {
         const int t = ra.n_mcs_run - 1;
-        rep_final(a, ra.g0 + (uint32_t)t, ra, chunk + (size_t)(t & 1) * kChunks * 6 * a.Rp, red);
+        rep_final(a, ra.g0 + (uint32_t)t, ra, rep_chunk_slot(ra, a, t & 1),
+                  ra.carry + (size_t)(t & 1) * 6 * a.Rp, red);
         if (threadIdx.x == 0) ra.ctl->g = ra.g0 + (uint32_t)ra.n_mcs_run;
     }
 }
@@ -753,17 +817,16 @@ static int lane_width(const RepLaneArgs &a) { return a.Rp % 64 == 0 ? 64 : 32; }
     } while (0)
 
 hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour, int t_off,
-                            bool reduce_prev, const RepLaneArgs &a, int ntiles, const RunArgs &ra)
+                            const RepLaneArgs &a, int ntiles, const RunArgs &ra)
 {
     const int nt = a.tile_off[colour + 1] - a.tile_off[colour];
     if (nt <= 0) return hipSuccess;
     const int Wd = lane_width(a);
-    // the folded reduction needs at least kChunks blocks
-    dim3 grid((unsigned)(reduce_prev ? std::max(nt, kChunks) : nt), (unsigned)(a.Rp / Wd));
+    dim3 grid((unsigned)nt, (unsigned)(a.Rp / Wd));
     dim3 blk(kRepThreads);
     HSIM_DISPATCH_KFW(kmode, fmode, Wd, HSIM_DISPATCH_D(a.ell_w, {
         hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD>), grid, blk, 0, st, a, colour, t_off,
-                           reduce_prev ? 1 : 0, ntiles, ra);
+                           ntiles, ra);
     }));
     return hipGetLastError();
 }
@@ -779,11 +842,16 @@ hipError_t launch_rep_efull(hipStream_t st, int kmode, int fmode, const RepLaneA
     return hipGetLastError();
 }
 
-hipError_t launch_rep_reduce(hipStream_t st, const RepLaneArgs &a, int ntiles, int t_off,
-                             int advance, const RunArgs &ra)
+hipError_t launch_rep_reduce(hipStream_t st, const RepLaneArgs &a, int ntiles, int t_first,
+                             int count, int advance, const RunArgs &ra)
 {
-    hipLaunchKernelGGL(k_rep_reduce, dim3(kChunks), dim3(1024), 0, st, a, ntiles, t_off, advance,
-                       ra);
+    if (count < 1 || count > ra.rec_win) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rep_chunks, dim3(kChunks, (unsigned)count), dim3(1024), 0, st, a, ntiles,
+                       t_first, ra);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rep_finals, dim3((unsigned)count), dim3(256), 0, st, a, t_first, count,
+                       advance, ra);
     return hipGetLastError();
 }
 
@@ -791,14 +859,13 @@ hipError_t launch_rep_persistent(hipStream_t st, int kmode, int fmode, const Rep
                                  int ntiles, int grid, const RunArgs &ra, uint32_t *flags,
                                  uint32_t spin_cap)
 {
-    if (grid > kMaxPersistentBlocks) return hipErrorInvalidValue;
-    double *chunk = ra.partials + (size_t)2 * ntiles * kRecFields * a.Rp;
+    if (grid > kMaxPersistentBlocks || ra.rec_win < 2) return hipErrorInvalidValue;
     hipError_t e = launch_fill_u32(st, flags, 0u, (int64_t)grid * 32);
     if (e != hipSuccess) return e;
     const int Wd = lane_width(a);
     HSIM_DISPATCH_KFW(kmode, fmode, Wd, HSIM_DISPATCH_D(a.ell_w, {
         hipLaunchKernelGGL((k_rep_persistent<KM, FM, W, MAXD>), dim3((unsigned)grid),
-                           dim3(kRepThreads), 0, st, a, ntiles, ra, chunk, flags, spin_cap);
+                           dim3(kRepThreads), 0, st, a, ntiles, ra, flags, spin_cap);
     }));
     return hipGetLastError();
 }

@@ -220,6 +220,7 @@ __global__ void k_ctl_set(Ctl *ctl, uint32_t g)
         ctl->g = g;
         ctl->bar_arrive = 0;
         ctl->pad[0] = 0;
+        ctl->pad[1] = 0;
     }
 }
 
