@@ -366,7 +366,8 @@ struct PhaseTimer {
         if (b->ev_used + 2 > b->ev_pool.size()) {
             for (int k = 0; k < 64; ++k) {
                 hipEvent_t e;
-                hip_check(hipEventCreate(&e), "hipEventCreate");
+                // timing only: no cache write-back/invalidate around the kernel
+                hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
                 b->ev_pool.push_back(e);
             }
         }

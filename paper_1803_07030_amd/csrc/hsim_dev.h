@@ -18,6 +18,14 @@ constexpr int kSiteBlock = 256;     // threads per block of the site-lane kernel
 constexpr int kRepWaves = HSIM_REP_WAVES;                    // waves per replica-lane block
 constexpr int kRepSitesPerWave = HSIM_REP_SITES_PER_WAVE;    // sites per wave of a tile
 constexpr int kRepThreads = kRepWaves * 64;
+#ifndef HSIM_REP_SITES_PER_STEP
+#define HSIM_REP_SITES_PER_STEP 2
+#endif
+// sites whose loads a wave issues together (64-lane groups); divides the
+// sites per wave
+constexpr int kRepSitesPerStep = HSIM_REP_SITES_PER_STEP;
+static_assert(kRepSitesPerWave % kRepSitesPerStep == 0 && kRepSitesPerWave % 2 == 0,
+              "sites per wave must be a multiple of the sites per step and even");
 constexpr int kMaxPersistentBlocks = 4096;   // barrier flags reserved in the workspace
 constexpr int kRepTile = kRepWaves * kRepSitesPerWave;   // sites per replica-lane tile
 constexpr int kRecSite = 8;         // doubles per site-lane partial record

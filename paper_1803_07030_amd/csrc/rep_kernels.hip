@@ -153,18 +153,23 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t rs, int32_t lane_b
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, lane_b, row_b, 0);
 }
 
+// kRepSitesPerStep sites of one 64-lane group at once, rows padded to MAXD:
+// all loads of the step are issued before any store (sites of one colour
+// class are never neighbours).  Row entries are wave-uniform scalar loads;
+// spin rows go through the buffer descriptors with the row in soffset.
 template <int KM, int FM, int MAXD>
-__device__ __forceinline__ void rep_pair_uniform(const RepLaneArgs &a, const SpinPlanes &sp3,
+__device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const SpinPlanes &sp3,
                                                  int i0, int ce, int r, uint32_t g, float beta,
                                                  float b, uint32_t rid, bool active,
                                                  const RunArgs &ra, double (&acc)[5])
 {
+    constexpr int NS = kRepSitesPerStep;
     const int32_t lane_b = r * 4;        // byte offset of this replica inside a row
-    float hx[2], hy[2], hz[2], sx[2], sy[2], sz[2];
-    int ic[2];
-    bool valid[2];
+    float hx[NS], hy[NS], hz[NS], sx[NS], sy[NS], sz[NS];
+    int ic[NS];
+    bool valid[NS];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < NS; ++u) {
         valid[u] = i0 + u < ce;
         ic[u] = valid[u] ? i0 + u : ce - 1;
         hx[u] = 0.0f;
@@ -184,7 +189,7 @@ __device__ __forceinline__ void rep_pair_uniform(const RepLaneArgs &a, const Spi
         sz[u] = bload(sp3.z, lane_b, oi);
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < NS; ++u) {
         const int i = ic[u];
         const RepSite<KM, FM, true> sp(a, i);
         const float fx = fmaf(b, sp.nx, hx[u]);
@@ -333,9 +338,9 @@ __device__ __forceinline__ void rep_tile(const RepLaneArgs &a, int colour, int t
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if constexpr (MAXD > 0) {
         const SpinPlanes sp3(a);
-        for (int j = 0; j < SPL && base + j < ce; j += 2) {
+        for (int j = 0; j < SPL && base + j < ce; j += (W == 64 ? kRepSitesPerStep : 2)) {
             if constexpr (W == 64)
-                rep_pair_uniform<KM, FM, MAXD>(a, sp3, base + j, ce, L.r, g, beta, b, rid, active,
+                rep_step_uniform<KM, FM, MAXD>(a, sp3, base + j, ce, L.r, g, beta, b, rid, active,
                                                ra, acc);
             else
                 rep_pair_update<KM, FM, MAXD>(a, base + j, ce, L.r, g, beta, b, rid, active, ra,
