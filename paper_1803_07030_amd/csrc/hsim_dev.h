@@ -19,7 +19,7 @@ constexpr int kRepWaves = HSIM_REP_WAVES;                    // waves per replic
 constexpr int kRepSitesPerWave = HSIM_REP_SITES_PER_WAVE;    // sites per wave of a tile
 constexpr int kRepThreads = kRepWaves * 64;
 #ifndef HSIM_REP_SITES_PER_STEP
-#define HSIM_REP_SITES_PER_STEP 2
+#define HSIM_REP_SITES_PER_STEP 1
 #endif
 // sites whose loads a wave issues together (64-lane groups); divides the
 // sites per wave

@@ -155,7 +155,7 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t rs, int32_t lane_b
 
 // kRepSitesPerStep sites of one 64-lane group at once, rows padded to MAXD:
 // all loads of the step are issued before any store (sites of one colour
-// class are never neighbours).  Row entries are wave-uniform scalar loads;
+// class are never neighbours); the own rows are written back whole.  Row entries are wave-uniform scalar loads;
 // spin rows go through the buffer descriptors with the row in soffset.
 template <int KM, int FM, int MAXD>
 __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const SpinPlanes &sp3,
@@ -203,10 +203,12 @@ __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const Spi
         const bool ok = accept32(dE, beta, t.u) && live;
         if (live && dE != dE) atomicOr(&ra.ctl->status, 1u);
         const int32_t oi = i * a.Rp * 4;
-        if (ok) {
-            bstore(sp3.x, lane_b, oi, t.x);
-            bstore(sp3.y, lane_b, oi, t.y);
-            bstore(sp3.z, lane_b, oi, t.z);
+        // every live lane stores (the old value when rejected): whole rows
+        // reach memory faster than rows with holes, though more bytes
+        if (live) {
+            bstore(sp3.x, lane_b, oi, ok ? t.x : sx[u]);
+            bstore(sp3.y, lane_b, oi, ok ? t.y : sy[u]);
+            bstore(sp3.z, lane_b, oi, ok ? t.z : sz[u]);
         }
         accumulate(acc, ok, live, dE, ok ? t.x : sx[u], ok ? t.y : sy[u], ok ? t.z : sz[u]);
     }
@@ -284,6 +286,30 @@ __device__ __forceinline__ double rep_site_energy(const RepLaneArgs &a, int i, i
     const RepSite<KM, FM> sp(a, i);
     const size_t oi = (size_t)i * a.Rp;
     const double sx = S[oi], sy = S[plane + oi], sz = S[2 * plane + oi];
+    const double an = sx * (double)sp.ex + sy * (double)sp.ey + sz * (double)sp.ez;
+    const double zn = sx * (double)sp.nx + sy * (double)sp.ny + sz * (double)sp.nz;
+    return -0.5 * (sx * hx + sy * hy + sz * hz) - b * zn - (double)sp.k * an * an;
+}
+
+// The same energy through the padded rows (row entries in CSR order, then
+// zero-J padding; 64-lane groups): scalar row loads, buffer spin loads.
+template <int KM, int FM, int MAXD>
+__device__ __forceinline__ double rep_site_energy_ell(const RepLaneArgs &a, const SpinPlanes &sp3,
+                                                      int i, int32_t lane_b, double b)
+{
+    double hx = 0.0, hy = 0.0, hz = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < MAXD; ++sl) {
+        const int32_t ob = cload(a.ell_col, i * MAXD + sl) * a.Rp * 4;
+        const double Jp = (double)cload(a.ell_J, i * MAXD + sl);
+        hx += Jp * (double)bload(sp3.x, lane_b, ob);
+        hy += Jp * (double)bload(sp3.y, lane_b, ob);
+        hz += Jp * (double)bload(sp3.z, lane_b, ob);
+    }
+    const RepSite<KM, FM, true> sp(a, i);
+    const int32_t oi = i * a.Rp * 4;
+    const double sx = bload(sp3.x, lane_b, oi), sy = bload(sp3.y, lane_b, oi),
+                 sz = bload(sp3.z, lane_b, oi);
     const double an = sx * (double)sp.ex + sy * (double)sp.ey + sz * (double)sp.ez;
     const double zn = sx * (double)sp.nx + sy * (double)sp.ny + sz * (double)sp.nz;
     return -0.5 * (sx * hx + sy * hy + sz * hz) - b * zn - (double)sp.k * an * an;
@@ -371,7 +397,7 @@ __device__ __forceinline__ void rep_tile(const RepLaneArgs &a, int colour, int t
 }
 
 // Energy records of one tile (field 5).
-template <int KM, int FM, int W>
+template <int KM, int FM, int W, int MAXD>
 __device__ __forceinline__ void rep_tile_energy(const RepLaneArgs &a, int tg, int group,
                                                 uint32_t g, const RunArgs &ra, double *part,
                                                 double *red)
@@ -386,10 +412,19 @@ __device__ __forceinline__ void rep_tile_energy(const RepLaneArgs &a, int tg, in
     double e = 0.0;
     if (L.r < a.R) {
         const double b = ra.bfield[(size_t)L.r * ra.S_hist + g / (uint32_t)ra.M];
-        for (int j = 0; j < SPL; ++j) {
-            const int i = base + j;
-            if (i >= ce) break;
-            e += rep_site_energy<KM, FM>(a, i, L.r, b);
+        if constexpr (MAXD > 0 && W == 64) {
+            const SpinPlanes sp3(a);
+            for (int j = 0; j < SPL; ++j) {
+                const int i = base + j;
+                if (i >= ce) break;
+                e += rep_site_energy_ell<KM, FM, MAXD>(a, sp3, i, L.r * 4, b);
+            }
+        } else {
+            for (int j = 0; j < SPL; ++j) {
+                const int i = base + j;
+                if (i >= ce) break;
+                e += rep_site_energy<KM, FM>(a, i, L.r, b);
+            }
         }
     }
     red[(L.w * 64 + L.lane) * 5] = e;
@@ -535,14 +570,14 @@ __global__ __launch_bounds__(kRepThreads) void k_rep_phase(RepLaneArgs a, int co
                               rep_slot(ra, a, ntiles, t_off % ra.rec_win), red);
 }
 
-template <int KM, int FM, int W>
+template <int KM, int FM, int W, int MAXD>
 __global__ __launch_bounds__(kRepThreads) void k_rep_efull(RepLaneArgs a, int t_off, int ntiles,
                                                            RunArgs ra)
 {
     __shared__ double red[kRedDoubles];
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     if (!rep_recompute_due(g % (uint32_t)ra.M, ra.P)) return;
-    rep_tile_energy<KM, FM, W>(a, blockIdx.x, blockIdx.y, g, ra,
+    rep_tile_energy<KM, FM, W, MAXD>(a, blockIdx.x, blockIdx.y, g, ra,
                                rep_slot(ra, a, ntiles, t_off % ra.rec_win), red);
 }
 
@@ -718,7 +753,7 @@ __global__ __launch_bounds__(kRepThreads) void k_rep_persistent(RepLaneArgs a, i
         double *chk = rep_chunk_slot(ra, a, t & 1);
         if (rep_recompute_due(g % (uint32_t)ra.M, ra.P)) {
             for (int u = blockIdx.x; u < ntiles * groups; u += gridDim.x)
-                rep_tile_energy<KM, FM, W>(a, u % ntiles, u / ntiles, g, ra, part, red);
+                rep_tile_energy<KM, FM, W, MAXD>(a, u % ntiles, u / ntiles, g, ra, part, red);
             // the energy reads spins that colour 0 is about to change
             grid_barrier(ra.ctl, flags, epoch, cap);
         }
@@ -841,9 +876,9 @@ hipError_t launch_rep_efull(hipStream_t st, int kmode, int fmode, const RepLaneA
 {
     const int Wd = lane_width(a);
     dim3 grid((unsigned)ntiles, (unsigned)(a.Rp / Wd)), blk(kRepThreads);
-    HSIM_DISPATCH_KFW(kmode, fmode, Wd, {
-        hipLaunchKernelGGL((k_rep_efull<KM, FM, W>), grid, blk, 0, st, a, t_off, ntiles, ra);
-    });
+    HSIM_DISPATCH_KFW(kmode, fmode, Wd, HSIM_DISPATCH_D(a.ell_w, {
+        hipLaunchKernelGGL((k_rep_efull<KM, FM, W, MAXD>), grid, blk, 0, st, a, t_off, ntiles, ra);
+    }));
     return hipGetLastError();
 }
 
