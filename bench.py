@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--cpu-mcs", type=int, default=400, help="MCS per thread of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--workload", default="sc64", choices=["sc64", "films"],
+                    help="sc64: the headline workload; films: 256 diluted films, one replica "
+                         "each (site-lane layout), for the site-lane kernel's numbers")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (HBM byte-counter calibration)")
     return ap.parse_args()
@@ -121,6 +124,9 @@ def main():
         copy_calibration()
         return
     stream = torch.cuda.Stream()
+    if args.workload == "films":
+        films_bench(args, stream)
+        return
     lat, T = workload()
     launch = dict(persistent=hsim.LAUNCH_PERSISTENT, graph=hsim.LAUNCH_GRAPH,
                   plain=hsim.LAUNCH_PLAIN, auto=hsim.LAUNCH_AUTO)[args.launch]
@@ -202,6 +208,60 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(lat, T, args.cpu_mcs, hist)
     print(json.dumps(out))
+
+
+def b_alg_site_lane(zbar, a):
+    """Algorithmic bytes per attempted update, site-lane layout, per-bond J:
+    user index (4) + row of zbar (column, J) pairs (8 zbar) + own spin (12) +
+    neighbour spins counted once per MCS (12) + write on accept (12 a)."""
+    return 4.0 + 8.0 * zbar + 24.0 + 12.0 * a
+
+
+def films_bench(args, stream):
+    """256 diluted films (L in 16..128, d in 2..10, 10% vacancies, per-bond J
+    in [0.5, 1.5], K = 0.05 z), each film one replica at its own temperature
+    in [0.2, 2.0], single precision, site-lane layout, plain launches with the
+    colour-phase launches of every n-th MCS timed."""
+    import torch
+    import synth
+    from paper_1803_07030_amd import hsim
+    mcs = args.mcs if args.mcs != MCS else 1000
+    films, Ts = synth.film_batch()
+    nsites = sum(f.n for f in films)
+    zbar = sum(f.nnz for f in films) / nsites
+    with torch.cuda.stream(stream):
+        plans = [hsim.Plan(f) for f in films]
+        batch = hsim.Batch(plans, seed=3, precision=hsim.FP32, layout=hsim.LAYOUT_SITE).bind(1, mcs)
+        Tm = np.asarray(Ts)[:, None]
+        for _ in range(args.warmup):
+            batch.init_spins(hsim.INIT_COLD_Z)
+            batch.run(Tm, 0.0, launch=hsim.LAUNCH_PLAIN)
+        stream.synchronize()
+        batch.phase_times()
+        batch.time_phases(args.time_every)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            batch.init_spins(hsim.INIT_COLD_Z)
+            batch.run(Tm, 0.0, launch=hsim.LAUNCH_PLAIN)
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+        assert batch.status() == 0
+        ph_ms, ph_n, ph_upd = batch.phase_times()
+        batch.time_phases(0)
+        hist = batch.history.cpu().numpy()
+    acc = float(hist[..., 4].sum() / (nsites * mcs))
+    balg = b_alg_site_lane(zbar, acc)
+    achieved = balg * ph_upd / (ph_ms / 1e3) / 1e9
+    print(json.dumps({
+        "metric": "spin updates/sec, site-lane films batch", "value": nsites * mcs * args.steps / wall,
+        "unit": "spin updates/s", "steps": args.steps, "warmup": args.warmup,
+        "config": {"workload": f"256 diluted films, {nsites} sites, {mcs} MCS, f32, site-lane, plain launch",
+                   "sites": nsites, "mean_degree": zbar},
+        "acceptance": acc,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "kernel": "k_site_phase",
+                     "launch_ms": ph_ms / ph_n, "updates_per_launch": ph_upd / ph_n,
+                     "bytes_per_update": balg, "timed_launches": ph_n}}))
 
 
 def plain_launch(lat, T, mcs, stream):
