@@ -27,6 +27,10 @@ _lock = threading.Lock()
 _lib = None
 
 PROPOSAL_EXACT, PROPOSAL_F32MAP = 0, 1
+# update policies (the moves of Hinzke and Nowak 1999 named in the paper's
+# "Monte Carlo Metropolis algorithm" section, and the adaptive move)
+POLICY_RANDOM, POLICY_FLIP, POLICY_SMALL_STEP, POLICY_GAUSSIAN, POLICY_HN, POLICY_ADAPTIVE = range(6)
+SIGMA_MIN, SIGMA_MAX = 1e-4, 60.0
 INIT_GIVEN, INIT_COLD_Z, INIT_RANDOM = 0, 1, 2
 INIT_CODES = {"given": INIT_GIVEN, "cold": INIT_COLD_Z, "random": INIT_RANDOM}
 
@@ -53,7 +57,11 @@ class _Params(ctypes.Structure):
                 ("first_step", ctypes.c_int32), ("recompute_every", ctypes.c_int32),
                 ("T", ctypes.c_void_p), ("B", ctypes.c_void_p), ("proposal", ctypes.c_int32),
                 ("init", ctypes.c_int32), ("order", ctypes.c_void_p), ("colour", ctypes.c_void_p),
-                ("check_every_update", ctypes.c_int32)]
+                ("check_every_update", ctypes.c_int32),
+                ("n_types", ctypes.c_int32), ("site_type", ctypes.c_void_p),
+                ("type_policy", ctypes.c_void_p), ("type_param", ctypes.c_void_p),
+                ("sigma_min", ctypes.c_double), ("sigma_max", ctypes.c_double),
+                ("sigma", ctypes.c_void_p), ("sigma_trace", ctypes.c_void_p)]
 
 
 class _Outputs(ctypes.Structure):
@@ -93,6 +101,11 @@ def lib():
             L.or_energy_grad.argtypes = [vp, dbl, vp, dbl, vp, vp, vp, vp]
             L.or_run.argtypes = [vp, vp, vp]
             L.or_run.restype = ctypes.c_int
+            L.or_log.argtypes = [dbl]
+            L.or_log.restype = dbl
+            L.or_trial.argtypes = [ctypes.c_int32, ctypes.c_int32, u64, u32, u32, u32, vp, dbl,
+                                   dbl, vp]
+            L.or_trial.restype = dbl
             _lib = L
     return _lib
 
@@ -149,6 +162,21 @@ def sphere_f32map(seed, site, g, rep):
     u = np.empty(1)
     lib().or_sphere_f32map(seed, site, g, rep, _ptr(out), _ptr(u))
     return out, float(u[0])
+
+
+def log(x):
+    """The oracle's own natural logarithm (or_log)."""
+    return lib().or_log(float(x))
+
+
+def trial(proposal, policy, seed, site, g, rep, s, param, cos_theta=None):
+    """Trial direction of one site: returns (trial (3,), acceptance uniform)."""
+    out = np.empty(3)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    c = np.cos(param) if cos_theta is None else cos_theta
+    u = lib().or_trial(proposal, policy, seed, site, g, rep, _ptr(s), float(param), float(c),
+                       _ptr(out))
+    return out, u
 
 
 def validate(lat):
@@ -208,12 +236,19 @@ def energy_grad(lat, B, spins, g=1.0):
 
 def run(lat, T, B, mcs_per_step, seed, replica=0, init="random", spins=None,
         proposal=PROPOSAL_EXACT, first_step=0, recompute_every=100, order=None,
-        colour=None, trace_accepts=False, full_energy=False, check_every_update=False):
+        colour=None, trace_accepts=False, full_energy=False, check_every_update=False,
+        policies=None, site_type=None, sigma=None, sigma_min=SIGMA_MIN, sigma_max=SIGMA_MAX,
+        trace_sigma=False):
     """Colour-ordered Metropolis sweep of one replica over a T/B schedule.
+
+    policies: None (random move everywhere) or a list of (policy, param) per
+    site type; site_type: per-site type in user order (None: type 0); sigma:
+    starting adaptive width (default: the adaptive type's param).
 
     Returns a dict: history (S, M, 5) [E, Mx, My, Mz, n_acc], spins (n, 3),
     accept (S*M, n) uint8 or None, e_full (S*M,) or None, near_ties,
-    max_incr_err, max_update_err, n_decisions.
+    max_incr_err, max_update_err, n_decisions, sigma (final adaptive width or
+    None), sigma_trace ((S*M,) width used in each MCS, or None).
     """
     T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
     B = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(B), T.shape), dtype=np.float64)
@@ -229,16 +264,31 @@ def run(lat, T, B, mcs_per_step, seed, replica=0, init="random", spins=None,
     ef = np.zeros(S_steps * M) if full_energy else None
     order_a = None if order is None else np.ascontiguousarray(order, dtype=np.int64)
     colour_a = None if colour is None else np.ascontiguousarray(colour, dtype=np.int32)
+    ntypes, tp, tq, st, sg, strace = 0, None, None, None, None, None
+    if policies is not None:
+        ntypes = len(policies)
+        tp = np.ascontiguousarray([int(a) for a, _ in policies], dtype=np.int32)
+        tq = np.ascontiguousarray([float(b) for _, b in policies], dtype=np.float64)
+        if site_type is not None:
+            st = np.ascontiguousarray(site_type, dtype=np.int32)
+        ad = [b for a, b in policies if int(a) == POLICY_ADAPTIVE]
+        sg = np.array([float(sigma) if sigma is not None else (ad[0] if ad else 1.0)])
+        if trace_sigma:
+            strace = np.zeros(S_steps * M)
     p = _Params(seed & 0xFFFFFFFFFFFFFFFF, replica, S_steps, M, first_step, recompute_every,
                 _ptr(T), _ptr(B), proposal, INIT_CODES[init] if isinstance(init, str) else init,
-                _ptr(order_a), _ptr(colour_a), 1 if check_every_update else 0)
+                _ptr(order_a), _ptr(colour_a), 1 if check_every_update else 0,
+                ntypes, _ptr(st), _ptr(tp), _ptr(tq), float(sigma_min), float(sigma_max),
+                _ptr(sg), _ptr(strace))
     o = _Outputs(_ptr(sp), _ptr(hist), _ptr(acc), _ptr(ef), 0, 0.0, 0.0, 0)
     rc = lib().or_run(L.ref, ctypes.byref(p), ctypes.byref(o))
     if rc != 0:
         raise ValueError(f"oracle run rejected its input (code {rc})")
+    has_ad = policies is not None and any(int(a) == POLICY_ADAPTIVE for a, _ in policies)
     return dict(history=hist, spins=sp, accept=acc, e_full=ef, near_ties=o.near_ties,
                 max_incr_err=o.max_incr_err, max_update_err=o.max_update_err,
-                n_decisions=o.n_decisions)
+                n_decisions=o.n_decisions, sigma=float(sg[0]) if has_ad else None,
+                sigma_trace=strace)
 
 
 def run_replicas(jobs, threads=None):

@@ -117,6 +117,194 @@ void or_sphere_f32map(uint64_t seed, uint32_t site, uint32_t g, uint32_t rep, do
 }
 
 /* ---------------------------------------------------------------------- */
+/* Natural logarithm from correctly rounded operations only: x = m 2^e with m
+ * in [sqrt(1/2), sqrt(2)) (exact), ln m = 2 atanh(t) with t = (m-1)/(m+1),
+ * |t| < 0.172, summed as 2t (1 + t^2/3 + ... + t^22/23) in Horner form (the
+ * next term is below 2^-60 of the sum); ln x = e ln 2 + ln m. */
+double or_log(double x)
+{
+    int e;
+    double m = frexp(x, &e);                 /* m in [0.5, 1) */
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    double t = (m - 1.0) / (m + 1.0);
+    double t2 = t * t;
+    double p = 1.0 / 23.0;
+    for (int k = 10; k >= 0; --k) p = p * t2 + 1.0 / (double)(2 * k + 1);
+    return (double)e * 0x1.62e42fefa39efp-1 + 2.0 * t * p;
+}
+
+/* Orthonormal pair perpendicular to the unit vector n (Duff, Burgess,
+ * Christensen, Hery, Kensler, Liani and Villemin, "Building an orthonormal
+ * basis, revisited", JCGT 2017), products taken left to right. */
+static void onb(const double n[3], double b1[3], double b2[3])
+{
+    double sign = copysign(1.0, n[2]);
+    double a = -1.0 / (sign + n[2]);
+    double b = n[0] * n[1] * a;
+    b1[0] = 1.0 + sign * n[0] * n[0] * a;
+    b1[1] = sign * b;
+    b1[2] = -sign * n[0];
+    b2[0] = b;
+    b2[1] = sign + n[1] * n[1] * a;
+    b2[2] = -n[1];
+}
+
+/* v / |v|, or s unchanged when |v| is 0. */
+static void normalise(const double v[3], const double s[3], double out[3])
+{
+    double nn = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    if (nn > 0.0) {
+        out[0] = v[0] / nn;
+        out[1] = v[1] / nn;
+        out[2] = v[2] / nn;
+    } else {
+        out[0] = s[0];
+        out[1] = s[1];
+        out[2] = s[2];
+    }
+}
+
+/* Point of the cap around s: polar cosine c, azimuth (cphi, sphi) in the
+ * basis of onb(s), then normalised. */
+static void cap_point(const double s[3], double c, double cphi, double sphi, double out[3])
+{
+    double b1[3], b2[3], v[3];
+    onb(s, b1, b2);
+    double st2 = 1.0 - c * c;
+    double st = sqrt(st2 > 0.0 ? st2 : 0.0);
+    for (int k = 0; k < 3; ++k) v[k] = c * s[k] + st * (cphi * b1[k] + sphi * b2[k]);
+    normalise(v, s, out);
+}
+
+/* Exact mode: a point (v1, v2) uniform in the unit disk minus its centre,
+ * from the words of attempts t = *att, *att+1, ... (v = 2 u53 - 1 per pair of
+ * words); *att is advanced past the accepted attempt.  Returns 0 after 64
+ * rejections (probability below 1e-40). */
+static int disk_point(uint64_t seed, uint32_t site, uint32_t g, uint32_t rep, uint32_t *att,
+                      double *v1, double *v2, double *s)
+{
+    for (int tries = 0; tries < 64; ++tries) {
+        uint32_t w[4];
+        words(seed, site, g, rep, (*att)++, w);
+        double a = 2.0 * or_u53(w[0], w[1]) - 1.0;
+        double b = 2.0 * or_u53(w[2], w[3]) - 1.0;
+        double q = a * a + b * b;
+        if (q < 1.0 && q > 0.0) {
+            *v1 = a;
+            *v2 = b;
+            *s = q;
+            return 1;
+        }
+    }
+    return 0;
+}
+
+/* Trial of one site.
+ *   Exact mode (double precision, correctly rounded operations and or_log):
+ *     acceptance uniform u53(w0, w1) of attempt 0 for every policy;
+ *     random: Marsaglia from attempts 1..32 (or_sphere_exact);
+ *     flip: -s;
+ *     small step: c = 1 - u53(attempt 1: w0, w1) (1 - cos theta); azimuth
+ *       from the first disk point of attempts 2.., (v1, v2)/sqrt(s);
+ *     Gaussian (and adaptive): three normals by the polar method (Marsaglia
+ *       and Bray 1964) from disk points of attempts 1..: f = sqrt(-2 ln s / s),
+ *       (v1 f, v2 f) from the first point, v1 f from the second;
+ *     Hinzke-Nowak: part k = (3 w3) >> 32 of attempt 0 picks random (0), flip
+ *       (1) or small step (2).
+ *   Single-precision map (evaluated here in double; u_k = u24 of word k):
+ *     random: z = 2 u0 - 1, phi = u1 turns, acceptance u2 (attempt 0);
+ *     flip: acceptance u2;
+ *     small step: c = 1 - u0 (1 - cos theta), phi = u1 turns, acceptance u2;
+ *     Gaussian: r0 = sqrt(-2 ln u0), r1 = sqrt(-2 ln u2), normals
+ *       (r0 cos 2pi u1, r0 sin 2pi u1, r1 cos 2pi u3); acceptance u24(w0) of
+ *       attempt 1;
+ *     Hinzke-Nowak: part from w3 as above, then random or small step on
+ *       (u0, u1), acceptance u2.
+ *   Small step, Gaussian and adaptive trials are normalised. */
+double or_trial(int32_t proposal, int32_t policy, uint64_t seed, uint32_t site, uint32_t g,
+                uint32_t rep, const double s[3], double param, double cos_theta, double out[3])
+{
+    uint32_t w[4];
+    words(seed, site, g, rep, 0, w);
+    int pol = policy;
+    if (pol == OR_POLICY_HN) {
+        uint32_t part = (uint32_t)(((uint64_t)w[3] * 3u) >> 32);
+        pol = part == 0 ? OR_POLICY_RANDOM : (part == 1 ? OR_POLICY_FLIP : OR_POLICY_SMALL_STEP);
+    }
+    if (proposal == OR_PROPOSAL_EXACT) {
+        double u = or_u53(w[0], w[1]);
+        if (pol == OR_POLICY_RANDOM) {
+            or_sphere_exact(seed, site, g, rep, out);
+        } else if (pol == OR_POLICY_FLIP) {
+            out[0] = -s[0];
+            out[1] = -s[1];
+            out[2] = -s[2];
+        } else if (pol == OR_POLICY_SMALL_STEP) {
+            uint32_t w1[4];
+            words(seed, site, g, rep, 1, w1);
+            double c = 1.0 - or_u53(w1[0], w1[1]) * (1.0 - cos_theta);
+            uint32_t att = 2;
+            double v1, v2, q, cphi = 1.0, sphi = 0.0;
+            if (disk_point(seed, site, g, rep, &att, &v1, &v2, &q)) {
+                double r = sqrt(q);
+                cphi = v1 / r;
+                sphi = v2 / r;
+            }
+            cap_point(s, c, cphi, sphi, out);
+        } else {   /* Gaussian, adaptive */
+            double n3[3] = {0.0, 0.0, 0.0};
+            uint32_t att = 1;
+            double v1, v2, q;
+            if (disk_point(seed, site, g, rep, &att, &v1, &v2, &q)) {
+                double f = sqrt(-2.0 * or_log(q) / q);
+                n3[0] = v1 * f;
+                n3[1] = v2 * f;
+                if (disk_point(seed, site, g, rep, &att, &v1, &v2, &q)) {
+                    double f2 = sqrt(-2.0 * or_log(q) / q);
+                    n3[2] = v1 * f2;
+                }
+            }
+            double v[3];
+            for (int k = 0; k < 3; ++k) v[k] = s[k] + param * n3[k];
+            normalise(v, s, out);
+        }
+        return u;
+    }
+    double u0 = or_u24(w[0]), u1 = or_u24(w[1]), u2 = or_u24(w[2]), u3 = or_u24(w[3]);
+    if (pol == OR_POLICY_RANDOM) {
+        double z = 2.0 * u0 - 1.0;
+        double r2 = 1.0 - z * z;
+        double r = sqrt(r2 > 0.0 ? r2 : 0.0);
+        out[0] = r * cos(OR_TWO_PI * u1);
+        out[1] = r * sin(OR_TWO_PI * u1);
+        out[2] = z;
+        return u2;
+    }
+    if (pol == OR_POLICY_FLIP) {
+        out[0] = -s[0];
+        out[1] = -s[1];
+        out[2] = -s[2];
+        return u2;
+    }
+    if (pol == OR_POLICY_SMALL_STEP) {
+        double c = 1.0 - u0 * (1.0 - cos_theta);
+        cap_point(s, c, cos(OR_TWO_PI * u1), sin(OR_TWO_PI * u1), out);
+        return u2;
+    }
+    double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+    double n3[3] = {r0 * cos(OR_TWO_PI * u1), r0 * sin(OR_TWO_PI * u1), r1 * cos(OR_TWO_PI * u3)};
+    double v[3];
+    for (int k = 0; k < 3; ++k) v[k] = s[k] + param * n3[k];
+    normalise(v, s, out);
+    uint32_t wa[4];
+    words(seed, site, g, rep, 1, wa);
+    return or_u24(wa[0]);
+}
+
+/* ---------------------------------------------------------------------- */
 static double dot3(const double *a, const double *b)
 {
     return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
@@ -323,6 +511,32 @@ int or_run(const or_lattice *lat, const or_params *p, or_outputs *out)
         return -1;
     for (int32_t s = 0; s < p->n_steps; ++s)
         if (!(p->T[s] >= 0.0) || !isfinite(p->B[s])) return -3;
+    /* update policies per site type */
+    int has_adaptive = 0;
+    double cos_t[OR_MAX_TYPES];
+    if (p->n_types < 0 || p->n_types > OR_MAX_TYPES) return -1;
+    if (p->n_types > 0) {
+        if (!p->type_policy || !p->type_param) return -1;
+        for (int32_t t = 0; t < p->n_types; ++t) {
+            int32_t pol = p->type_policy[t];
+            double prm = p->type_param[t];
+            if (pol < OR_POLICY_RANDOM || pol > OR_POLICY_ADAPTIVE) return -1;
+            if ((pol == OR_POLICY_SMALL_STEP || pol == OR_POLICY_HN) &&
+                !(prm > 0.0 && prm <= 3.14159265358979323846))
+                return -3;
+            if ((pol == OR_POLICY_GAUSSIAN || pol == OR_POLICY_ADAPTIVE) && !(prm > 0.0 && isfinite(prm)))
+                return -3;
+            cos_t[t] = cos(prm);
+            if (pol == OR_POLICY_ADAPTIVE) has_adaptive = 1;
+        }
+        if (p->site_type)
+            for (int64_t i = 0; i < lat->n; ++i)
+                if (p->site_type[i] < 0 || p->site_type[i] >= p->n_types) return -1;
+        if (has_adaptive && (!p->sigma || !(*p->sigma > 0.0) || !isfinite(*p->sigma) ||
+                             !(p->sigma_min > 0.0) || !(p->sigma_max >= p->sigma_min) ||
+                             !isfinite(p->sigma_max)))
+            return -3;
+    }
 
     int32_t *colour = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
     if (p->colour) {
@@ -364,6 +578,9 @@ int or_run(const or_lattice *lat, const or_params *p, or_outputs *out)
             int64_t rec = (int64_t)s * M + m;
             double dEsum = 0.0;
             int64_t nacc = 0;
+            int64_t n_ad = 0, acc_ad = 0;     /* adaptive-policy sites: attempts, accepts */
+            double sigma = has_adaptive ? *p->sigma : 0.0;
+            if (p->sigma_trace) p->sigma_trace[rec] = sigma;
             for (int64_t t = 0; t < n; ++t) {
                 int64_t i = vis[t].site;
                 double *si = S + 3 * i;
@@ -381,7 +598,13 @@ int or_run(const or_lattice *lat, const or_params *p, or_outputs *out)
                 hz = hz + b * nd[2];
 
                 double sn[3], u;
-                if (p->proposal == OR_PROPOSAL_EXACT) {
+                int32_t ty = (p->n_types > 0 && p->site_type) ? p->site_type[i] : 0;
+                int32_t pol = p->n_types > 0 ? p->type_policy[ty] : OR_POLICY_RANDOM;
+                if (pol != OR_POLICY_RANDOM) {
+                    double prm = pol == OR_POLICY_ADAPTIVE ? sigma : p->type_param[ty];
+                    u = or_trial(p->proposal, pol, p->seed, (uint32_t)i, g, p->replica, si, prm,
+                                 cos_t[ty], sn);
+                } else if (p->proposal == OR_PROPOSAL_EXACT) {
                     uint32_t w[4];
                     words(p->seed, (uint32_t)i, g, p->replica, 0, w);
                     u = or_u53(w[0], w[1]);
@@ -406,6 +629,10 @@ int or_run(const or_lattice *lat, const or_params *p, or_outputs *out)
                     if (fabs(u - pr) <= 4.0 * ulp) out->near_ties++;
                 }
                 out->n_decisions++;
+                if (pol == OR_POLICY_ADAPTIVE) {
+                    n_ad++;
+                    acc_ad += acc;
+                }
                 if (out->accept) out->accept[rec * n + i] = (uint8_t)acc;
                 if (acc) {
                     if (p->check_every_update) {
@@ -422,6 +649,13 @@ int or_run(const or_lattice *lat, const or_params *p, or_outputs *out)
                 }
             }
             E = E + dEsum;
+            /* adaptive width for the next MCS: scaled by 0.5 / (1 - a), a the
+             * acceptance of the adaptive sites in this MCS, kept in bounds */
+            if (has_adaptive && n_ad > 0) {
+                double a = (double)acc_ad / (double)n_ad;
+                double sg = sigma * (0.5 / (1.0 - a));
+                *p->sigma = fmin(p->sigma_max, fmax(p->sigma_min, sg));
+            }
             double Mx = 0.0, My = 0.0, Mz = 0.0;
             for (int64_t i = 0; i < n; ++i) {
                 Mx = Mx + S[3 * i];

@@ -40,6 +40,18 @@ typedef struct {
 } or_lattice;
 
 enum { OR_PROPOSAL_EXACT = 0, OR_PROPOSAL_F32MAP = 1 };
+/* Update policies (paper, section "Monte Carlo Metropolis algorithm" and the
+ * feature list of section "VEGAS software package"; the moves of Hinzke and
+ * Nowak 1999): the trial direction of a site. */
+enum {
+    OR_POLICY_RANDOM = 0,     /* uniform on the sphere, independent of S */
+    OR_POLICY_FLIP = 1,       /* S' = -S */
+    OR_POLICY_SMALL_STEP = 2, /* uniform in the cap of half-angle theta around S */
+    OR_POLICY_GAUSSIAN = 3,   /* S' = (S + sigma g) / |S + sigma g|, g standard normal */
+    OR_POLICY_HN = 4,         /* random, flip or small step, one third each */
+    OR_POLICY_ADAPTIVE = 5    /* Gaussian with a per-replica sigma tuned toward 50% acceptance */
+};
+#define OR_MAX_TYPES 8
 enum { OR_INIT_GIVEN = 0, OR_INIT_COLD_Z = 1, OR_INIT_RANDOM = 2 };
 
 typedef struct {
@@ -56,6 +68,15 @@ typedef struct {
     const int64_t *order;    /* NULL, or a permutation: visiting order inside each class */
     const int32_t *colour;   /* NULL (computed here) or a colouring to validate and use */
     int32_t check_every_update; /* O(n) full-energy check of every accepted move */
+    /* update policies per site type; n_types == 0: the random move everywhere */
+    int32_t n_types;
+    const int32_t *site_type;   /* n, values in [0, n_types) (NULL: type 0) */
+    const int32_t *type_policy; /* n_types, OR_POLICY_* */
+    const double *type_param;   /* n_types: half-angle theta (radians) for SMALL_STEP and HN,
+                                   sigma for GAUSSIAN, starting sigma for ADAPTIVE */
+    double sigma_min, sigma_max;/* bounds of the adaptive width */
+    double *sigma;              /* in/out: the adaptive width (used when a type is ADAPTIVE) */
+    double *sigma_trace;        /* NULL or n_steps*mcs_per_step: width used in each MCS */
 } or_params;
 
 typedef struct {
@@ -79,6 +100,16 @@ double or_u24(uint32_t w);
 int or_sphere_exact(uint64_t seed, uint32_t site, uint32_t g, uint32_t rep, double out[3]);
 /* Single-call proposal of the FP32 production mode, evaluated in double; u_out gets the acceptance uniform. */
 void or_sphere_f32map(uint64_t seed, uint32_t site, uint32_t g, uint32_t rep, double out[3], double *u_out);
+
+/* Natural logarithm by a fixed sequence of correctly rounded operations
+ * (binary exponent split, then the atanh series), so that any implementation
+ * of the same steps gives the same bits.  x > 0 finite. */
+double or_log(double x);
+/* Trial direction of one site under a policy (both proposal maps).  s: the
+ * current spin; param: theta or sigma; cos_theta: cos(param) for the cap
+ * moves.  Returns the acceptance uniform; out gets the trial. */
+double or_trial(int32_t proposal, int32_t policy, uint64_t seed, uint32_t site, uint32_t g,
+                uint32_t rep, const double s[3], double param, double cos_theta, double out[3]);
 
 /* 0 if valid, else a negative code: -1 argument, -2 structure, -3 values. */
 int or_validate(const or_lattice *lat);
