@@ -114,6 +114,13 @@ hsim_status hsim_plan_colouring(hsim_plan plan, int32_t *colour_out);
 /* Bonds i < j in row-major CSR order (the order of every per-bond array):
  * bond_ij_out [2*n_bonds] (may be NULL), *n_bonds_out (may be NULL). */
 hsim_status hsim_plan_bonds(hsim_plan plan, int32_t *bond_ij_out, int64_t *n_bonds_out);
+/* Site types (paper, section "Material building": every site belongs to a
+ * magnetic phase, and each phase may use its own update policy).
+ *   site_type [n] user order, values 0..7; NULL: type 0 everywhere.
+ * Set the types before creating the batches that use the plan; a batch
+ * picks them up at its next hsim_batch_bind or hsim_batch_set_policies.
+ * HSIM_E_PARAM for a value outside 0..7. */
+hsim_status hsim_plan_set_types(hsim_plan plan, const int32_t *site_type);
 void hsim_plan_destroy(hsim_plan plan);
 
 /* ---------------------------------------------------------------- batches */
@@ -163,6 +170,30 @@ hsim_status hsim_batch_init_spins(hsim_batch b, int32_t mode, const double *host
 hsim_status hsim_batch_run(hsim_batch b, int32_t first_step, int32_t n_steps, const double *T,
                            const double *B, int32_t recompute_every, hsim_launch launch,
                            uint32_t run_flags, uint32_t *d_trace, void *stream);
+/* Update policies (paper, section "Monte Carlo Metropolis algorithm" and the
+ * feature list: random, spin flip, small step, Gaussian and the adaptive
+ * move, one policy per magnetic phase), one per site type:
+ *   policy [n_types]: HSIM_POLICY_*; param [n_types]: the cap half-angle in
+ *     radians, (0, pi], for SMALL_STEP and HN; the width sigma > 0 for
+ *     GAUSSIAN; the starting width for ADAPTIVE (the first adaptive type's
+ *     value; all adaptive types of a replica share one width).
+ *   sigma_min, sigma_max: bounds of the adaptive width (0 < min <= max).
+ * The adaptive width of a replica is scaled after every MCS by
+ * 0.5 / (1 - a), a the acceptance of its adaptive sites in that MCS, then
+ * clamped to the bounds; it carries over between runs and is reset to the
+ * starting value by this call and by hsim_batch_bind.  n_types = 0 restores
+ * the random move everywhere.  Every site type of the batch's plans must be
+ * below n_types (HSIM_E_PARAM).  With policies set, PERSISTENT launches run
+ * as PLAIN launches. */
+enum {
+    HSIM_POLICY_RANDOM = 0, HSIM_POLICY_FLIP = 1, HSIM_POLICY_SMALL_STEP = 2,
+    HSIM_POLICY_GAUSSIAN = 3, HSIM_POLICY_HN = 4, HSIM_POLICY_ADAPTIVE = 5
+};
+hsim_status hsim_batch_set_policies(hsim_batch b, int32_t n_types, const int32_t *policy,
+                                    const double *param, double sigma_min, double sigma_max);
+/* Current adaptive width of every replica, host double [n_rep] (synchronous;
+ * the batch must be bound). */
+hsim_status hsim_batch_sigma(hsim_batch b, double *sigma_out);
 /* Launch timing of the colour phases (the dominant kernels).  With every > 0,
  * plain-launch runs record a HIP event pair around each colour-phase launch
  * of every `every`-th MCS, on the run's stream; 0 switches it off.  GRAPH

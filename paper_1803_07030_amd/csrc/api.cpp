@@ -25,6 +25,9 @@ void batch_to_user_impl(hsim_batch, int32_t, double *, hipStream_t);
 int32_t batch_status_impl(hsim_batch);
 void autotune_impl(hsim_batch, const char *, int32_t, hipStream_t);
 void batch_time_phases_impl(hsim_batch, int32_t);
+void plan_set_types_impl(hsim_plan, const int32_t *);
+void batch_set_policies_impl(hsim_batch, int32_t, const int32_t *, const double *, double, double);
+void batch_sigma_impl(hsim_batch, double *);
 void batch_phase_times_impl(hsim_batch, double *, int64_t *, int64_t *);
 
 namespace {
@@ -106,6 +109,11 @@ hsim_status hsim_plan_bonds(hsim_plan p, int32_t *bond_ij_out, int64_t *n_bonds_
     });
 }
 
+hsim_status hsim_plan_set_types(hsim_plan p, const int32_t *site_type)
+{
+    return guarded([&] { plan_set_types_impl(p, site_type); });
+}
+
 void hsim_plan_destroy(hsim_plan p) { delete p; }
 
 hsim_status hsim_batch_create(hsim_batch *out, int32_t n_rep, const hsim_plan *plans, uint64_t seed,
@@ -156,6 +164,17 @@ hsim_status hsim_batch_run(hsim_batch b, int32_t first_step, int32_t n_steps, co
         batch_run_impl(b, first_step, n_steps, T, B, recompute_every, launch, run_flags, d_trace,
                        S(stream));
     });
+}
+
+hsim_status hsim_batch_set_policies(hsim_batch b, int32_t n_types, const int32_t *policy,
+                                    const double *param, double sigma_min, double sigma_max)
+{
+    return guarded([&] { batch_set_policies_impl(b, n_types, policy, param, sigma_min, sigma_max); });
+}
+
+hsim_status hsim_batch_sigma(hsim_batch b, double *sigma_out)
+{
+    return guarded([&] { batch_sigma_impl(b, sigma_out); });
 }
 
 hsim_status hsim_batch_time_phases(hsim_batch b, int32_t every)

@@ -157,6 +157,7 @@ void batch_sizes_impl(hsim_batch b, int32_t S, int32_t M, size_t *ws, size_t *sp
     size_t off = align_up(sizeof(hsim::Ctl));
     off += align_up((size_t)b->R * 8);                 // ecarry
     off += 2 * align_up((size_t)b->R * S * 8);         // beta, bfield
+    off += align_up((size_t)b->R * 8);                 // adaptive widths
     size_t part = 0;
     if (b->layout == HSIM_LAYOUT_SITE) part = b->tiles.size() * hsim::kRecSite * 8;
     else if (b->layout == HSIM_LAYOUT_REPLICA)
@@ -176,6 +177,8 @@ void batch_sizes_impl(hsim_batch b, int32_t S, int32_t M, size_t *ws, size_t *sp
 void hsim_batch_s::upload_tables()
 {
     const size_t elem = f64 ? 8 : 4;
+    if (nad.size() != (size_t)R) nad.assign((size_t)R, 0.0);
+    d_nad.upload(nad);
     for (auto P : plans) P->upload_sweep();
     if (layout == HSIM_LAYOUT_REPLICA) {
         hsim_plan P = plans[0];
@@ -185,6 +188,7 @@ void hsim_batch_s::upload_tables()
         la.rp = (const int32_t *)P->d_rp.p;
         la.ci = (const int32_t *)P->d_ci.p;
         la.J = (const float *)P->d_Jf.p;
+        la.type = (const int32_t *)P->d_type.p;
         la.ell_col = (const int32_t *)P->d_ell_col.p;
         la.ell_J = (const float *)P->d_ell_J.p;
         la.orig = (const uint32_t *)P->d_orig.p;
@@ -221,6 +225,7 @@ void hsim_batch_s::upload_tables()
             d.nd = f64 ? P->d_ndd.p : P->d_ndf.p;
             d.spins = (char *)spins + spin_off[r] * elem;
             d.ell_w = P->ell_w;
+            d.type = (const int32_t *)P->d_type.p;
             d.ellT_col = (const int32_t *)P->d_ellT_col.p;
             d.ellT_J = f64 ? P->d_ellT_Jd.p : P->d_ellT_Jf.p;
             d.k0 = P->k0;
@@ -265,6 +270,8 @@ void batch_bind_impl(hsim_batch b, int32_t S, int32_t M, void *ws, void *spins, 
     off += align_up((size_t)b->R * S * 8);
     b->off_bfield = off;
     off += align_up((size_t)b->R * S * 8);
+    b->off_sigma = off;
+    off += align_up((size_t)b->R * 8);
     b->off_part = off;
     b->h_beta.assign((size_t)b->R * S, 0.0);
     b->h_bfield.assign((size_t)b->R * S, 0.0);
@@ -281,6 +288,70 @@ void batch_bind_impl(hsim_batch b, int32_t S, int32_t M, void *ws, void *spins, 
     // clear the control block once (outside any graph)
     hip_check(hipMemset(ws, 0, align_up(sizeof(hsim::Ctl))), "hipMemset");
     b->bound = true;
+    b->reset_sigma();
+}
+
+void hsim_batch_s::reset_sigma()
+{
+    if (!bound) return;
+    std::vector<double> s0((size_t)R, sigma0);
+    hip_check(hipMemcpy(ws + off_sigma, s0.data(), (size_t)R * 8, hipMemcpyHostToDevice), "hipMemcpy");
+}
+
+// Update policy per site type.  n_types == 0: the random move everywhere.
+void batch_set_policies_impl(hsim_batch b, int32_t nt, const int32_t *policy, const double *param,
+                             double smin, double smax)
+{
+    if (!b || nt < 0 || nt > hsim::kMaxTypes || (nt > 0 && (!policy || !param)))
+        throw Error(HSIM_E_ARG, "set_policies: bad argument");
+    hsim::Policies P{};
+    P.n_types = nt;
+    double s0 = 1.0;
+    for (int t = 0; t < nt; ++t) {
+        const int pol = policy[t];
+        const double prm = param[t];
+        if (pol < hsim::POL_RANDOM || pol > hsim::POL_ADAPTIVE)
+            throw Error(HSIM_E_ARG, "set_policies: unknown policy");
+        if ((pol == hsim::POL_SMALL_STEP || pol == hsim::POL_HN) && !(prm > 0.0 && prm <= M_PI))
+            throw Error(HSIM_E_PARAM, "cap half-angle must be in (0, pi]");
+        if ((pol == hsim::POL_GAUSSIAN || pol == hsim::POL_ADAPTIVE) && !(prm > 0.0 && std::isfinite(prm)))
+            throw Error(HSIM_E_PARAM, "Gaussian width must be positive and finite");
+        P.pol[t] = pol;
+        P.param[t] = prm;
+        P.cos_t[t] = std::cos(prm);
+        if (pol == hsim::POL_ADAPTIVE && !P.adaptive) {
+            P.adaptive = 1;
+            s0 = prm;
+        }
+    }
+    if (P.adaptive && !(smin > 0.0 && smax >= smin && std::isfinite(smax)))
+        throw Error(HSIM_E_PARAM, "adaptive width bounds must satisfy 0 < min <= max");
+    P.sigma_min = smin;
+    P.sigma_max = smax;
+    std::vector<double> nad((size_t)b->R, 0.0);
+    for (int r = 0; r < b->R; ++r) {
+        hsim_plan pl = b->plans[r];
+        if (nt > 0)
+            for (int64_t k = 0; k < pl->n; ++k) {
+                const int ty = pl->type.empty() ? 0 : pl->type[k];
+                if (ty >= nt) throw Error(HSIM_E_PARAM, "a site type has no policy");
+                if (P.pol[ty] == hsim::POL_ADAPTIVE) nad[r] += 1.0;
+            }
+    }
+    b->pol = P;
+    b->nad.swap(nad);
+    b->sigma0 = s0;
+    if (b->bound) {
+        b->upload_tables();
+        b->reset_sigma();
+    }
+}
+
+void batch_sigma_impl(hsim_batch b, double *out)
+{
+    if (!b || !out) throw Error(HSIM_E_ARG, "sigma: NULL argument");
+    if (!b->bound) throw Error(HSIM_E_STATE, "sigma before bind");
+    hip_check(hipMemcpy(out, b->ws + b->off_sigma, (size_t)b->R * 8, hipMemcpyDeviceToHost), "hipMemcpy");
 }
 
 hsim::RunArgs hsim_batch_s::run_args(uint32_t g0, int n_mcs, int P, uint32_t *trace)
@@ -296,6 +367,9 @@ hsim::RunArgs hsim_batch_s::run_args(uint32_t g0, int n_mcs, int P, uint32_t *tr
         a.carry = a.chunks + (size_t)rec_win * hsim::kChunks * 6 * Rp;
     }
     a.rec_win = rec_win;
+    a.pol = pol;
+    a.sigma = (double *)(ws + off_sigma);
+    a.n_ad = (const double *)d_nad.p;
     a.history = history;
     a.trace = trace;
     a.seed = seed;
@@ -431,6 +505,8 @@ void enqueue_rep_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F ef
             hip_check(hsim::launch_rep_phase(st, b->kmode, b->fmode, c, t, b->la, b->rep_ntiles, ra),
                       "phase launch");
         }
+        if (ra.pol.adaptive)
+            hip_check(hsim::launch_rep_sigma(st, b->la, b->rep_ntiles, t, ra), "sigma launch");
         if ((t + 1) % W == 0 || t == count - 1) {
             const int first = t - t % W;
             hip_check(hsim::launch_rep_reduce(st, b->la, b->rep_ntiles, first, t - first + 1,
@@ -592,6 +668,9 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
         if (b->tuned_launch >= 0) mode = b->tuned_launch;
         else mode = HSIM_LAUNCH_GRAPH;
     }
+    // the persistent kernel runs the random move only: with update policies
+    // the same sweep runs as plain launches
+    if (mode == HSIM_LAUNCH_PERSISTENT && b->pol.n_types > 0) mode = HSIM_LAUNCH_PLAIN;
     if (mode == HSIM_LAUNCH_PERSISTENT) {
         if (b->layout != HSIM_LAYOUT_REPLICA)
             throw Error(HSIM_E_UNSUPPORTED, "persistent launch needs the replica layout");

@@ -29,7 +29,7 @@ static_assert(kRepSitesPerWave % kRepSitesPerStep == 0 && kRepSitesPerWave % 2 =
 constexpr int kMaxPersistentBlocks = 4096;   // barrier flags reserved in the workspace
 constexpr int kRepTile = kRepWaves * kRepSitesPerWave;   // sites per replica-lane tile
 constexpr int kRecSite = 8;         // doubles per site-lane partial record
-constexpr int kRecFields = 6;       // dE, Mx, My, Mz, n_acc, E_full
+constexpr int kRecFields = 7;       // dE, Mx, My, Mz, n_acc, E_full, adaptive accepts
 constexpr int kChunks = 64;         // replica layout: chunks of the per-MCS record sum
 
 // How the anisotropy and field-direction terms are read.
@@ -46,6 +46,7 @@ struct RepDesc {
     const void *ax;           // [3][n] (K_SITE), stride n
     const void *nd;           // [3][n] (F_SITE), stride n
     void *spins;              // [3][n_pad] of this replica (site and block layouts)
+    const int32_t *type;      // n site types (internal order), NULL: type 0 everywhere
     const int32_t *ellT_col;  // [ell_w][n] padded rows, slot-major (NULL: use the CSR)
     const void *ellT_J;       // [ell_w][n] (float or double)
     double k0, e0[3], n0[3];  // uniform values (K_UNIFORM / F_UNIFORM)
@@ -59,6 +60,19 @@ struct RepDesc {
 // A block's share of one colour phase of one replica: internal sites [begin, end).
 struct Tile {
     int32_t rep, begin, end, colour;
+};
+
+// Update policy of every site type.
+enum : int32_t { POL_RANDOM = 0, POL_FLIP = 1, POL_SMALL_STEP = 2, POL_GAUSSIAN = 3, POL_HN = 4,
+                 POL_ADAPTIVE = 5 };
+constexpr int kMaxTypes = 8;
+struct Policies {
+    int32_t n_types;            // 0: the random move everywhere
+    int32_t adaptive;           // some type uses the adaptive move
+    int32_t pol[kMaxTypes];
+    double param[kMaxTypes];    // half-angle theta (small step, Hinzke-Nowak) or sigma (Gaussian)
+    double cos_t[kMaxTypes];    // cos theta
+    double sigma_min, sigma_max;
 };
 
 // Run-control word block at the start of the workspace.
@@ -89,11 +103,15 @@ struct RunArgs {
     int32_t trace_words;  // words per replica per MCS
     int32_t R;
     int32_t rec_win;      // replica layout: MCS per record window (>= 2)
+    Policies pol;
+    double *sigma;        // [R] adaptive width (when pol.adaptive)
+    const double *n_ad;   // [R] sites under the adaptive move per replica
 };
 
 struct RepLaneArgs {
     const int32_t *rp, *ci;
     const float *J;
+    const int32_t *type;        // [n] site types (internal order), NULL: type 0
     const int32_t *ell_col;     // [n][maxd] padded rows, site-major
     const float *ell_J;
     const uint32_t *orig;
@@ -138,6 +156,10 @@ hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour, in
                             const RepLaneArgs &a, int ntiles, const RunArgs &ra);
 hipError_t launch_rep_efull(hipStream_t st, int kmode, int fmode, const RepLaneArgs &a,
                             int ntiles, int t_off, const RunArgs &ra);
+// Adaptive widths after MCS t_off of the current sequence (policies with the
+// adaptive move).
+hipError_t launch_rep_sigma(hipStream_t st, const RepLaneArgs &a, int ntiles, int t_off,
+                            const RunArgs &ra);
 // Reduction of the record window holding MCS t_first .. t_first + count - 1
 // of the current sequence (count <= rec_win); advance > 0 closes the sequence.
 hipError_t launch_rep_reduce(hipStream_t st, const RepLaneArgs &a, int ntiles, int t_first,

@@ -83,6 +83,8 @@ struct hsim_plan_s {
     std::vector<int32_t> ell_col, ellT_col;
     std::vector<float> ell_Jf, ellT_Jf;
     std::vector<double> ellT_Jd;
+    // site types (internal order; empty: type 0 everywhere)
+    std::vector<int32_t> type;
     // user-order CSR for the energy and its gradient
     std::vector<int64_t> urp;
     std::vector<int32_t> uci, ubond, fwd_entry, bond_ij;
@@ -90,7 +92,7 @@ struct hsim_plan_s {
     // device copies (uploaded on first use)
     bool sweep_on_device = false, energy_on_device = false;
     hsim::DevBuf d_rp, d_ci, d_Jf, d_Jd, d_orig, d_kf, d_kd, d_axf, d_axd, d_ndf, d_ndd;
-    hsim::DevBuf d_ell_col, d_ell_J, d_ellT_col, d_ellT_Jf, d_ellT_Jd;
+    hsim::DevBuf d_ell_col, d_ell_J, d_ellT_col, d_ellT_Jf, d_ellT_Jd, d_type;
     hsim::DevBuf d_urp, d_uci, d_ubond, d_fwd, d_scratch;
 
     void upload_sweep();
@@ -122,6 +124,14 @@ struct hsim_batch_s {
     // replica layout
     int32_t Rp = 0;
     int32_t rep_ntiles = 0;
+    // update policies per site type, the adaptive sites per replica and the
+    // starting adaptive width
+    hsim::Policies pol{};
+    std::vector<double> nad;
+    hsim::DevBuf d_nad;
+    double sigma0 = 1.0;
+    size_t off_sigma = 0;
+    void reset_sigma();             // every replica's adaptive width to sigma0
     int32_t rec_win = 2;              // replica layout: MCS per record window
     // replica layout: bytes of the record window, its chunk sums and totals
     size_t rep_rec_bytes() const

@@ -247,7 +247,28 @@ void hsim_plan_s::upload_sweep()
         d_ellT_Jf.upload(ellT_Jf);
         d_ellT_Jd.upload(ellT_Jd);
     }
+    if (!type.empty()) d_type.upload(type);
     sweep_on_device = true;
+}
+
+// Site types (user order, values 0 .. kMaxTypes-1) kept in internal order;
+// NULL clears them.
+void plan_set_types_impl(hsim_plan P, const int32_t *user_type)
+{
+    if (!P) throw Error(HSIM_E_ARG, "set_types: NULL plan");
+    if (!user_type) {
+        P->type.clear();
+        P->d_type.release();
+        return;
+    }
+    std::vector<int32_t> t(P->n);
+    for (int64_t k = 0; k < P->n; ++k) {
+        const int32_t v = user_type[P->perm[k]];
+        if (v < 0 || v >= hsim::kMaxTypes) throw Error(HSIM_E_PARAM, "site type outside 0..7");
+        t[k] = v;
+    }
+    P->type.swap(t);
+    if (P->sweep_on_device) P->d_type.upload(P->type);
 }
 
 void hsim_plan_s::upload_energy()

@@ -25,7 +25,7 @@ namespace {
 
 // LDS of a replica-lane block: the tile sums ([kRepWaves][64][5]) and, reused,
 // the history reductions (chunk quarters [4][6][32], final eighths [8][6][32]).
-constexpr int kRedDoubles = kRepWaves * 64 * 5 > 8 * 6 * 32 ? kRepWaves * 64 * 5 : 8 * 6 * 32;
+constexpr int kRedDoubles = kRepWaves * 64 * 6 > 8 * 6 * 32 ? kRepWaves * 64 * 6 : 8 * 6 * 32;
 
 __device__ __forceinline__ bool rep_recompute_due(uint32_t m, int P)
 {
@@ -34,7 +34,7 @@ __device__ __forceinline__ bool rep_recompute_due(uint32_t m, int P)
 
 // History accumulators of one lane without branches: energy change and count
 // of accepted moves, and the final spin of every live site.
-__device__ __forceinline__ void accumulate(double (&acc)[5], bool ok, bool live, float dE, float x,
+__device__ __forceinline__ void accumulate(double (&acc)[6], bool ok, bool live, float dE, float x,
                                            float y, float z)
 {
     acc[0] += ok ? (double)dE : 0.0;
@@ -79,12 +79,33 @@ struct RepSite {
     }
 };
 
+// Trial of site i for one lane: the random move, or (POL) the move of the
+// site's type, with the lane's replica width for the adaptive move; ad tells
+// whether the move is adaptive (its accepts steer the width).
+template <bool POL>
+__device__ __forceinline__ Trial32 rep_trial(const RepLaneArgs &a, const RunArgs &ra, int i,
+                                             uint32_t orig, uint32_t g, uint32_t rid, float sx,
+                                             float sy, float sz, float sigma, bool &ad)
+{
+    const uint4 w = draw(ra.seed, orig, g, rid, 0);
+    ad = false;
+    if constexpr (!POL) {
+        return trial32(w);
+    } else {
+        const SitePol pl = pick_policy(ra.pol.pol, ra.pol.param, ra.pol.cos_t, a.type ? a.type[i] : 0);
+        ad = pl.pol == POL_ADAPTIVE;
+        if (pl.pol == POL_RANDOM) return trial32(w);
+        return trial32_policy(pl.pol, w, sx, sy, sz, ad ? sigma : (float)pl.param,
+                              (float)(1.0 - pl.cos_t), ra.seed, orig, g, rid);
+    }
+}
+
 // Update site i for replica lane r (spin column r of the [3][n][Rp] array),
 // generic CSR row walk (rows of any degree).
-template <int KM, int FM>
+template <int KM, int FM, bool POL>
 __device__ __forceinline__ void rep_site_update(const RepLaneArgs &a, int i, int r, uint32_t g,
                                                 float beta, float b, uint32_t rid, bool active,
-                                                const RunArgs &ra, double (&acc)[5])
+                                                float sigma, const RunArgs &ra, double (&acc)[6])
 {
     const size_t plane = (size_t)a.n * a.Rp;
     float *S = a.spins + r;
@@ -103,10 +124,12 @@ __device__ __forceinline__ void rep_site_update(const RepLaneArgs &a, int i, int
     hz = fmaf(b, sp.nz, hz);
     const size_t oi = (size_t)i * a.Rp;
     const float sx = S[oi], sy = S[plane + oi], sz = S[2 * plane + oi];
-    const Trial32 t = trial32(draw(ra.seed, a.orig[i], g, rid, 0));
+    bool ad;
+    const Trial32 t = rep_trial<POL>(a, ra, i, a.orig[i], g, rid, sx, sy, sz, sigma, ad);
     const float dE = (KM == K_NONE) ? delta_e32_iso(sx, sy, sz, t, hx, hy, hz)
                                     : delta_e32(sx, sy, sz, t, hx, hy, hz, sp.k, sp.ex, sp.ey, sp.ez);
     const bool ok = accept32(dE, beta, t.u) && active;
+    acc[5] += (ok && ad) ? 1.0 : 0.0;
     if (active && dE != dE) atomicOr(&ra.ctl->status, 1u);
     if (ok) {
         S[oi] = t.x;
@@ -157,11 +180,11 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t rs, int32_t lane_b
 // all loads of the step are issued before any store (sites of one colour
 // class are never neighbours); the own rows are written back whole.  Row entries are wave-uniform scalar loads;
 // spin rows go through the buffer descriptors with the row in soffset.
-template <int KM, int FM, int MAXD>
+template <int KM, int FM, int MAXD, bool POL>
 __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const SpinPlanes &sp3,
                                                  int i0, int ce, int r, uint32_t g, float beta,
-                                                 float b, uint32_t rid, bool active,
-                                                 const RunArgs &ra, double (&acc)[5])
+                                                 float b, uint32_t rid, bool active, float sigma,
+                                                 const RunArgs &ra, double (&acc)[6])
 {
     constexpr int NS = kRepSitesPerStep;
     const int32_t lane_b = r * 4;        // byte offset of this replica inside a row
@@ -195,12 +218,15 @@ __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const Spi
         const float fx = fmaf(b, sp.nx, hx[u]);
         const float fy = fmaf(b, sp.ny, hy[u]);
         const float fz = fmaf(b, sp.nz, hz[u]);
-        const Trial32 t = trial32(draw(ra.seed, cload(a.orig, i), g, rid, 0));
+        bool ad;
+        const Trial32 t = rep_trial<POL>(a, ra, i, cload(a.orig, i), g, rid, sx[u], sy[u], sz[u],
+                                         sigma, ad);
         const float dE = (KM == K_NONE) ? delta_e32_iso(sx[u], sy[u], sz[u], t, fx, fy, fz)
                                         : delta_e32(sx[u], sy[u], sz[u], t, fx, fy, fz, sp.k, sp.ex,
                                                     sp.ey, sp.ez);
         const bool live = active && valid[u];
         const bool ok = accept32(dE, beta, t.u) && live;
+        acc[5] += (ok && ad) ? 1.0 : 0.0;
         if (live && dE != dE) atomicOr(&ra.ctl->status, 1u);
         const int32_t oi = i * a.Rp * 4;
         // every live lane stores (the old value when rejected): whole rows
@@ -216,10 +242,11 @@ __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const Spi
 
 // Two sites of one lane group at once: all loads of both sites are issued
 // before either stores (sites of one colour class are never neighbours).
-template <int KM, int FM, int MAXD>
+template <int KM, int FM, int MAXD, bool POL>
 __device__ __forceinline__ void rep_pair_update(const RepLaneArgs &a, int i0, int ce, int r,
                                                 uint32_t g, float beta, float b, uint32_t rid,
-                                                bool active, const RunArgs &ra, double (&acc)[5])
+                                                bool active, float sigma, const RunArgs &ra,
+                                                double (&acc)[6])
 {
     const size_t plane = (size_t)a.n * a.Rp;
     float *S = a.spins + r;
@@ -253,12 +280,14 @@ __device__ __forceinline__ void rep_pair_update(const RepLaneArgs &a, int i0, in
         const float fx = fmaf(b, sp.nx, hx[u]);
         const float fy = fmaf(b, sp.ny, hy[u]);
         const float fz = fmaf(b, sp.nz, hz[u]);
-        const Trial32 t = trial32(draw(ra.seed, a.orig[i], g, rid, 0));
+        bool ad;
+        const Trial32 t = rep_trial<POL>(a, ra, i, a.orig[i], g, rid, sx[u], sy[u], sz[u], sigma, ad);
         const float dE = (KM == K_NONE) ? delta_e32_iso(sx[u], sy[u], sz[u], t, fx, fy, fz)
                                         : delta_e32(sx[u], sy[u], sz[u], t, fx, fy, fz, sp.k, sp.ex,
                                                     sp.ey, sp.ez);
         const bool live = active && valid[u];
         const bool ok = accept32(dE, beta, t.u) && live;
+        acc[5] += (ok && ad) ? 1.0 : 0.0;
         if (live && dE != dE) atomicOr(&ra.ctl->status, 1u);
         const size_t oi = (size_t)i * a.Rp;
         if (ok) {
@@ -339,59 +368,65 @@ __device__ __forceinline__ int xcd_tile(int b, int nt)
 }
 
 // One tile of one colour phase: the body shared by the per-phase kernel and
-// the persistent kernel.  red: LDS [kRepWaves][64][5].  MAXD > 0: rows of at
-// most MAXD entries staged in LDS; MAXD == 0: generic row walk.
-template <int KM, int FM, int W, int MAXD>
+// the persistent kernel.  red: LDS [kRepWaves][64][NQ].  MAXD > 0: rows padded
+// to MAXD entries; MAXD == 0: generic row walk.  POL: update policies (the
+// tile also records its accepted adaptive moves, field 6).
+template <int KM, int FM, int W, int MAXD, bool POL = false>
 __device__ __forceinline__ void rep_tile(const RepLaneArgs &a, int colour, int tile, int group,
                                          uint32_t g, const RunArgs &ra, double *part,
                                          double *red)
 {
     constexpr int SPL = kRepSitesPerWave * W / 64;   // sites per lane group
+    constexpr int NQ = POL ? 6 : 5;
     const Lanes<W> L(group);
     const int ce = a.cls_off[colour + 1];
     const int wbase = a.cls_off[colour] + tile * kRepTile + L.w * kRepSitesPerWave;
     const int base = wbase + L.sub * SPL;
     const bool active = L.r < a.R;
     const uint32_t s_abs = g / (uint32_t)ra.M;
-    float beta = 0.0f, b = 0.0f;
+    float beta = 0.0f, b = 0.0f, sigma = 0.0f;
     uint32_t rid = 0;
     if (active) {
         const size_t sidx = (size_t)L.r * ra.S_hist + s_abs;
         beta = (float)ra.beta[sidx];
         b = (float)ra.bfield[sidx];
         rid = a.rep_id[L.r];
+        if (POL && ra.pol.adaptive) sigma = (float)ra.sigma[L.r];
     }
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if constexpr (MAXD > 0) {
         const SpinPlanes sp3(a);
         for (int j = 0; j < SPL && base + j < ce; j += (W == 64 ? kRepSitesPerStep : 2)) {
             if constexpr (W == 64)
-                rep_step_uniform<KM, FM, MAXD>(a, sp3, base + j, ce, L.r, g, beta, b, rid, active,
-                                               ra, acc);
+                rep_step_uniform<KM, FM, MAXD, POL>(a, sp3, base + j, ce, L.r, g, beta, b, rid,
+                                                    active, sigma, ra, acc);
             else
-                rep_pair_update<KM, FM, MAXD>(a, base + j, ce, L.r, g, beta, b, rid, active, ra,
-                                              acc);
+                rep_pair_update<KM, FM, MAXD, POL>(a, base + j, ce, L.r, g, beta, b, rid, active,
+                                                   sigma, ra, acc);
         }
     } else {
         for (int j = 0; j < SPL; ++j) {
             const int i = base + j;
             if (i >= ce) break;
-            rep_site_update<KM, FM>(a, i, L.r, g, beta, b, rid, active, ra, acc);
+            rep_site_update<KM, FM, POL>(a, i, L.r, g, beta, b, rid, active, sigma, ra, acc);
         }
     }
 #pragma unroll
-    for (int q = 0; q < 5; ++q) red[(L.w * 64 + L.lane) * 5 + q] = acc[q];
+    for (int q = 0; q < NQ; ++q) red[(L.w * 64 + L.lane) * NQ + q] = acc[q];
     __syncthreads();
     if (threadIdx.x < W) {
-        double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        double v[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] = 0.0;
         for (int ww = 0; ww < kRepWaves; ++ww)
             for (int sb = 0; sb < 64 / W; ++sb)
 #pragma unroll
-                for (int q = 0; q < 5; ++q) v[q] += red[(ww * 64 + sb * W + (int)threadIdx.x) * 5 + q];
+                for (int q = 0; q < NQ; ++q) v[q] += red[(ww * 64 + sb * W + (int)threadIdx.x) * NQ + q];
         const int rr = (int)threadIdx.x + W * group;
         const int tg = a.tile_off[colour] + tile;
 #pragma unroll
         for (int q = 0; q < 5; ++q) part[((size_t)tg * kRecFields + q) * a.Rp + rr] = v[q];
+        if constexpr (POL) part[((size_t)tg * kRecFields + 6) * a.Rp + rr] = v[5];
     }
     __syncthreads();
 }
@@ -559,15 +594,39 @@ __device__ __forceinline__ double *rep_chunk_slot(const RunArgs &ra, const RepLa
 }
 
 // Per-phase kernel: grid (tiles of the colour, replica groups).
-template <int KM, int FM, int W, int MAXD>
+template <int KM, int FM, int W, int MAXD, bool POL>
 __global__ __launch_bounds__(kRepThreads) void k_rep_phase(RepLaneArgs a, int colour, int t_off,
                                                            int ntiles, RunArgs ra)
 {
     __shared__ double red[kRedDoubles];
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     const int nt = a.tile_off[colour + 1] - a.tile_off[colour];
-    rep_tile<KM, FM, W, MAXD>(a, colour, xcd_tile(blockIdx.x, nt), blockIdx.y, g, ra,
-                              rep_slot(ra, a, ntiles, t_off % ra.rec_win), red);
+    rep_tile<KM, FM, W, MAXD, POL>(a, colour, xcd_tile(blockIdx.x, nt), blockIdx.y, g, ra,
+                                   rep_slot(ra, a, ntiles, t_off % ra.rec_win), red);
+}
+
+// Adaptive widths after MCS t_off of the sequence: the accepted adaptive
+// moves of every replica (record field 6 of all tiles of the MCS, summed in
+// sixteen fixed strided parts, then the parts in order) steer its width.
+__global__ __launch_bounds__(1024) void k_rep_sigma(RepLaneArgs a, int ntiles, int t_off, RunArgs ra)
+{
+    __shared__ double parts[16 * 64];
+    const double *rec = rep_slot(ra, a, ntiles, t_off % ra.rec_win);
+    for (int r0 = 0; r0 < a.R; r0 += 64) {
+        const int rl = threadIdx.x & 63, k = threadIdx.x >> 6, r = r0 + rl;
+        double v = 0.0;
+        if (r < a.R)
+            for (int tg = k; tg < ntiles; tg += 16) v += rec[((size_t)tg * kRecFields + 6) * a.Rp + r];
+        parts[k * 64 + rl] = v;
+        __syncthreads();
+        if (threadIdx.x < 64 && r < a.R) {
+            double n = 0.0;
+            for (int q = 0; q < 16; ++q) n += parts[q * 64 + rl];
+            ra.sigma[r] = adapted_sigma(ra.sigma[r], n, ra.n_ad[r], ra.pol.sigma_min,
+                                        ra.pol.sigma_max);
+        }
+        __syncthreads();
+    }
 }
 
 template <int KM, int FM, int W, int MAXD>
@@ -865,9 +924,20 @@ hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour, in
     dim3 grid((unsigned)nt, (unsigned)(a.Rp / Wd));
     dim3 blk(kRepThreads);
     HSIM_DISPATCH_KFW(kmode, fmode, Wd, HSIM_DISPATCH_D(a.ell_w, {
-        hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD>), grid, blk, 0, st, a, colour, t_off,
-                           ntiles, ra);
+        if (ra.pol.n_types > 0)
+            hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD, true>), grid, blk, 0, st, a, colour,
+                               t_off, ntiles, ra);
+        else
+            hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD, false>), grid, blk, 0, st, a, colour,
+                               t_off, ntiles, ra);
     }));
+    return hipGetLastError();
+}
+
+hipError_t launch_rep_sigma(hipStream_t st, const RepLaneArgs &a, int ntiles, int t_off,
+                            const RunArgs &ra)
+{
+    hipLaunchKernelGGL(k_rep_sigma, dim3(1), dim3(1024), 0, st, a, ntiles, t_off, ra);
     return hipGetLastError();
 }
 

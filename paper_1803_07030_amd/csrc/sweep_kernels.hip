@@ -52,6 +52,11 @@ __device__ __forceinline__ bool recompute_due(uint32_t m, int P)
     return m == 0 || (P > 0 && (m % (uint32_t)P) == 0);
 }
 
+__device__ __forceinline__ void adapt_sigma(const RunArgs &ra, int r, double n_acc)
+{
+    ra.sigma[r] = adapted_sigma(ra.sigma[r], n_acc, ra.n_ad[r], ra.pol.sigma_min, ra.pol.sigma_max);
+}
+
 template <typename T>
 __device__ __forceinline__ T as_t(double v)
 {
@@ -138,10 +143,11 @@ __device__ __forceinline__ void exchange_field(const RepDesc &rd, const T *S, in
     }
 }
 
+// sigma: the replica's adaptive width; ad counts accepted adaptive moves.
 template <typename T, int KM, int FM, bool TRACE, int MAXD>
 __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint32_t g,
                                             const RunArgs &ra, int rep, T beta, T b,
-                                            double (&acc)[5])
+                                            double sigma, double (&acc)[5], double &ad)
 {
     const int np = rd.n_pad;
     const SiteParams<T, KM, FM> sp(rd, i);
@@ -151,11 +157,20 @@ __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint
     T nx, ny, nz, dE;
     T hx, hy, hz;
     exchange_field<T, MAXD>(rd, S, i, hx, hy, hz);
+    SitePol pl{POL_RANDOM, 0.0, 1.0};
+    if (ra.pol.n_types > 0) {
+        pl = pick_policy(ra.pol.pol, ra.pol.param, ra.pol.cos_t, rd.type ? rd.type[i] : 0);
+        if (pl.pol == POL_ADAPTIVE) pl.param = sigma;
+    }
     if constexpr (sizeof(T) == 4) {
         hx = fmaf(b, sp.nx, hx);
         hy = fmaf(b, sp.ny, hy);
         hz = fmaf(b, sp.nz, hz);
-        const Trial32 t = trial32(draw(ra.seed, orig, g, rd.rep_id, 0));
+        const uint4 w0 = draw(ra.seed, orig, g, rd.rep_id, 0);
+        const Trial32 t = pl.pol == POL_RANDOM
+                              ? trial32(w0)
+                              : trial32_policy(pl.pol, w0, sx, sy, sz, (float)pl.param,
+                                               (float)(1.0 - pl.cos_t), ra.seed, orig, g, rd.rep_id);
         dE = (KM == K_NONE) ? delta_e32_iso(sx, sy, sz, t, hx, hy, hz)
                             : delta_e32(sx, sy, sz, t, hx, hy, hz, sp.k, sp.ex, sp.ey, sp.ez);
         acc_move = accept32(dE, beta, t.u);
@@ -167,10 +182,16 @@ __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint
         hy = hy + b * sp.ny;
         hz = hz + b * sp.nz;
         double dd;
-        acc_move = update64(ra.seed, orig, g, rd.rep_id, sx, sy, sz, hx, hy, hz, sp.k, sp.ex,
-                            sp.ey, sp.ez, beta, nx, ny, nz, dd);
+        if (pl.pol == POL_RANDOM)
+            acc_move = update64(ra.seed, orig, g, rd.rep_id, sx, sy, sz, hx, hy, hz, sp.k, sp.ex,
+                                sp.ey, sp.ez, beta, nx, ny, nz, dd);
+        else
+            acc_move = update64_policy(pl.pol, pl.param, pl.cos_t, ra.seed, orig, g, rd.rep_id, sx,
+                                       sy, sz, hx, hy, hz, sp.k, sp.ex, sp.ey, sp.ez, beta, nx, ny,
+                                       nz, dd);
         dE = dd;
     }
+    ad += (pl.pol == POL_ADAPTIVE && acc_move) ? 1.0 : 0.0;
     if (dE != dE) atomicOr(&ra.ctl->status, 1u);
     if (acc_move) {
         S[i] = nx;
@@ -310,7 +331,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_phase(const RepDesc *__rest
                                                            const Tile *__restrict__ tiles,
                                                            int tile_off, int t_off, RunArgs ra)
 {
-    __shared__ double red[(kSiteBlock / 64) * 5];
+    __shared__ double red[(kSiteBlock / 64) * 6];
     const Tile t = tiles[tile_off + blockIdx.x];
     const RepDesc &rd = reps[t.rep];
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
@@ -318,15 +339,20 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_phase(const RepDesc *__rest
     const size_t sidx = (size_t)t.rep * ra.S_hist + s_abs;
     const T beta = (T)ra.beta[sidx];
     const T b = (T)ra.bfield[sidx];
+    const double sigma = ra.pol.adaptive ? ra.sigma[t.rep] : 0.0;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double ad = 0.0;
     const int i = t.begin + (int)threadIdx.x;
     if (i < t.end)
-        site_update<T, KM, FM, TRACE, MAXD>(rd, (T *)rd.spins, i, g, ra, t.rep, beta, b, acc);
-    block_sum<5>(acc, red);
+        site_update<T, KM, FM, TRACE, MAXD>(rd, (T *)rd.spins, i, g, ra, t.rep, beta, b, sigma,
+                                            acc, ad);
+    double v[6] = {acc[0], acc[1], acc[2], acc[3], acc[4], ad};
+    block_sum<6>(v, red);
     if (threadIdx.x == 0) {
         double *rec = ra.partials + (size_t)(tile_off + blockIdx.x) * kRecSite;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) rec[q] = acc[q];
+        for (int q = 0; q < 5; ++q) rec[q] = v[q];
+        rec[6] = v[5];
     }
 }
 
@@ -361,17 +387,18 @@ __global__ __launch_bounds__(256) void k_site_reduce(const int32_t *__restrict__
     const int lane = threadIdx.x & 63;
     const int r = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
     if (r >= ra.R) return;
-    double v[6] = {0, 0, 0, 0, 0, 0};
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int c = 0; c < ncol_max; ++c) {
         const int tb = rep_tiles[(r * ncol_max + c) * 2], te = rep_tiles[(r * ncol_max + c) * 2 + 1];
         for (int tt = tb + lane; tt < te; tt += 64) {
             const double *rec = ra.partials + (size_t)tt * kRecSite;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) v[q] += rec[q];
+            for (int q = 0; q < 7; ++q) v[q] += rec[q];
         }
     }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) v[q] = wave_sum(v[q]);
+    for (int q = 0; q < 7; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0 && ra.pol.adaptive) adapt_sigma(ra, r, v[6]);
     if (lane == 0) {
         const double E = (rec_due ? v[5] : ra.ecarry[r]) + v[0];
         ra.ecarry[r] = E;
@@ -458,7 +485,7 @@ template <typename T, int KM, int FM, bool TRACE, bool LDS, int MAXD>
 __global__ __launch_bounds__(1024) void k_block_sweep(const RepDesc *__restrict__ reps, RunArgs ra)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[16 * 5];
+    __shared__ double red[16 * 6];
     const int rep = blockIdx.x;
     const RepDesc &rd = reps[rep];
     const int np = rd.n_pad, n = rd.n;
@@ -487,23 +514,28 @@ __global__ __launch_bounds__(1024) void k_block_sweep(const RepDesc *__restrict_
         }
         const T beta = (T)ra.beta[sidx];
         const T b = (T)bd;
+        const double sigma = ra.pol.adaptive ? ra.sigma[rep] : 0.0;
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        double ad = 0.0;
         for (int c = 0; c < rd.ncol; ++c) {
             const int ce = rd.cls_off[c + 1];
             for (int i = rd.cls_off[c] + threadIdx.x; i < ce; i += blockDim.x)
-                site_update<T, KM, FM, TRACE, MAXD>(rd, S, i, g, ra, rep, beta, b, acc);
+                site_update<T, KM, FM, TRACE, MAXD>(rd, S, i, g, ra, rep, beta, b, sigma, acc, ad);
             __syncthreads();
         }
-        block_sum<5>(acc, red);
+        double v[6] = {acc[0], acc[1], acc[2], acc[3], acc[4], ad};
+        block_sum<6>(v, red);
         if (threadIdx.x == 0) {
-            E = E + acc[0];
+            E = E + v[0];
             double *h = ra.history + (sidx * ra.M + m) * 5;
             h[0] = E;
-            h[1] = acc[1];
-            h[2] = acc[2];
-            h[3] = acc[3];
-            h[4] = acc[4];
+            h[1] = v[1];
+            h[2] = v[2];
+            h[3] = v[3];
+            h[4] = v[4];
+            if (ra.pol.adaptive) adapt_sigma(ra, rep, v[5]);
         }
+        __syncthreads();
     }
     if (threadIdx.x == 0) ra.ecarry[rep] = E;
     if (LDS) {

@@ -19,6 +19,9 @@ FP32, FP64_EXACT = 0, 1
 LAYOUT_AUTO, LAYOUT_SITE, LAYOUT_REPLICA, LAYOUT_BLOCK = 0, 1, 2, 3
 LAUNCH_PLAIN, LAUNCH_PERSISTENT, LAUNCH_GRAPH, LAUNCH_AUTO = 0, 1, 2, 3
 INIT_GIVEN, INIT_COLD_Z, INIT_RANDOM = 0, 1, 2
+(POLICY_RANDOM, POLICY_FLIP, POLICY_SMALL_STEP, POLICY_GAUSSIAN, POLICY_HN,
+ POLICY_ADAPTIVE) = range(6)
+SIGMA_MIN, SIGMA_MAX = 1e-4, 60.0
 RUN_TRACE_ACCEPTS = 0x1
 LAYOUT_NAMES = {1: "site", 2: "replica", 3: "block"}
 
@@ -65,6 +68,9 @@ _SIGNATURES = {
     "hsim_batch_status": [_vp, _vp],
     "hsim_autotune": [_vp, ctypes.c_char_p, _i32, _vp],
     "hsim_batch_time_phases": [_vp, _i32],
+    "hsim_plan_set_types": [_vp, _vp],
+    "hsim_batch_set_policies": [_vp, _i32, _vp, _vp, _dbl, _dbl],
+    "hsim_batch_sigma": [_vp, _vp],
     "hsim_batch_phase_times": [_vp, _vp, _vp, _vp],
     "hsim_energy_forward": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp],
     "hsim_energy_backward": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp,
@@ -145,6 +151,11 @@ def hsim_plan_bonds(plan):
     return ij[:2 * nb.value].reshape(nb.value, 2)
 
 
+def hsim_plan_set_types(plan, site_type):
+    t = None if site_type is None else np.ascontiguousarray(site_type, dtype=np.int32)
+    _check(lib().hsim_plan_set_types(plan, _ptr(t)))
+
+
 def hsim_plan_destroy(plan):
     lib().hsim_plan_destroy(plan)
 
@@ -203,6 +214,20 @@ def hsim_batch_status(batch):
 def hsim_autotune(batch, cache_path=None, trial_mcs=20):
     cp = None if cache_path is None else cache_path.encode()
     _check(lib().hsim_autotune(batch, cp, trial_mcs, _stream()))
+
+
+def hsim_batch_set_policies(batch, policies, sigma_min=SIGMA_MIN, sigma_max=SIGMA_MAX):
+    pol = np.ascontiguousarray([int(a) for a, _ in policies], dtype=np.int32)
+    prm = np.ascontiguousarray([float(b) for _, b in policies], dtype=np.float64)
+    _check(lib().hsim_batch_set_policies(batch, len(policies), _ptr(pol) if len(pol) else None,
+                                         _ptr(prm) if len(prm) else None, float(sigma_min),
+                                         float(sigma_max)))
+
+
+def hsim_batch_sigma(batch, n_rep):
+    out = np.empty(n_rep)
+    _check(lib().hsim_batch_sigma(batch, _ptr(out)))
+    return out
 
 
 def hsim_batch_time_phases(batch, every):
@@ -265,6 +290,10 @@ class Plan:
     def bonds(self):
         return hsim_plan_bonds(self.handle)
 
+    def set_types(self, site_type):
+        """Site types (user order, 0..7), or None for type 0 everywhere."""
+        hsim_plan_set_types(self.handle, site_type)
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and _lib is not None:
@@ -326,6 +355,17 @@ class Batch:
 
     def autotune(self, cache_path=None, trial_mcs=20):
         hsim_autotune(self.handle, cache_path, trial_mcs)
+
+    def set_policies(self, policies, sigma_min=SIGMA_MIN, sigma_max=SIGMA_MAX):
+        """policies: list of (POLICY_*, param) per site type; [] for the
+        random move everywhere."""
+        hsim_batch_set_policies(self.handle, policies, sigma_min, sigma_max)
+        return self
+
+    def sigma(self):
+        """Current adaptive width of every replica (host array)."""
+        torch.cuda.current_stream().synchronize()
+        return hsim_batch_sigma(self.handle, self.R)
 
     def time_phases(self, every):
         hsim_batch_time_phases(self.handle, every)

@@ -118,3 +118,28 @@ def test_batch_layouts_sizes_and_errors():
     _expect(-4, lambda: hsim.hsim_batch_run(b.handle, 0, np.ones((1, 1)), np.zeros((1, 1))))
     _expect(-4, lambda: hsim.hsim_batch_init_spins(b.handle, hsim.INIT_COLD_Z))
     _expect(-1, lambda: hsim.hsim_batch_create([], 0))
+
+
+def test_site_types_and_policies_validation():
+    """Site types are 0..7; every policy id and parameter is checked, and a
+    batch refuses policies that leave one of its site types without a move.
+    Reading the adaptive width needs a bound batch."""
+    lat = synth.sc_periodic(6)
+    p = hsim.Plan(lat)
+    _expect(-3, lambda: p.set_types(np.full(lat.n, 8)))
+    _expect(-3, lambda: p.set_types(np.full(lat.n, -1)))
+    p.set_types(np.arange(lat.n) % 3)
+    b = hsim.Batch([p] * 2, seed=0, precision=hsim.FP64_EXACT, layout=hsim.LAYOUT_SITE)
+    R, F, S, G, H, A = (hsim.POLICY_RANDOM, hsim.POLICY_FLIP, hsim.POLICY_SMALL_STEP,
+                        hsim.POLICY_GAUSSIAN, hsim.POLICY_HN, hsim.POLICY_ADAPTIVE)
+    _expect(-3, lambda: b.set_policies([(R, 0.0), (F, 0.0)]))             # type 2 uncovered
+    _expect(-1, lambda: b.set_policies([(R, 0.0), (F, 0.0), (9, 0.0)]))
+    _expect(-3, lambda: b.set_policies([(R, 0.0), (F, 0.0), (S, 0.0)]))
+    _expect(-3, lambda: b.set_policies([(R, 0.0), (F, 0.0), (H, 4.0)]))
+    _expect(-3, lambda: b.set_policies([(R, 0.0), (F, 0.0), (G, -1.0)]))
+    _expect(-3, lambda: b.set_policies([(R, 0.0), (F, 0.0), (A, 1.0)], sigma_min=0.0))
+    _expect(-1, lambda: hsim.hsim_batch_set_policies(b.handle, [(R, 0.0)] * 9))
+    b.set_policies([(R, 0.0), (S, 0.5), (A, 0.7)])
+    b.set_policies([])
+    _expect(-4, lambda: hsim.hsim_batch_sigma(b.handle, 2))
+    p.set_types(None)
