@@ -44,6 +44,11 @@ def parse():
     ap.add_argument("--cpu-mcs", type=int, default=400, help="MCS per thread of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--policy", default="random",
+                    choices=["random", "flip", "small_step", "gaussian", "hn", "adaptive"],
+                    help="update policy of every site (sc64 workload): random (the headline), "
+                         "flip, small step (30 degrees), Gaussian (sigma 0.5), Hinzke-Nowak "
+                         "(30 degrees), adaptive (sigma from 1.0)")
     ap.add_argument("--workload", default="sc64", choices=["sc64", "films"],
                     help="sc64: the headline workload; films: 256 diluted films, one replica "
                          "each (site-lane layout), for the site-lane kernel's numbers")
@@ -134,6 +139,11 @@ def main():
         plan = hsim.Plan(lat)
         batch = hsim.Batch([plan] * R, seed=SEED, precision=hsim.FP32,
                            layout=hsim.LAYOUT_REPLICA).bind(1, args.mcs)
+        if args.policy != "random":
+            pol = {"flip": (hsim.POLICY_FLIP, 0.0), "small_step": (hsim.POLICY_SMALL_STEP, np.pi / 6),
+                   "gaussian": (hsim.POLICY_GAUSSIAN, 0.5), "hn": (hsim.POLICY_HN, np.pi / 6),
+                   "adaptive": (hsim.POLICY_ADAPTIVE, 1.0)}[args.policy]
+            batch.set_policies([pol])
         Tm = T[:, None]
         timed_phases = args.launch == "plain" and args.time_every > 0
 
@@ -189,9 +199,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"sc{L}^3 periodic J=1 K={K_ANI} z, {R} replicas T=0.1..3.0, "
                                f"{args.mcs} MCS, cold start, f32 spins, f64 history, "
-                               f"{args.launch} launch, replica-lane layout",
+                               f"{args.launch} launch, replica-lane layout"
+                               + ("" if args.policy == "random" else f", {args.policy} move"),
                    "sites": lat.n, "replicas": R, "mcs": args.mcs,
-                   "updates_per_step": n_upd_step, "launch": args.launch},
+                   "updates_per_step": n_upd_step, "launch": args.launch, "policy": args.policy},
         "acceptance": acc,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -247,6 +247,53 @@ hsim_status hsim_energy_backward(hsim_plan plan, int32_t batch, hsim_precision p
 hsim_status hsim_fluct_estimate(int64_t n, double beta, const double *d_O, const double *d_dE,
                                 const double *d_dO, double *d_out, void *stream);
 
+/* ------------------------------------------------- analysis of the history */
+/* A series is the history of one replica at one step, MCS m0 .. mcs-1 of a
+ * history d_history [n_rep][n_steps][mcs][5] (device, as written by
+ * hsim_batch_run).  Results are per site (k_B = 1), with |M| the length of
+ * the magnetisation vector and <.> the (weighted) mean over the series:
+ *   [0] e = <E>/N            [1] m_abs = <|M|>/N     [2] m2 = <|M|^2>/N^2
+ *   [3] m4 = <|M|^4>/N^4     [4] cv = beta^2 <(E-<E>)^2>/N
+ *   [5] chi = beta <(|M|-<|M|>)^2>/N                 [6] u4 = 1 - m4/(3 m2^2)
+ *   [7] v1 = -<(|M|-<|M|>)(E-<E>)>/<|M|>             [8] v2 = the same with |M|^2
+ * (paper, sections "Thermal averages" and "Critical exponents": M, chi and
+ * the specific heat, and the cumulants of the magnetisation used for
+ * finite-size scaling; v_j = d ln<|M|^j>/d beta).  Every sum is taken in a
+ * fixed order.  All calls return after their kernels have finished on
+ * `stream`; they allocate small device tables of their own. */
+#define HSIM_THERMAL_FIELDS 9
+/* Thermal summary of every series, evaluated at n_eval inverse temperatures
+ * by single-histogram reweighting (paper, section "Histogram and multiple
+ * histogram methods"; weights exp(-(beta' - beta) E_m)):
+ *   beta [n_rep][n_steps] (host): the sampling inverse temperatures;
+ *   beta_eval [n_rep][n_steps][n_eval] (host; NULL with n_eval = 1: beta);
+ *   d_out [n_rep][n_steps][n_eval][9] (device). */
+hsim_status hsim_analysis_thermal(const double *d_history, int32_t n_rep, int32_t n_steps,
+                                  int32_t mcs, int32_t m0, int64_t n_sites, const double *beta,
+                                  int32_t n_eval, const double *beta_eval, double *d_out,
+                                  void *stream);
+/* Integrated autocorrelation time of E (observable 0) or |M| (1) of every
+ * series (paper, section "Dynamic behavior"): tau = 1/2 + sum_{t=1..W} rho(t)
+ * with Sokal's window, W the first lag with W >= c tau (at most the half
+ * length).  d_tau [n_rep][n_steps] double, d_window (NULL or int32, same
+ * shape). */
+hsim_status hsim_analysis_tau(const double *d_history, int32_t n_rep, int32_t n_steps,
+                              int32_t mcs, int32_t m0, int32_t observable, double c,
+                              double *d_tau, int32_t *d_window, void *stream);
+/* Multiple-histogram method (paper, section "Histogram and multiple
+ * histogram methods"; Ferrenberg and Swendsen 1989) over K series
+ * series [K][2] = (replica, step) (host) sampled at beta_k [K] (host): the
+ * free energies f_k (f_0 = 0) from the self-consistent equations, iterated
+ * in log space until max |f_new - f| < tol or max_iter iterations
+ * (f_out [K] host, *iters_out), then the thermal summary at beta_eval [n_eval]
+ * (host) into d_out [n_eval][9] (device). */
+hsim_status hsim_analysis_multihist(const double *d_history, int32_t n_rep, int32_t n_steps,
+                                    int32_t mcs, int32_t m0, int64_t n_sites, int32_t K,
+                                    const int32_t *series, const double *beta_k, int32_t n_eval,
+                                    const double *beta_eval, int32_t max_iter, double tol,
+                                    double *f_out, int32_t *iters_out, double *d_out,
+                                    void *stream);
+
 const char *hsim_last_error(void);
 const char *hsim_version(void);
 

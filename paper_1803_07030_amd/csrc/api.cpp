@@ -28,6 +28,15 @@ void batch_time_phases_impl(hsim_batch, int32_t);
 void plan_set_types_impl(hsim_plan, const int32_t *);
 void batch_set_policies_impl(hsim_batch, int32_t, const int32_t *, const double *, double, double);
 void batch_sigma_impl(hsim_batch, double *);
+namespace hsim {
+void analysis_thermal_impl(const double *, int32_t, int32_t, int32_t, int32_t, int64_t,
+                           const double *, int32_t, const double *, double *, hipStream_t);
+void analysis_tau_impl(const double *, int32_t, int32_t, int32_t, int32_t, int32_t, double,
+                       double *, int32_t *, hipStream_t);
+void analysis_multihist_impl(const double *, int32_t, int32_t, int32_t, int32_t, int64_t, int32_t,
+                             const int32_t *, const double *, int32_t, const double *, int32_t,
+                             double, double *, int32_t *, double *, hipStream_t);
+}  // namespace hsim
 void batch_phase_times_impl(hsim_batch, double *, int64_t *, int64_t *);
 
 namespace {
@@ -237,6 +246,40 @@ hsim_status hsim_fluct_estimate(int64_t n, double beta, const double *d_O, const
         if (n < 1 || !d_O || !d_dE || !d_out) throw hsim::Error(HSIM_E_ARG, "fluct_estimate: bad argument");
         if (!std::isfinite(beta) || beta < 0) throw hsim::Error(HSIM_E_PARAM, "beta must be finite and >= 0");
         hsim::hip_check(hsim::launch_fluct(S(stream), n, beta, d_O, d_dE, d_dO, d_out), "fluct launch");
+    });
+}
+
+hsim_status hsim_analysis_thermal(const double *d_history, int32_t n_rep, int32_t n_steps,
+                                  int32_t mcs, int32_t m0, int64_t n_sites, const double *beta,
+                                  int32_t n_eval, const double *beta_eval, double *d_out,
+                                  void *stream)
+{
+    return guarded([&] {
+        hsim::analysis_thermal_impl(d_history, n_rep, n_steps, mcs, m0, n_sites, beta, n_eval,
+                                    beta_eval, d_out, S(stream));
+    });
+}
+
+hsim_status hsim_analysis_tau(const double *d_history, int32_t n_rep, int32_t n_steps,
+                              int32_t mcs, int32_t m0, int32_t observable, double c,
+                              double *d_tau, int32_t *d_window, void *stream)
+{
+    return guarded([&] {
+        hsim::analysis_tau_impl(d_history, n_rep, n_steps, mcs, m0, observable, c, d_tau, d_window,
+                                S(stream));
+    });
+}
+
+hsim_status hsim_analysis_multihist(const double *d_history, int32_t n_rep, int32_t n_steps,
+                                    int32_t mcs, int32_t m0, int64_t n_sites, int32_t K,
+                                    const int32_t *series, const double *beta_k, int32_t n_eval,
+                                    const double *beta_eval, int32_t max_iter, double tol,
+                                    double *f_out, int32_t *iters_out, double *d_out, void *stream)
+{
+    return guarded([&] {
+        hsim::analysis_multihist_impl(d_history, n_rep, n_steps, mcs, m0, n_sites, K, series,
+                                      beta_k, n_eval, beta_eval, max_iter, tol, f_out, iters_out,
+                                      d_out, S(stream));
     });
 }
 

@@ -365,6 +365,7 @@ hsim::RunArgs hsim_batch_s::run_args(uint32_t g0, int n_mcs, int P, uint32_t *tr
     if (layout == HSIM_LAYOUT_REPLICA) {
         a.chunks = a.partials + (size_t)rec_win * rep_ntiles * hsim::kRecFields * Rp;
         a.carry = a.chunks + (size_t)rec_win * hsim::kChunks * 6 * Rp;
+        a.sig_part = a.carry + (size_t)rec_win * 6 * Rp;
     }
     a.rec_win = rec_win;
     a.pol = pol;

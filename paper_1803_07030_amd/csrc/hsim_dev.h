@@ -106,6 +106,7 @@ struct RunArgs {
     Policies pol;
     double *sigma;        // [R] adaptive width (when pol.adaptive)
     const double *n_ad;   // [R] sites under the adaptive move per replica
+    double *sig_part;     // replica layout: [kChunks][Rp] partial adaptive accepts
 };
 
 struct RepLaneArgs {

@@ -133,10 +133,12 @@ struct hsim_batch_s {
     size_t off_sigma = 0;
     void reset_sigma();             // every replica's adaptive width to sigma0
     int32_t rec_win = 2;              // replica layout: MCS per record window
-    // replica layout: bytes of the record window, its chunk sums and totals
+    // replica layout: bytes of the record window, its chunk sums and totals,
+    // and the partial adaptive-accept sums
     size_t rep_rec_bytes() const
     {
-        return (size_t)rec_win * ((size_t)rep_ntiles * hsim::kRecFields + (size_t)hsim::kChunks * 6 + 6) * Rp * 8;
+        return ((size_t)rec_win * ((size_t)rep_ntiles * hsim::kRecFields + (size_t)hsim::kChunks * 6 + 6) +
+                (size_t)hsim::kChunks) * Rp * 8;
     }
     hsim::RepLaneArgs la{};
 

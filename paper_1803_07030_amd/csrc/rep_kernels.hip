@@ -606,27 +606,32 @@ __global__ __launch_bounds__(kRepThreads) void k_rep_phase(RepLaneArgs a, int co
 }
 
 // Adaptive widths after MCS t_off of the sequence: the accepted adaptive
-// moves of every replica (record field 6 of all tiles of the MCS, summed in
-// sixteen fixed strided parts, then the parts in order) steer its width.
-__global__ __launch_bounds__(1024) void k_rep_sigma(RepLaneArgs a, int ntiles, int t_off, RunArgs ra)
+// moves of every replica (record field 6 of all tiles of the MCS) are summed
+// in kChunks fixed chunks of tiles, one per block, each in tile order; the
+// last block to finish adds the chunks in order and steers every width.
+__global__ __launch_bounds__(256) void k_rep_sigma(RepLaneArgs a, int ntiles, int t_off, RunArgs ra)
 {
-    __shared__ double parts[16 * 64];
+    __shared__ int last;
     const double *rec = rep_slot(ra, a, ntiles, t_off % ra.rec_win);
-    for (int r0 = 0; r0 < a.R; r0 += 64) {
-        const int rl = threadIdx.x & 63, k = threadIdx.x >> 6, r = r0 + rl;
+    const int k = blockIdx.x;
+    const int tb = (int)((int64_t)ntiles * k / kChunks), te = (int)((int64_t)ntiles * (k + 1) / kChunks);
+    for (int r = threadIdx.x; r < a.R; r += blockDim.x) {
         double v = 0.0;
-        if (r < a.R)
-            for (int tg = k; tg < ntiles; tg += 16) v += rec[((size_t)tg * kRecFields + 6) * a.Rp + r];
-        parts[k * 64 + rl] = v;
-        __syncthreads();
-        if (threadIdx.x < 64 && r < a.R) {
-            double n = 0.0;
-            for (int q = 0; q < 16; ++q) n += parts[q * 64 + rl];
-            ra.sigma[r] = adapted_sigma(ra.sigma[r], n, ra.n_ad[r], ra.pol.sigma_min,
-                                        ra.pol.sigma_max);
-        }
-        __syncthreads();
+        for (int tg = tb; tg < te; ++tg) v += rec[((size_t)tg * kRecFields + 6) * a.Rp + r];
+        ra.sig_part[(size_t)k * a.Rp + r] = v;
     }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(&ra.ctl->pad[2], 1u) == kChunks - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int r = threadIdx.x; r < a.R; r += blockDim.x) {
+        double n = 0.0;
+        for (int q = 0; q < kChunks; ++q) n += ra.sig_part[(size_t)q * a.Rp + r];
+        ra.sigma[r] = adapted_sigma(ra.sigma[r], n, ra.n_ad[r], ra.pol.sigma_min, ra.pol.sigma_max);
+    }
+    if (threadIdx.x == 0) ra.ctl->pad[2] = 0;
 }
 
 template <int KM, int FM, int W, int MAXD>
@@ -937,7 +942,7 @@ hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour, in
 hipError_t launch_rep_sigma(hipStream_t st, const RepLaneArgs &a, int ntiles, int t_off,
                             const RunArgs &ra)
 {
-    hipLaunchKernelGGL(k_rep_sigma, dim3(1), dim3(1024), 0, st, a, ntiles, t_off, ra);
+    hipLaunchKernelGGL(k_rep_sigma, dim3(kChunks), dim3(256), 0, st, a, ntiles, t_off, ra);
     return hipGetLastError();
 }
 

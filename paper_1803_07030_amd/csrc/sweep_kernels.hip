@@ -242,6 +242,7 @@ __global__ void k_ctl_set(Ctl *ctl, uint32_t g)
         ctl->bar_arrive = 0;
         ctl->pad[0] = 0;
         ctl->pad[1] = 0;
+        ctl->pad[2] = 0;
     }
 }
 

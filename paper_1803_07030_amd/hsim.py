@@ -22,6 +22,7 @@ INIT_GIVEN, INIT_COLD_Z, INIT_RANDOM = 0, 1, 2
 (POLICY_RANDOM, POLICY_FLIP, POLICY_SMALL_STEP, POLICY_GAUSSIAN, POLICY_HN,
  POLICY_ADAPTIVE) = range(6)
 SIGMA_MIN, SIGMA_MAX = 1e-4, 60.0
+THERMAL_FIELDS = ("e", "m_abs", "m2", "m4", "cv", "chi", "u4", "v1", "v2")
 RUN_TRACE_ACCEPTS = 0x1
 LAYOUT_NAMES = {1: "site", 2: "replica", 3: "block"}
 
@@ -76,6 +77,10 @@ _SIGNATURES = {
     "hsim_energy_backward": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp,
                              _vp, _vp],
     "hsim_fluct_estimate": [_i64, _dbl, _vp, _vp, _vp, _vp, _vp],
+    "hsim_analysis_thermal": [_vp, _i32, _i32, _i32, _i32, _i64, _vp, _i32, _vp, _vp, _vp],
+    "hsim_analysis_tau": [_vp, _i32, _i32, _i32, _i32, _i32, _dbl, _vp, _vp, _vp],
+    "hsim_analysis_multihist": [_vp, _i32, _i32, _i32, _i32, _i64, _i32, _vp, _vp, _i32, _vp,
+                                _i32, _dbl, _vp, _vp, _vp, _vp],
 }
 EXPORTED = sorted(list(_SIGNATURES) + ["hsim_plan_destroy", "hsim_batch_destroy",
                                        "hsim_last_error", "hsim_version"])
@@ -266,6 +271,53 @@ def hsim_version():
 
 
 # ------------------------------------------------------------- objects
+def _hist_shape(history):
+    if history.dim() != 4 or history.shape[-1] != 5 or history.dtype != torch.float64:
+        raise ValueError("history must be a float64 tensor [R][S][M][5]")
+    return [int(v) for v in history.shape[:3]]
+
+
+def hsim_analysis_thermal(history, m0, n_sites, beta, beta_eval=None):
+    """Thermal summaries [R][S][n_eval][9] (THERMAL_FIELDS) of every series,
+    at the sampling beta [R][S] or reweighted to beta_eval [R][S][n_eval]."""
+    R, S, M = _hist_shape(history)
+    b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, dtype=np.float64), (R, S)))
+    be = None if beta_eval is None else np.ascontiguousarray(beta_eval, dtype=np.float64).reshape(R, S, -1)
+    ne = 1 if be is None else be.shape[-1]
+    out = torch.empty((R, S, ne, 9), dtype=torch.float64, device=history.device)
+    _check(lib().hsim_analysis_thermal(_ptr(history), R, S, M, m0, n_sites, _ptr(b), ne, _ptr(be),
+                                       _ptr(out), _stream()))
+    return out
+
+
+def hsim_analysis_tau(history, m0, observable=0, c=6.0):
+    """Integrated autocorrelation times [R][S] of E (0) or |M| (1), and windows."""
+    R, S, M = _hist_shape(history)
+    tau = torch.empty((R, S), dtype=torch.float64, device=history.device)
+    win = torch.empty((R, S), dtype=torch.int32, device=history.device)
+    _check(lib().hsim_analysis_tau(_ptr(history), R, S, M, m0, observable, float(c), _ptr(tau),
+                                   _ptr(win), _stream()))
+    return tau, win
+
+
+def hsim_analysis_multihist(history, m0, n_sites, series, beta_k, beta_eval, max_iter=5000,
+                            tol=1e-11):
+    """Multiple-histogram free energies f [K] (f_0 = 0), iterations, and the
+    thermal summaries [n_eval][9] at beta_eval."""
+    R, S, M = _hist_shape(history)
+    sr = np.ascontiguousarray(series, dtype=np.int32).reshape(-1, 2)
+    K = sr.shape[0]
+    bk = np.ascontiguousarray(beta_k, dtype=np.float64)
+    be = np.ascontiguousarray(np.atleast_1d(beta_eval), dtype=np.float64)
+    f = np.empty(K)
+    it = ctypes.c_int32()
+    out = torch.empty((be.size, 9), dtype=torch.float64, device=history.device)
+    _check(lib().hsim_analysis_multihist(_ptr(history), R, S, M, m0, n_sites, K, _ptr(sr), _ptr(bk),
+                                         be.size, _ptr(be), max_iter, float(tol), _ptr(f),
+                                         ctypes.byref(it), _ptr(out), _stream()))
+    return f, it.value, out
+
+
 class Plan:
     """One lattice: CSR neighbours with per-entry J, per-site k/axis/field
     direction (host arrays; copied by the library)."""
