@@ -49,9 +49,10 @@ def parse():
                     help="update policy of every site (sc64 workload): random (the headline), "
                          "flip, small step (30 degrees), Gaussian (sigma 0.5), Hinzke-Nowak "
                          "(30 degrees), adaptive (sigma from 1.0)")
-    ap.add_argument("--workload", default="sc64", choices=["sc64", "films"],
+    ap.add_argument("--workload", default="sc64", choices=["sc64", "films", "policies"],
                     help="sc64: the headline workload; films: 256 diluted films, one replica "
-                         "each (site-lane layout), for the site-lane kernel's numbers")
+                         "each (site-lane layout), for the site-lane kernel's numbers; policies: "
+                         "equilibrium correlation times of every update policy")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (HBM byte-counter calibration)")
     return ap.parse_args()
@@ -131,6 +132,9 @@ def main():
     stream = torch.cuda.Stream()
     if args.workload == "films":
         films_bench(args, stream)
+        return
+    if args.workload == "policies":
+        policies_bench(args, stream)
         return
     lat, T = workload()
     launch = dict(persistent=hsim.LAUNCH_PERSISTENT, graph=hsim.LAUNCH_GRAPH,
@@ -273,6 +277,57 @@ def films_bench(args, stream):
                      "frac": achieved / HBM_PEAK_GBS, "kernel": "k_site_phase",
                      "launch_ms": ph_ms / ph_n, "updates_per_launch": ph_upd / ph_n,
                      "bytes_per_update": balg, "timed_launches": ph_n}}))
+
+
+def policies_bench(args, stream):
+    """Equilibrium correlation times per update policy: SC 32^3 periodic,
+    J = 1, K = 0.1 z, 64 replicas at T = 0.4 .. 1.4 (below the ordering
+    temperature, about 1.44), cold start, one step of `mcs` MCS to
+    equilibrate, then `mcs` MCS measured; integrated autocorrelation times of
+    E and |M| by the library's analysis (Sokal window, c = 6), and the sweep
+    rate."""
+    import torch
+    import synth
+    from paper_1803_07030_amd import hsim
+    L, R = 32, 64
+    mcs = args.mcs if args.mcs != MCS else 4000
+    lat = synth.sc_periodic(L)
+    lat.k = np.full(lat.n, K_ANI)
+    T = np.linspace(0.4, 1.4, R)
+    pols = {"random": None, "small_step_15deg": (hsim.POLICY_SMALL_STEP, np.pi / 12),
+            "small_step_30deg": (hsim.POLICY_SMALL_STEP, np.pi / 6),
+            "gaussian_0.2": (hsim.POLICY_GAUSSIAN, 0.2),
+            "hinzke_nowak_15deg": (hsim.POLICY_HN, np.pi / 12),
+            "hinzke_nowak_30deg": (hsim.POLICY_HN, np.pi / 6),
+            "adaptive": (hsim.POLICY_ADAPTIVE, 1.0)}
+    res = {}
+    with torch.cuda.stream(stream):
+        plan = hsim.Plan(lat)
+        for name, pol in pols.items():
+            b = hsim.Batch([plan] * R, seed=SEED, precision=hsim.FP32,
+                           layout=hsim.LAYOUT_REPLICA).bind(2, mcs)
+            if pol is not None:
+                b.set_policies([pol])
+            b.init_spins(hsim.INIT_COLD_Z)
+            Tm = np.stack([T, T], axis=1)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            b.run(Tm[:, :1], 0.0, first_step=0, launch=hsim.LAUNCH_GRAPH)
+            b.run(Tm[:, 1:], 0.0, first_step=1, launch=hsim.LAUNCH_GRAPH)
+            stream.synchronize()
+            dt = time.perf_counter() - t0
+            assert b.status() == 0
+            h = b.history[:, 1:2].contiguous()
+            tE, _ = hsim.hsim_analysis_tau(h, 0, 0)
+            tM, _ = hsim.hsim_analysis_tau(h, 0, 1)
+            acc = b.history[:, 1, :, 4].mean(dim=1) / lat.n
+            res[name] = {"tau_E": tE[:, 0].cpu().numpy().round(2).tolist(),
+                         "tau_M": tM[:, 0].cpu().numpy().round(2).tolist(),
+                         "acceptance": acc.cpu().numpy().round(3).tolist(),
+                         "updates_per_s": R * lat.n * mcs * 2 / dt}
+    print(json.dumps({"workload": f"sc{L}^3 K={K_ANI} z, {R} replicas T=0.4..1.4, {mcs} MCS "
+                                  f"equilibration, {mcs} MCS measured, f32, replica-lane, graph",
+                      "T": T.round(4).tolist(), "policies": res}))
 
 
 def plain_launch(lat, T, mcs, stream):
