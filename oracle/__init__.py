@@ -48,7 +48,7 @@ def build(force=True):
 class _Lattice(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
                 ("J", ctypes.c_void_p), ("k", ctypes.c_void_p), ("axis", ctypes.c_void_p),
-                ("ndir", ctypes.c_void_p)]
+                ("ndir", ctypes.c_void_p), ("kc", ctypes.c_void_p), ("norm", ctypes.c_void_p)]
 
 
 class _Params(ctypes.Structure):
@@ -124,9 +124,13 @@ class _Lat:
         self.k = None if lat.k is None else np.ascontiguousarray(lat.k, dtype=np.float64)
         self.axis = None if lat.axis is None else np.ascontiguousarray(lat.axis, dtype=np.float64)
         self.ndir = None if lat.ndir is None else np.ascontiguousarray(lat.ndir, dtype=np.float64)
+        kc, norm = getattr(lat, "kc", None), getattr(lat, "norm", None)
+        self.kc = None if kc is None else np.ascontiguousarray(kc, dtype=np.float64)
+        self.norm = None if norm is None else np.ascontiguousarray(norm, dtype=np.float64)
         self.n = int(lat.n)
         self.s = _Lattice(self.n, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.J),
-                          _ptr(self.k), _ptr(self.axis), _ptr(self.ndir))
+                          _ptr(self.k), _ptr(self.axis), _ptr(self.ndir), _ptr(self.kc),
+                          _ptr(self.norm))
 
     @property
     def ref(self):

@@ -324,6 +324,21 @@ static double k_of(const or_lattice *lat, int64_t i)
 {
     return lat->k ? lat->k[i] : 0.0;
 }
+static double kc_of(const or_lattice *lat, int64_t i)
+{
+    return lat->kc ? lat->kc[i] : 0.0;
+}
+static double norm_of(const or_lattice *lat, int64_t i)
+{
+    return lat->norm ? lat->norm[i] : 1.0;
+}
+
+/* Cubic anisotropy function of Eq. 3: Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2. */
+static double cubic_f(const double *s)
+{
+    double a = s[0] * s[0], b = s[1] * s[1], c = s[2] * s[2];
+    return (a * b + b * c) + a * c;
+}
 
 int or_validate(const or_lattice *lat)
 {
@@ -349,7 +364,8 @@ int or_validate(const or_lattice *lat)
         }
     }
     for (int64_t i = 0; i < n; ++i) {
-        if (!isfinite(k_of(lat, i))) return -3;
+        if (!isfinite(k_of(lat, i)) || !isfinite(kc_of(lat, i))) return -3;
+        if (!(norm_of(lat, i) > 0.0) || !isfinite(norm_of(lat, i))) return -3;
         const double *e = axis_of(lat, i), *m = ndir_of(lat, i);
         if (!(fabs(sqrt(dot3(e, e)) - 1.0) <= 1e-9)) return -3;
         if (!(fabs(sqrt(dot3(m, m)) - 1.0) <= 1e-9)) return -3;
@@ -429,6 +445,11 @@ double or_energy(const or_lattice *lat, double B, const double *S,
         double ta = k_of(lat, i) * (a * a);
         an = an - ta;
         sc = sc + fabs(ta);
+        if (lat->kc) {
+            double tc = lat->kc[i] * cubic_f(si);
+            an = an - tc;
+            sc = sc + fabs(tc);
+        }
     }
     double zee = -(B * zsum);
     sc = sc + fabs(B) * zabs;
@@ -477,9 +498,18 @@ void or_energy_grad(const or_lattice *lat, double B, const double *S, double g,
         const double *e = axis_of(lat, i), *m = ndir_of(lat, i);
         double a = dot3(si, e);
         double ki = k_of(lat, i);
-        if (gS)
+        if (gS) {
             for (int c = 0; c < 3; ++c)
                 gS[3 * i + c] += g * (-h[c] - B * m[c] - 2.0 * ki * a * e[c]);
+            if (lat->kc) {
+                /* d/dS of -kc (Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2) */
+                double x2 = si[0] * si[0], y2 = si[1] * si[1], z2 = si[2] * si[2];
+                double kci = lat->kc[i];
+                gS[3 * i + 0] += g * (-2.0 * kci * si[0] * (y2 + z2));
+                gS[3 * i + 1] += g * (-2.0 * kci * si[1] * (x2 + z2));
+                gS[3 * i + 2] += g * (-2.0 * kci * si[2] * (x2 + y2));
+            }
+        }
         if (gk) gk[i] += g * -(a * a);
         zsum = zsum + dot3(si, m);
     }
@@ -555,10 +585,13 @@ int or_run(const or_lattice *lat, const or_params *p, or_outputs *out)
 
     double *S = out->spins;
     if (p->init == OR_INIT_COLD_Z) {
-        for (int64_t i = 0; i < n; ++i) { S[3 * i] = 0.0; S[3 * i + 1] = 0.0; S[3 * i + 2] = 1.0; }
+        for (int64_t i = 0; i < n; ++i) { S[3 * i] = 0.0; S[3 * i + 1] = 0.0; S[3 * i + 2] = norm_of(lat, i); }
     } else if (p->init == OR_INIT_RANDOM) {
-        for (int64_t i = 0; i < n; ++i)
+        for (int64_t i = 0; i < n; ++i) {
             or_sphere_exact(p->seed, (uint32_t)i, 0xFFFFFFFFu, p->replica, S + 3 * i);
+            if (lat->norm)
+                for (int c = 0; c < 3; ++c) S[3 * i + c] = lat->norm[i] * S[3 * i + c];
+        }
     }
 
     out->near_ties = 0;
@@ -600,9 +633,14 @@ int or_run(const or_lattice *lat, const or_params *p, or_outputs *out)
                 double sn[3], u;
                 int32_t ty = (p->n_types > 0 && p->site_type) ? p->site_type[i] : 0;
                 int32_t pol = p->n_types > 0 ? p->type_policy[ty] : OR_POLICY_RANDOM;
+                /* trial moves act on the direction; the trial gets the norm back */
+                const double mu = norm_of(lat, i);
+                double dir[3] = {si[0], si[1], si[2]};
+                if (lat->norm)
+                    for (int c = 0; c < 3; ++c) dir[c] = si[c] / mu;
                 if (pol != OR_POLICY_RANDOM) {
                     double prm = pol == OR_POLICY_ADAPTIVE ? sigma : p->type_param[ty];
-                    u = or_trial(p->proposal, pol, p->seed, (uint32_t)i, g, p->replica, si, prm,
+                    u = or_trial(p->proposal, pol, p->seed, (uint32_t)i, g, p->replica, dir, prm,
                                  cos_t[ty], sn);
                 } else if (p->proposal == OR_PROPOSAL_EXACT) {
                     uint32_t w[4];
@@ -612,12 +650,15 @@ int or_run(const or_lattice *lat, const or_params *p, or_outputs *out)
                 } else {
                     or_sphere_f32map(p->seed, (uint32_t)i, g, p->replica, sn, &u);
                 }
+                if (lat->norm)
+                    for (int c = 0; c < 3; ++c) sn[c] = mu * sn[c];
                 double dSx = sn[0] - si[0], dSy = sn[1] - si[1], dSz = sn[2] - si[2];
                 double q = dSx * hx + dSy * hy + dSz * hz;
                 const double *e = axis_of(lat, i);
                 double a1 = dot3(sn, e);
                 double a0 = dot3(si, e);
                 double dE = -q - k_of(lat, i) * (a1 * a1 - a0 * a0);
+                if (lat->kc) dE = dE - lat->kc[i] * (cubic_f(sn) - cubic_f(si));
 
                 int acc;
                 if (dE <= 0.0) {

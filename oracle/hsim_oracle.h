@@ -9,10 +9,12 @@
  * contraction (-ffp-contract=off) so that every product and sum is rounded
  * separately in the order written.
  *
- * Model (paper, section "Classical spin Hamiltonian", Eqs. 1-2):
+ * Model (paper, section "Classical spin Hamiltonian", Eqs. 1-3):
  *   H = - sum_<ij> J_ij S_i.S_j - B sum_i S_i.n_i - sum_i k_i (S_i.e_i)^2
+ *       - sum_i kc_i (Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2)_i
  * with every unordered bond counted once and the anisotropy entering Eq. 1 with
- * a minus sign (k > 0 is an easy axis).
+ * a minus sign (k > 0 is an easy axis).  Spin i has length norm_i (1 unless
+ * given); trial moves act on its direction.
  * Dynamics (paper, section "Monte Carlo Metropolis algorithm", Eq. 4): a trial
  * direction uniform on the sphere is accepted when dE <= 0 or u < exp(-dE/T),
  * k_B = 1; one attempt per site makes one Monte Carlo step (MCS).  Sites are
@@ -37,6 +39,8 @@ typedef struct {
     const double *k;         /* n, or NULL for k = 0 */
     const double *axis;      /* 3n, or NULL for +z */
     const double *ndir;      /* 3n, or NULL for +z */
+    const double *kc;        /* n cubic anisotropy constants (Eq. 3), or NULL for 0 */
+    const double *norm;      /* n spin norms, or NULL for unit spins */
 } or_lattice;
 
 enum { OR_PROPOSAL_EXACT = 0, OR_PROPOSAL_F32MAP = 1 };

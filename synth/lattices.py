@@ -6,7 +6,8 @@ section, held as arrays):
     link are stored, with equal constants (``J[p(i->j)] == J[p(j->i)]``).
   * ``k`` float64 [n] uniaxial constants (None = 0 everywhere), ``axis``
     float64 [n, 3] unit anisotropy axes (None = +z), ``ndir`` float64 [n, 3]
-    unit field directions (None = +z).
+    unit field directions (None = +z), ``kc`` float64 [n] cubic constants
+    (None = 0), ``norm`` float64 [n] spin norms (None = 1).
   * Bond b is the b-th CSR entry (i, p) with col[p] > i, taken in row-major
     order; ``Lattice.bonds()`` lists them.
 """
@@ -31,6 +32,8 @@ class Lattice:
     site_type: Optional[np.ndarray] = None
     name: str = ""
     meta: dict = field(default_factory=dict)
+    kc: Optional[np.ndarray] = None      # [n] cubic anisotropy constants (None = 0)
+    norm: Optional[np.ndarray] = None    # [n] spin norms (None = 1)
 
     @property
     def nnz(self):
@@ -74,7 +77,8 @@ class Lattice:
         """Copy of the lattice with per-bond constants Jb (row-major bond order)."""
         J = np.asarray(Jb, dtype=np.float64)[self.entry_bond_id()]
         return Lattice(self.n, self.row_ptr, self.col, J, self.k, self.axis,
-                       self.ndir, self.pos, self.site_type, self.name, dict(self.meta))
+                       self.ndir, self.pos, self.site_type, self.name, dict(self.meta),
+                       self.kc, self.norm)
 
 
 def from_bonds(n, bi, bj, bJ, **kw):
