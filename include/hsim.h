@@ -121,6 +121,19 @@ hsim_status hsim_plan_bonds(hsim_plan plan, int32_t *bond_ij_out, int64_t *n_bon
  * picks them up at its next hsim_batch_bind or hsim_batch_set_policies.
  * HSIM_E_PARAM for a value outside 0..7. */
 hsim_status hsim_plan_set_types(hsim_plan plan, const int32_t *site_type);
+/* Per-site terms beyond Eqs. 1-2 (paper, Eq. 3 and the spin norm of the
+ * material file, section "Material building"):
+ *   k_cubic [n] user order (NULL: 0): cubic anisotropy, entering the energy
+ *     as -k_cubic (Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2) (the same sign
+ *     convention as the uniaxial term);
+ *   spin_norm [n] user order (NULL: 1): the length of each spin.  Cold and
+ *     random starts get the length; trial moves change the direction only.
+ * Also counted by hsim_energy_forward / hsim_energy_backward (dE/dS includes
+ * the cubic term).  Set before hsim_batch_bind.  With either term, PERSISTENT
+ * launches run as PLAIN launches.  HSIM_E_PARAM for a non-finite constant or
+ * a norm that is not positive and finite. */
+hsim_status hsim_plan_set_site_terms(hsim_plan plan, const double *k_cubic,
+                                     const double *spin_norm);
 void hsim_plan_destroy(hsim_plan plan);
 
 /* ---------------------------------------------------------------- batches */

@@ -26,6 +26,7 @@ int32_t batch_status_impl(hsim_batch);
 void autotune_impl(hsim_batch, const char *, int32_t, hipStream_t);
 void batch_time_phases_impl(hsim_batch, int32_t);
 void plan_set_types_impl(hsim_plan, const int32_t *);
+void plan_set_site_terms_impl(hsim_plan, const double *, const double *);
 void batch_set_policies_impl(hsim_batch, int32_t, const int32_t *, const double *, double, double);
 void batch_sigma_impl(hsim_batch, double *);
 namespace hsim {
@@ -121,6 +122,11 @@ hsim_status hsim_plan_bonds(hsim_plan p, int32_t *bond_ij_out, int64_t *n_bonds_
 hsim_status hsim_plan_set_types(hsim_plan p, const int32_t *site_type)
 {
     return guarded([&] { plan_set_types_impl(p, site_type); });
+}
+
+hsim_status hsim_plan_set_site_terms(hsim_plan p, const double *k_cubic, const double *spin_norm)
+{
+    return guarded([&] { plan_set_site_terms_impl(p, k_cubic, spin_norm); });
 }
 
 void hsim_plan_destroy(hsim_plan p) { delete p; }

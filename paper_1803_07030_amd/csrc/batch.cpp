@@ -189,6 +189,9 @@ void hsim_batch_s::upload_tables()
         la.ci = (const int32_t *)P->d_ci.p;
         la.J = (const float *)P->d_Jf.p;
         la.type = (const int32_t *)P->d_type.p;
+        la.kc = (const float *)P->d_kcf.p;
+        la.mu = (const float *)P->d_muf.p;
+        la.mu_d = (const double *)P->d_mud.p;
         la.ell_col = (const int32_t *)P->d_ell_col.p;
         la.ell_J = (const float *)P->d_ell_J.p;
         la.orig = (const uint32_t *)P->d_orig.p;
@@ -226,6 +229,9 @@ void hsim_batch_s::upload_tables()
             d.spins = (char *)spins + spin_off[r] * elem;
             d.ell_w = P->ell_w;
             d.type = (const int32_t *)P->d_type.p;
+            d.kc = f64 ? P->d_kcd.p : P->d_kcf.p;
+            d.mu = f64 ? P->d_mud.p : P->d_muf.p;
+            d.mu_d = (const double *)P->d_mud.p;
             d.ellT_col = (const int32_t *)P->d_ellT_col.p;
             d.ellT_J = f64 ? P->d_ellT_Jd.p : P->d_ellT_Jf.p;
             d.k0 = P->k0;
@@ -669,9 +675,12 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
         if (b->tuned_launch >= 0) mode = b->tuned_launch;
         else mode = HSIM_LAUNCH_GRAPH;
     }
-    // the persistent kernel runs the random move only: with update policies
-    // the same sweep runs as plain launches
-    if (mode == HSIM_LAUNCH_PERSISTENT && b->pol.n_types > 0) mode = HSIM_LAUNCH_PLAIN;
+    // the persistent kernel runs the random move of the plain model only:
+    // with update policies, cubic constants or spin norms the same sweep runs
+    // as plain launches
+    bool xt = false;
+    for (auto p : b->plans) xt |= !p->kcd.empty() || !p->mud.empty();
+    if (mode == HSIM_LAUNCH_PERSISTENT && (b->pol.n_types > 0 || xt)) mode = HSIM_LAUNCH_PLAIN;
     if (mode == HSIM_LAUNCH_PERSISTENT) {
         if (b->layout != HSIM_LAYOUT_REPLICA)
             throw Error(HSIM_E_UNSUPPORTED, "persistent launch needs the replica layout");

@@ -97,15 +97,25 @@ __global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const dou
         zn = sx * (double)s.nx + sy * (double)s.ny + sz * (double)s.nz;
         e = -0.5 * (sx * (double)s.hx + sy * (double)s.hy + sz * (double)s.hz) - a.B * zn -
             (double)s.k * an * an;
+        // cubic term of Eq. 3, -kc (Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2)
+        if (a.kc) e -= (double)((const T *)a.kc)[i] * ((sx * sx * (sy * sy) + sy * sy * (sz * sz)) + sx * sx * (sz * sz));
         if (BWD) {
             const T g = (T)gE[b];
             const T B = (T)a.B;
             const T an_t = s.sx * s.ex + s.sy * s.ey + s.sz * s.ez;
             const T two_ka = T(2) * s.k * an_t;
             T *o = gS + (size_t)b * 3 * a.n;
-            o[i] = g * (-s.hx - B * s.nx - two_ka * s.ex);
-            o[a.n + i] = g * (-s.hy - B * s.ny - two_ka * s.ey);
-            o[2 * a.n + i] = g * (-s.hz - B * s.nz - two_ka * s.ez);
+            T cx = T(0), cy = T(0), cz = T(0);
+            if (a.kc) {
+                const T kc2 = T(2) * ((const T *)a.kc)[i];
+                const T x2 = s.sx * s.sx, y2 = s.sy * s.sy, z2 = s.sz * s.sz;
+                cx = kc2 * s.sx * (y2 + z2);
+                cy = kc2 * s.sy * (x2 + z2);
+                cz = kc2 * s.sz * (x2 + y2);
+            }
+            o[i] = g * (-s.hx - B * s.nx - two_ka * s.ex - cx);
+            o[a.n + i] = g * (-s.hy - B * s.ny - two_ka * s.ey - cy);
+            o[2 * a.n + i] = g * (-s.hz - B * s.nz - two_ka * s.ez - cz);
         }
     }
     const double et = bsum(e, red);

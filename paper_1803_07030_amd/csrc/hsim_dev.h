@@ -47,6 +47,9 @@ struct RepDesc {
     const void *nd;           // [3][n] (F_SITE), stride n
     void *spins;              // [3][n_pad] of this replica (site and block layouts)
     const int32_t *type;      // n site types (internal order), NULL: type 0 everywhere
+    const void *kc;           // n cubic constants (float or double), NULL: none
+    const void *mu;           // n spin norms (float or double), NULL: unit spins
+    const double *mu_d;       // n spin norms in double (initial states), NULL: unit
     const int32_t *ellT_col;  // [ell_w][n] padded rows, slot-major (NULL: use the CSR)
     const void *ellT_J;       // [ell_w][n] (float or double)
     double k0, e0[3], n0[3];  // uniform values (K_UNIFORM / F_UNIFORM)
@@ -113,6 +116,8 @@ struct RepLaneArgs {
     const int32_t *rp, *ci;
     const float *J;
     const int32_t *type;        // [n] site types (internal order), NULL: type 0
+    const float *kc, *mu;       // [n] cubic constants / spin norms, NULL: none / unit
+    const double *mu_d;         // [n] spin norms in double (initial states)
     const int32_t *ell_col;     // [n][maxd] padded rows, site-major
     const float *ell_J;
     const uint32_t *orig;
@@ -179,6 +184,7 @@ struct EnergyArgs {
     int64_t n, nnz, nb;
     int batch;
     const void *S, *Jb, *k, *ax, *nd;
+    const void *kc;         // NULL, or [n] cubic constants of the plan (user order)
     double B;
 };
 hipError_t launch_energy_forward(hipStream_t st, bool f64, const EnergyArgs &a, double *partial,

@@ -85,6 +85,10 @@ struct hsim_plan_s {
     std::vector<double> ellT_Jd;
     // site types (internal order; empty: type 0 everywhere)
     std::vector<int32_t> type;
+    // cubic constants and spin norms (internal order; empty: none / unit),
+    // and the cubic constants in user order for the energy API
+    std::vector<double> kcd, mud, ukcd;
+    std::vector<float> kcf, muf, ukcf;
     // user-order CSR for the energy and its gradient
     std::vector<int64_t> urp;
     std::vector<int32_t> uci, ubond, fwd_entry, bond_ij;
@@ -93,6 +97,8 @@ struct hsim_plan_s {
     bool sweep_on_device = false, energy_on_device = false;
     hsim::DevBuf d_rp, d_ci, d_Jf, d_Jd, d_orig, d_kf, d_kd, d_axf, d_axd, d_ndf, d_ndd;
     hsim::DevBuf d_ell_col, d_ell_J, d_ellT_col, d_ellT_Jf, d_ellT_Jd, d_type;
+    hsim::DevBuf d_kcf, d_kcd, d_muf, d_mud, d_ukcf, d_ukcd;
+    void upload_terms();
     hsim::DevBuf d_urp, d_uci, d_ubond, d_fwd, d_scratch;
 
     void upload_sweep();

@@ -249,6 +249,66 @@ void hsim_plan_s::upload_sweep()
     }
     if (!type.empty()) d_type.upload(type);
     sweep_on_device = true;
+    upload_terms();
+}
+
+// Device copies of the cubic constants and spin norms (idempotent).
+void hsim_plan_s::upload_terms()
+{
+    if (!kcd.empty() && !d_kcd.p) {
+        d_kcd.upload(kcd);
+        d_kcf.upload(kcf);
+        d_ukcd.upload(ukcd);
+        d_ukcf.upload(ukcf);
+    }
+    if (!mud.empty() && !d_mud.p) {
+        d_mud.upload(mud);
+        d_muf.upload(muf);
+    }
+}
+
+// Cubic constants (Eq. 3) and spin norms, user order; NULL, all-zero
+// constants or all-unit norms mean none.
+void plan_set_site_terms_impl(hsim_plan P, const double *k_cubic, const double *spin_norm)
+{
+    if (!P) throw Error(HSIM_E_ARG, "set_site_terms: NULL plan");
+    const int64_t n = P->n;
+    bool any_kc = false, any_mu = false;
+    for (int64_t u = 0; u < n; ++u) {
+        if (k_cubic) {
+            if (!std::isfinite(k_cubic[u])) throw Error(HSIM_E_PARAM, "non-finite cubic constant");
+            any_kc |= k_cubic[u] != 0.0;
+        }
+        if (spin_norm) {
+            if (!(spin_norm[u] > 0.0) || !std::isfinite(spin_norm[u]))
+                throw Error(HSIM_E_PARAM, "spin norms must be positive and finite");
+            any_mu |= spin_norm[u] != 1.0;
+        }
+    }
+    P->kcd.clear(); P->kcf.clear(); P->ukcd.clear(); P->ukcf.clear();
+    P->mud.clear(); P->muf.clear();
+    P->d_kcd.release(); P->d_kcf.release(); P->d_ukcd.release(); P->d_ukcf.release();
+    P->d_mud.release(); P->d_muf.release();
+    if (any_kc) {
+        P->ukcd.assign(k_cubic, k_cubic + n);
+        P->ukcf.resize(n);
+        P->kcd.resize(n);
+        P->kcf.resize(n);
+        for (int64_t u = 0; u < n; ++u) P->ukcf[u] = (float)k_cubic[u];
+        for (int64_t k = 0; k < n; ++k) {
+            P->kcd[k] = k_cubic[P->perm[k]];
+            P->kcf[k] = (float)P->kcd[k];
+        }
+    }
+    if (any_mu) {
+        P->mud.resize(n);
+        P->muf.resize(n);
+        for (int64_t k = 0; k < n; ++k) {
+            P->mud[k] = spin_norm[P->perm[k]];
+            P->muf[k] = (float)P->mud[k];
+        }
+    }
+    if (P->sweep_on_device) P->upload_terms();
 }
 
 // Site types (user order, values 0 .. kMaxTypes-1) kept in internal order;
@@ -285,9 +345,10 @@ void hsim_plan_s::upload_energy()
 namespace {
 
 hsim::EnergyArgs energy_args(hsim_plan P, int32_t batch, const void *S, const void *Jb,
-                             const void *k, const void *ax, double B, const void *nd)
+                             const void *k, const void *ax, double B, const void *nd, bool f64)
 {
     P->upload_energy();
+    P->upload_terms();
     hsim::EnergyArgs a{};
     a.rp = (const int64_t *)P->d_urp.p;
     a.ci = (const int32_t *)P->d_uci.p;
@@ -302,6 +363,7 @@ hsim::EnergyArgs energy_args(hsim_plan P, int32_t batch, const void *S, const vo
     a.k = k;
     a.ax = ax;
     a.nd = nd;
+    a.kc = P->ukcd.empty() ? nullptr : (f64 ? P->d_ukcd.p : P->d_ukcf.p);
     a.B = B;
     return a;
 }
@@ -328,7 +390,7 @@ void energy_forward_impl(hsim_plan P, int32_t batch, hsim_precision prec, const 
     if (prec != HSIM_FP32 && prec != HSIM_FP64_EXACT) throw Error(HSIM_E_ARG, "bad precision");
     if (!std::isfinite(B)) throw Error(HSIM_E_PARAM, "non-finite field");
     if (batch == 0) return;
-    const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd);
+    const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd, prec == HSIM_FP64_EXACT);
     double *scr = energy_scratch(P, batch);
     hsim::hip_check(hsim::launch_energy_forward(st, prec == HSIM_FP64_EXACT, a, scr, 0, E),
                     "energy forward launch");
@@ -345,7 +407,7 @@ void energy_backward_impl(hsim_plan P, int32_t batch, hsim_precision prec, const
     if (prec != HSIM_FP32 && prec != HSIM_FP64_EXACT) throw Error(HSIM_E_ARG, "bad precision");
     if (!std::isfinite(B)) throw Error(HSIM_E_PARAM, "non-finite field");
     if (batch == 0) return;
-    const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd);
+    const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd, prec == HSIM_FP64_EXACT);
     double *scr = energy_scratch(P, batch);
     hsim::hip_check(hsim::launch_energy_backward(st, prec == HSIM_FP64_EXACT, a, gE, gS, gJ, gk, gB,
                                                  scr, 0),

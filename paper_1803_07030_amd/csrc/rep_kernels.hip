@@ -79,30 +79,60 @@ struct RepSite {
     }
 };
 
-// Trial of site i for one lane: the random move, or (POL) the move of the
+// Kernel variants: bit 0 (VAR_POL) update policies, bit 1 (VAR_XT) cubic
+// anisotropy and / or spin norms.
+constexpr int VAR_POL = 1, VAR_XT = 2;
+
+// Trial of site i for one lane: the random move, or (VAR_POL) the move of the
 // site's type, with the lane's replica width for the adaptive move; ad tells
-// whether the move is adaptive (its accepts steer the width).
-template <bool POL>
+// whether the move is adaptive (its accepts steer the width).  With VAR_XT
+// and spin norms the move acts on the direction and the trial gets the
+// site's length mu back.
+template <int VAR>
 __device__ __forceinline__ Trial32 rep_trial(const RepLaneArgs &a, const RunArgs &ra, int i,
                                              uint32_t orig, uint32_t g, uint32_t rid, float sx,
-                                             float sy, float sz, float sigma, bool &ad)
+                                             float sy, float sz, float sigma, float mu, bool &ad)
 {
     const uint4 w = draw(ra.seed, orig, g, rid, 0);
     ad = false;
-    if constexpr (!POL) {
-        return trial32(w);
+    Trial32 t;
+    if constexpr (!(VAR & VAR_POL)) {
+        t = trial32(w);
     } else {
         const SitePol pl = pick_policy(ra.pol.pol, ra.pol.param, ra.pol.cos_t, a.type ? a.type[i] : 0);
         ad = pl.pol == POL_ADAPTIVE;
-        if (pl.pol == POL_RANDOM) return trial32(w);
-        return trial32_policy(pl.pol, w, sx, sy, sz, ad ? sigma : (float)pl.param,
-                              (float)(1.0 - pl.cos_t), ra.seed, orig, g, rid);
+        if (pl.pol == POL_RANDOM) {
+            t = trial32(w);
+        } else {
+            const float inv = (VAR & VAR_XT) ? 1.0f / mu : 1.0f;
+            t = trial32_policy(pl.pol, w, sx * inv, sy * inv, sz * inv, ad ? sigma : (float)pl.param,
+                               (float)(1.0 - pl.cos_t), ra.seed, orig, g, rid);
+        }
     }
+    if constexpr ((VAR & VAR_XT) != 0) {
+        t.x *= mu;
+        t.y *= mu;
+        t.z *= mu;
+    }
+    return t;
 }
+
+// Per-site extra terms of a lane's update (VAR_XT): spin length and cubic
+// constant (0 / 1 when the plan has none).
+template <bool UNI>
+struct RepXt {
+    float mu = 1.0f, kc = 0.0f;
+    __device__ __forceinline__ RepXt() {}
+    __device__ __forceinline__ RepXt(const RepLaneArgs &a, int i)
+    {
+        if (a.mu) mu = UNI ? ((const __attribute__((address_space(4))) float *)a.mu)[i] : a.mu[i];
+        if (a.kc) kc = UNI ? ((const __attribute__((address_space(4))) float *)a.kc)[i] : a.kc[i];
+    }
+};
 
 // Update site i for replica lane r (spin column r of the [3][n][Rp] array),
 // generic CSR row walk (rows of any degree).
-template <int KM, int FM, bool POL>
+template <int KM, int FM, int VAR>
 __device__ __forceinline__ void rep_site_update(const RepLaneArgs &a, int i, int r, uint32_t g,
                                                 float beta, float b, uint32_t rid, bool active,
                                                 float sigma, const RunArgs &ra, double (&acc)[6])
@@ -125,9 +155,12 @@ __device__ __forceinline__ void rep_site_update(const RepLaneArgs &a, int i, int
     const size_t oi = (size_t)i * a.Rp;
     const float sx = S[oi], sy = S[plane + oi], sz = S[2 * plane + oi];
     bool ad;
-    const Trial32 t = rep_trial<POL>(a, ra, i, a.orig[i], g, rid, sx, sy, sz, sigma, ad);
-    const float dE = (KM == K_NONE) ? delta_e32_iso(sx, sy, sz, t, hx, hy, hz)
-                                    : delta_e32(sx, sy, sz, t, hx, hy, hz, sp.k, sp.ex, sp.ey, sp.ez);
+    const RepXt<false> xt = (VAR & VAR_XT) ? RepXt<false>(a, i) : RepXt<false>();
+    const Trial32 t = rep_trial<VAR>(a, ra, i, a.orig[i], g, rid, sx, sy, sz, sigma, xt.mu, ad);
+    float dE = (KM == K_NONE) ? delta_e32_iso(sx, sy, sz, t, hx, hy, hz)
+                              : delta_e32(sx, sy, sz, t, hx, hy, hz, sp.k, sp.ex, sp.ey, sp.ez);
+    if constexpr ((VAR & VAR_XT) != 0)
+        dE = fmaf(-xt.kc, cubic32(t.x, t.y, t.z) - cubic32(sx, sy, sz), dE);
     const bool ok = accept32(dE, beta, t.u) && active;
     acc[5] += (ok && ad) ? 1.0 : 0.0;
     if (active && dE != dE) atomicOr(&ra.ctl->status, 1u);
@@ -180,7 +213,7 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t rs, int32_t lane_b
 // all loads of the step are issued before any store (sites of one colour
 // class are never neighbours); the own rows are written back whole.  Row entries are wave-uniform scalar loads;
 // spin rows go through the buffer descriptors with the row in soffset.
-template <int KM, int FM, int MAXD, bool POL>
+template <int KM, int FM, int MAXD, int VAR>
 __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const SpinPlanes &sp3,
                                                  int i0, int ce, int r, uint32_t g, float beta,
                                                  float b, uint32_t rid, bool active, float sigma,
@@ -219,11 +252,14 @@ __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const Spi
         const float fy = fmaf(b, sp.ny, hy[u]);
         const float fz = fmaf(b, sp.nz, hz[u]);
         bool ad;
-        const Trial32 t = rep_trial<POL>(a, ra, i, cload(a.orig, i), g, rid, sx[u], sy[u], sz[u],
-                                         sigma, ad);
-        const float dE = (KM == K_NONE) ? delta_e32_iso(sx[u], sy[u], sz[u], t, fx, fy, fz)
-                                        : delta_e32(sx[u], sy[u], sz[u], t, fx, fy, fz, sp.k, sp.ex,
-                                                    sp.ey, sp.ez);
+        const RepXt<true> xt = (VAR & VAR_XT) ? RepXt<true>(a, i) : RepXt<true>();
+        const Trial32 t = rep_trial<VAR>(a, ra, i, cload(a.orig, i), g, rid, sx[u], sy[u], sz[u],
+                                         sigma, xt.mu, ad);
+        float dE = (KM == K_NONE) ? delta_e32_iso(sx[u], sy[u], sz[u], t, fx, fy, fz)
+                                  : delta_e32(sx[u], sy[u], sz[u], t, fx, fy, fz, sp.k, sp.ex,
+                                              sp.ey, sp.ez);
+        if constexpr ((VAR & VAR_XT) != 0)
+            dE = fmaf(-xt.kc, cubic32(t.x, t.y, t.z) - cubic32(sx[u], sy[u], sz[u]), dE);
         const bool live = active && valid[u];
         const bool ok = accept32(dE, beta, t.u) && live;
         acc[5] += (ok && ad) ? 1.0 : 0.0;
@@ -242,7 +278,7 @@ __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const Spi
 
 // Two sites of one lane group at once: all loads of both sites are issued
 // before either stores (sites of one colour class are never neighbours).
-template <int KM, int FM, int MAXD, bool POL>
+template <int KM, int FM, int MAXD, int VAR>
 __device__ __forceinline__ void rep_pair_update(const RepLaneArgs &a, int i0, int ce, int r,
                                                 uint32_t g, float beta, float b, uint32_t rid,
                                                 bool active, float sigma, const RunArgs &ra,
@@ -281,10 +317,14 @@ __device__ __forceinline__ void rep_pair_update(const RepLaneArgs &a, int i0, in
         const float fy = fmaf(b, sp.ny, hy[u]);
         const float fz = fmaf(b, sp.nz, hz[u]);
         bool ad;
-        const Trial32 t = rep_trial<POL>(a, ra, i, a.orig[i], g, rid, sx[u], sy[u], sz[u], sigma, ad);
-        const float dE = (KM == K_NONE) ? delta_e32_iso(sx[u], sy[u], sz[u], t, fx, fy, fz)
-                                        : delta_e32(sx[u], sy[u], sz[u], t, fx, fy, fz, sp.k, sp.ex,
-                                                    sp.ey, sp.ez);
+        const RepXt<false> xt = (VAR & VAR_XT) ? RepXt<false>(a, i) : RepXt<false>();
+        const Trial32 t = rep_trial<VAR>(a, ra, i, a.orig[i], g, rid, sx[u], sy[u], sz[u], sigma,
+                                         xt.mu, ad);
+        float dE = (KM == K_NONE) ? delta_e32_iso(sx[u], sy[u], sz[u], t, fx, fy, fz)
+                                  : delta_e32(sx[u], sy[u], sz[u], t, fx, fy, fz, sp.k, sp.ex,
+                                              sp.ey, sp.ez);
+        if constexpr ((VAR & VAR_XT) != 0)
+            dE = fmaf(-xt.kc, cubic32(t.x, t.y, t.z) - cubic32(sx[u], sy[u], sz[u]), dE);
         const bool live = active && valid[u];
         const bool ok = accept32(dE, beta, t.u) && live;
         acc[5] += (ok && ad) ? 1.0 : 0.0;
@@ -317,7 +357,9 @@ __device__ __forceinline__ double rep_site_energy(const RepLaneArgs &a, int i, i
     const double sx = S[oi], sy = S[plane + oi], sz = S[2 * plane + oi];
     const double an = sx * (double)sp.ex + sy * (double)sp.ey + sz * (double)sp.ez;
     const double zn = sx * (double)sp.nx + sy * (double)sp.ny + sz * (double)sp.nz;
-    return -0.5 * (sx * hx + sy * hy + sz * hz) - b * zn - (double)sp.k * an * an;
+    double e = -0.5 * (sx * hx + sy * hy + sz * hz) - b * zn - (double)sp.k * an * an;
+    if (a.kc) e -= (double)a.kc[i] * cubic64(sx, sy, sz);
+    return e;
 }
 
 // The same energy through the padded rows (row entries in CSR order, then
@@ -341,7 +383,9 @@ __device__ __forceinline__ double rep_site_energy_ell(const RepLaneArgs &a, cons
                  sz = bload(sp3.z, lane_b, oi);
     const double an = sx * (double)sp.ex + sy * (double)sp.ey + sz * (double)sp.ez;
     const double zn = sx * (double)sp.nx + sy * (double)sp.ny + sz * (double)sp.nz;
-    return -0.5 * (sx * hx + sy * hy + sz * hz) - b * zn - (double)sp.k * an * an;
+    double e = -0.5 * (sx * hx + sy * hy + sz * hz) - b * zn - (double)sp.k * an * an;
+    if (a.kc) e -= (double)cload(a.kc, i) * cubic64(sx, sy, sz);
+    return e;
 }
 
 // Lane geometry for lane-group width W: replica column and sub-group.
@@ -369,14 +413,16 @@ __device__ __forceinline__ int xcd_tile(int b, int nt)
 
 // One tile of one colour phase: the body shared by the per-phase kernel and
 // the persistent kernel.  red: LDS [kRepWaves][64][NQ].  MAXD > 0: rows padded
-// to MAXD entries; MAXD == 0: generic row walk.  POL: update policies (the
-// tile also records its accepted adaptive moves, field 6).
-template <int KM, int FM, int W, int MAXD, bool POL = false>
+// to MAXD entries; MAXD == 0: generic row walk.  VAR: VAR_POL update
+// policies (the tile also records its accepted adaptive moves, field 6),
+// VAR_XT cubic anisotropy and spin norms.
+template <int KM, int FM, int W, int MAXD, int VAR = 0>
 __device__ __forceinline__ void rep_tile(const RepLaneArgs &a, int colour, int tile, int group,
                                          uint32_t g, const RunArgs &ra, double *part,
                                          double *red)
 {
     constexpr int SPL = kRepSitesPerWave * W / 64;   // sites per lane group
+    constexpr bool POL = (VAR & VAR_POL) != 0;
     constexpr int NQ = POL ? 6 : 5;
     const Lanes<W> L(group);
     const int ce = a.cls_off[colour + 1];
@@ -398,17 +444,17 @@ __device__ __forceinline__ void rep_tile(const RepLaneArgs &a, int colour, int t
         const SpinPlanes sp3(a);
         for (int j = 0; j < SPL && base + j < ce; j += (W == 64 ? kRepSitesPerStep : 2)) {
             if constexpr (W == 64)
-                rep_step_uniform<KM, FM, MAXD, POL>(a, sp3, base + j, ce, L.r, g, beta, b, rid,
+                rep_step_uniform<KM, FM, MAXD, VAR>(a, sp3, base + j, ce, L.r, g, beta, b, rid,
                                                     active, sigma, ra, acc);
             else
-                rep_pair_update<KM, FM, MAXD, POL>(a, base + j, ce, L.r, g, beta, b, rid, active,
+                rep_pair_update<KM, FM, MAXD, VAR>(a, base + j, ce, L.r, g, beta, b, rid, active,
                                                    sigma, ra, acc);
         }
     } else {
         for (int j = 0; j < SPL; ++j) {
             const int i = base + j;
             if (i >= ce) break;
-            rep_site_update<KM, FM, POL>(a, i, L.r, g, beta, b, rid, active, sigma, ra, acc);
+            rep_site_update<KM, FM, VAR>(a, i, L.r, g, beta, b, rid, active, sigma, ra, acc);
         }
     }
 #pragma unroll
@@ -594,14 +640,14 @@ __device__ __forceinline__ double *rep_chunk_slot(const RunArgs &ra, const RepLa
 }
 
 // Per-phase kernel: grid (tiles of the colour, replica groups).
-template <int KM, int FM, int W, int MAXD, bool POL>
+template <int KM, int FM, int W, int MAXD, int VAR>
 __global__ __launch_bounds__(kRepThreads) void k_rep_phase(RepLaneArgs a, int colour, int t_off,
                                                            int ntiles, RunArgs ra)
 {
     __shared__ double red[kRedDoubles];
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     const int nt = a.tile_off[colour + 1] - a.tile_off[colour];
-    rep_tile<KM, FM, W, MAXD, POL>(a, colour, xcd_tile(blockIdx.x, nt), blockIdx.y, g, ra,
+    rep_tile<KM, FM, W, MAXD, VAR>(a, colour, xcd_tile(blockIdx.x, nt), blockIdx.y, g, ra,
                                    rep_slot(ra, a, ntiles, t_off % ra.rec_win), red);
 }
 
@@ -860,6 +906,12 @@ __global__ void k_init_spins_rep(RepLaneArgs a, int mode, const double *given, u
                 y = gv[1];
                 z = gv[2];
             }
+            if (mode != 0 && a.mu_d) {   // cold and random starts: spins of length mu
+                const double mu = a.mu_d[i];
+                x = mu * x;
+                y = mu * y;
+                z = mu * z;
+            }
         }
         const size_t oi = (size_t)i * a.Rp + r;
         a.spins[oi] = (float)x;
@@ -929,12 +981,19 @@ hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour, in
     dim3 grid((unsigned)nt, (unsigned)(a.Rp / Wd));
     dim3 blk(kRepThreads);
     HSIM_DISPATCH_KFW(kmode, fmode, Wd, HSIM_DISPATCH_D(a.ell_w, {
-        if (ra.pol.n_types > 0)
-            hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD, true>), grid, blk, 0, st, a, colour,
+        const int var = (ra.pol.n_types > 0 ? VAR_POL : 0) | (a.kc || a.mu ? VAR_XT : 0);
+        if (var == 0)
+            hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD, 0>), grid, blk, 0, st, a, colour,
+                               t_off, ntiles, ra);
+        else if (var == VAR_POL)
+            hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD, VAR_POL>), grid, blk, 0, st, a, colour,
+                               t_off, ntiles, ra);
+        else if (var == VAR_XT)
+            hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD, VAR_XT>), grid, blk, 0, st, a, colour,
                                t_off, ntiles, ra);
         else
-            hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD, false>), grid, blk, 0, st, a, colour,
-                               t_off, ntiles, ra);
+            hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD, VAR_POL | VAR_XT>), grid, blk, 0, st,
+                               a, colour, t_off, ntiles, ra);
     }));
     return hipGetLastError();
 }

@@ -167,12 +167,21 @@ __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint
         hy = fmaf(b, sp.ny, hy);
         hz = fmaf(b, sp.nz, hz);
         const uint4 w0 = draw(ra.seed, orig, g, rd.rep_id, 0);
-        const Trial32 t = pl.pol == POL_RANDOM
-                              ? trial32(w0)
-                              : trial32_policy(pl.pol, w0, sx, sy, sz, (float)pl.param,
-                                               (float)(1.0 - pl.cos_t), ra.seed, orig, g, rd.rep_id);
+        const float mu = rd.mu ? ((const float *)rd.mu)[i] : 1.0f;
+        const float inv = rd.mu ? 1.0f / mu : 1.0f;
+        Trial32 t = pl.pol == POL_RANDOM
+                        ? trial32(w0)
+                        : trial32_policy(pl.pol, w0, sx * inv, sy * inv, sz * inv, (float)pl.param,
+                                         (float)(1.0 - pl.cos_t), ra.seed, orig, g, rd.rep_id);
+        if (rd.mu) {
+            t.x *= mu;
+            t.y *= mu;
+            t.z *= mu;
+        }
         dE = (KM == K_NONE) ? delta_e32_iso(sx, sy, sz, t, hx, hy, hz)
                             : delta_e32(sx, sy, sz, t, hx, hy, hz, sp.k, sp.ex, sp.ey, sp.ez);
+        if (rd.kc)
+            dE = fmaf(-((const float *)rd.kc)[i], cubic32(t.x, t.y, t.z) - cubic32(sx, sy, sz), dE);
         acc_move = accept32(dE, beta, t.u);
         nx = t.x;
         ny = t.y;
@@ -182,7 +191,12 @@ __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint
         hy = hy + b * sp.ny;
         hz = hz + b * sp.nz;
         double dd;
-        if (pl.pol == POL_RANDOM)
+        if (rd.kc || rd.mu)
+            acc_move = update64_general(pl.pol, pl.param, pl.cos_t, ra.seed, orig, g, rd.rep_id, sx,
+                                        sy, sz, hx, hy, hz, sp.k, sp.ex, sp.ey, sp.ez, rd.kc != nullptr,
+                                        rd.kc ? ((const double *)rd.kc)[i] : 0.0, rd.mu != nullptr,
+                                        rd.mu ? ((const double *)rd.mu)[i] : 1.0, beta, nx, ny, nz, dd);
+        else if (pl.pol == POL_RANDOM)
             acc_move = update64(ra.seed, orig, g, rd.rep_id, sx, sy, sz, hx, hy, hz, sp.k, sp.ex,
                                 sp.ey, sp.ez, beta, nx, ny, nz, dd);
         else
@@ -229,7 +243,9 @@ __device__ __forceinline__ double site_energy(const RepDesc &rd, const T *S, int
     const double sx = S[i], sy = S[np + i], sz = S[2 * np + i];
     const double a = sx * (double)sp.ex + sy * (double)sp.ey + sz * (double)sp.ez;
     const double zn = sx * (double)sp.nx + sy * (double)sp.ny + sz * (double)sp.nz;
-    return -0.5 * (sx * hx + sy * hy + sz * hz) - b * zn - (double)sp.k * a * a;
+    double e = -0.5 * (sx * hx + sy * hy + sz * hz) - b * zn - (double)sp.k * a * a;
+    if (rd.kc) e -= (double)((const T *)rd.kc)[i] * cubic64(sx, sy, sz);
+    return e;
 }
 
 }  // namespace
@@ -282,6 +298,12 @@ __global__ void k_init_spins(const RepDesc *reps, int mode, const double *given,
         x = gv[0];
         y = gv[1];
         z = gv[2];
+    }
+    if (mode != 0 && rd.mu_d) {    // cold and random starts: spins of length mu
+        const double mu = rd.mu_d[i];
+        x = mu * x;
+        y = mu * y;
+        z = mu * z;
     }
     S[i] = (T)x;
     S[rd.n_pad + i] = (T)y;

@@ -99,6 +99,13 @@ __device__ __forceinline__ float delta_e32_iso(float sx, float sy, float sz, con
     return -fmaf(dz, hz, fmaf(dy, hy, dx * hx));
 }
 
+// Cubic anisotropy function of Eq. 3: Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2.
+__device__ __forceinline__ float cubic32(float x, float y, float z)
+{
+    const float a = x * x, b = y * y, c = z * z;
+    return fmaf(a, c, fmaf(b, c, a * b));
+}
+
 // Metropolis rule (Eq. 4, k_B = 1): accept if dE <= 0 or u < exp(-beta dE).
 __device__ __forceinline__ bool accept32(float dE, float beta, float u)
 {
@@ -423,6 +430,14 @@ __device__ inline double trial64_policy(int pol, uint64_t seed, uint32_t site, u
     return u;
 }
 
+// Eq. 3's function in the validation mode, in the order
+// (a b + b c) + a c with a = Sx^2, b = Sy^2, c = Sz^2.
+__device__ inline double cubic64(double x, double y, double z)
+{
+    const double a = x * x, b = y * y, c = z * z;
+    return (a * b + b * c) + a * c;
+}
+
 // Validation-mode update under a policy (random: identical to update64).
 __device__ inline bool update64_policy(int pol, double param, double cos_t, uint64_t seed,
                                        uint32_t site, uint32_t g, uint32_t rep, double sx,
@@ -436,6 +451,46 @@ __device__ inline bool update64_policy(int pol, double param, double cos_t, uint
     const double a1 = dot64(nx, ny, nz, ex, ey, ez);
     const double a0 = dot64(sx, sy, sz, ex, ey, ez);
     dE = -q - k * (a1 * a1 - a0 * a0);
+    if (dE <= 0.0) return true;
+    return u < exp(-beta * dE);
+}
+
+// Validation-mode update of a spin of length mu (has_mu) with a cubic term
+// kc (has_kc): the trial acts on the direction S / mu and gets the length
+// back, and dE gains -kc (f(S') - f(S)).  Without either term it is
+// update64 / update64_policy.
+__device__ inline bool update64_general(int pol, double param, double cos_t, uint64_t seed,
+                                        uint32_t site, uint32_t g, uint32_t rep, double sx,
+                                        double sy, double sz, double hx, double hy, double hz,
+                                        double k, double ex, double ey, double ez, bool has_kc,
+                                        double kc, bool has_mu, double mu, double beta, double &nx,
+                                        double &ny, double &nz, double &dE)
+{
+    double dx = sx, dy = sy, dz = sz;
+    if (has_mu) {
+        dx = sx / mu;
+        dy = sy / mu;
+        dz = sz / mu;
+    }
+    double u;
+    if (pol == POL_RANDOM) {
+        const uint4 w0 = draw(seed, site, g, rep, 0);
+        u = u53(w0.x, w0.y);
+        sphere64(seed, site, g, rep, nx, ny, nz);
+    } else {
+        u = trial64_policy(pol, seed, site, g, rep, dx, dy, dz, param, cos_t, nx, ny, nz);
+    }
+    if (has_mu) {
+        nx = mu * nx;
+        ny = mu * ny;
+        nz = mu * nz;
+    }
+    const double dSx = nx - sx, dSy = ny - sy, dSz = nz - sz;
+    const double q = (dSx * hx + dSy * hy) + dSz * hz;
+    const double a1 = dot64(nx, ny, nz, ex, ey, ez);
+    const double a0 = dot64(sx, sy, sz, ex, ey, ez);
+    dE = -q - k * (a1 * a1 - a0 * a0);
+    if (has_kc) dE = dE - kc * (cubic64(nx, ny, nz) - cubic64(sx, sy, sz));
     if (dE <= 0.0) return true;
     return u < exp(-beta * dE);
 }

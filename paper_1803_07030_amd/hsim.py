@@ -70,6 +70,7 @@ _SIGNATURES = {
     "hsim_autotune": [_vp, ctypes.c_char_p, _i32, _vp],
     "hsim_batch_time_phases": [_vp, _i32],
     "hsim_plan_set_types": [_vp, _vp],
+    "hsim_plan_set_site_terms": [_vp, _vp, _vp],
     "hsim_batch_set_policies": [_vp, _i32, _vp, _vp, _dbl, _dbl],
     "hsim_batch_sigma": [_vp, _vp],
     "hsim_batch_phase_times": [_vp, _vp, _vp, _vp],
@@ -159,6 +160,12 @@ def hsim_plan_bonds(plan):
 def hsim_plan_set_types(plan, site_type):
     t = None if site_type is None else np.ascontiguousarray(site_type, dtype=np.int32)
     _check(lib().hsim_plan_set_types(plan, _ptr(t)))
+
+
+def hsim_plan_set_site_terms(plan, k_cubic=None, spin_norm=None):
+    kc = None if k_cubic is None else np.ascontiguousarray(k_cubic, dtype=np.float64)
+    mu = None if spin_norm is None else np.ascontiguousarray(spin_norm, dtype=np.float64)
+    _check(lib().hsim_plan_set_site_terms(plan, _ptr(kc), _ptr(mu)))
 
 
 def hsim_plan_destroy(plan):
@@ -334,6 +341,9 @@ class Plan:
         kp = self._keep
         self.handle = hsim_plan_create(self.n, kp["row_ptr"], kp["col"], kp["J"], kp["k"],
                                        kp["axis"], kp["ndir"])
+        kc, mu = getattr(lat, "kc", None), getattr(lat, "norm", None)
+        if kc is not None or mu is not None:
+            hsim_plan_set_site_terms(self.handle, kc, mu)
         self.info = hsim_plan_info(self.handle)
 
     def colouring(self):
