@@ -68,7 +68,8 @@ class _Outputs(ctypes.Structure):
     _fields_ = [("spins", ctypes.c_void_p), ("history", ctypes.c_void_p),
                 ("accept", ctypes.c_void_p), ("e_full", ctypes.c_void_p),
                 ("near_ties", ctypes.c_int64), ("max_incr_err", ctypes.c_double),
-                ("max_update_err", ctypes.c_double), ("n_decisions", ctypes.c_int64)]
+                ("max_update_err", ctypes.c_double), ("n_decisions", ctypes.c_int64),
+                ("type_mag", ctypes.c_void_p), ("snapshots", ctypes.c_void_p)]
 
 
 def lib():
@@ -242,17 +243,21 @@ def run(lat, T, B, mcs_per_step, seed, replica=0, init="random", spins=None,
         proposal=PROPOSAL_EXACT, first_step=0, recompute_every=100, order=None,
         colour=None, trace_accepts=False, full_energy=False, check_every_update=False,
         policies=None, site_type=None, sigma=None, sigma_min=SIGMA_MIN, sigma_max=SIGMA_MAX,
-        trace_sigma=False):
+        trace_sigma=False, type_mag=False, snapshots=False):
     """Colour-ordered Metropolis sweep of one replica over a T/B schedule.
 
     policies: None (random move everywhere) or a list of (policy, param) per
     site type; site_type: per-site type in user order (None: type 0); sigma:
     starting adaptive width (default: the adaptive type's param).
+    type_mag: record the magnetisation of every site type after every MCS
+    (site types from site_type, as many types as policies; without policies
+    one type); snapshots: record the spins at the end of every step.
 
     Returns a dict: history (S, M, 5) [E, Mx, My, Mz, n_acc], spins (n, 3),
     accept (S*M, n) uint8 or None, e_full (S*M,) or None, near_ties,
     max_incr_err, max_update_err, n_decisions, sigma (final adaptive width or
-    None), sigma_trace ((S*M,) width used in each MCS, or None).
+    None), sigma_trace ((S*M,) width used in each MCS, or None), type_mag
+    ((S, M, n_types, 3) or None), snapshots ((S, n, 3) or None).
     """
     T = np.ascontiguousarray(np.atleast_1d(T), dtype=np.float64)
     B = np.ascontiguousarray(np.broadcast_to(np.atleast_1d(B), T.shape), dtype=np.float64)
@@ -284,7 +289,10 @@ def run(lat, T, B, mcs_per_step, seed, replica=0, init="random", spins=None,
                 _ptr(order_a), _ptr(colour_a), 1 if check_every_update else 0,
                 ntypes, _ptr(st), _ptr(tp), _ptr(tq), float(sigma_min), float(sigma_max),
                 _ptr(sg), _ptr(strace))
-    o = _Outputs(_ptr(sp), _ptr(hist), _ptr(acc), _ptr(ef), 0, 0.0, 0.0, 0)
+    nt = max(ntypes, 1)
+    tm = np.zeros((S_steps, M, nt, 3)) if type_mag else None
+    snap = np.zeros((S_steps, n, 3)) if snapshots else None
+    o = _Outputs(_ptr(sp), _ptr(hist), _ptr(acc), _ptr(ef), 0, 0.0, 0.0, 0, _ptr(tm), _ptr(snap))
     rc = lib().or_run(L.ref, ctypes.byref(p), ctypes.byref(o))
     if rc != 0:
         raise ValueError(f"oracle run rejected its input (code {rc})")
@@ -292,7 +300,7 @@ def run(lat, T, B, mcs_per_step, seed, replica=0, init="random", spins=None,
     return dict(history=hist, spins=sp, accept=acc, e_full=ef, near_ties=o.near_ties,
                 max_incr_err=o.max_incr_err, max_update_err=o.max_update_err,
                 n_decisions=o.n_decisions, sigma=float(sg[0]) if has_ad else None,
-                sigma_trace=strace)
+                sigma_trace=strace, type_mag=tm, snapshots=snap)
 
 
 def run_replicas(jobs, threads=None):

@@ -705,6 +705,27 @@ int or_run(const or_lattice *lat, const or_params *p, or_outputs *out)
             }
             double *h = out->history + 5 * rec;
             h[0] = E; h[1] = Mx; h[2] = My; h[3] = Mz; h[4] = (double)nacc;
+            /* magnetisation of every site type ("the statistics of each
+             * magnetic phase"), sites in index order within a type */
+            if (out->type_mag) {
+                int32_t nt = p->n_types > 0 ? p->n_types : 1;
+                double *tm = out->type_mag + (size_t)rec * nt * 3;
+                for (int32_t t = 0; t < nt; ++t) {
+                    double x = 0.0, y = 0.0, z = 0.0;
+                    for (int64_t i = 0; i < n; ++i) {
+                        int32_t ty = (p->n_types > 0 && p->site_type) ? p->site_type[i] : 0;
+                        if (ty != t) continue;
+                        x = x + S[3 * i];
+                        y = y + S[3 * i + 1];
+                        z = z + S[3 * i + 2];
+                    }
+                    tm[3 * t] = x; tm[3 * t + 1] = y; tm[3 * t + 2] = z;
+                }
+            }
+            /* final state of the step ("the direction of every spin moment at
+             * the last MCS ... per temperature and magnetic field step") */
+            if (out->snapshots && m == M - 1)
+                memcpy(out->snapshots + (size_t)s * n * 3, S, sizeof(double) * 3 * (size_t)n);
             if (out->e_full) {
                 double sc, ef = or_energy(lat, b, S, NULL, NULL, NULL, &sc);
                 out->e_full[rec] = ef;

@@ -92,6 +92,11 @@ typedef struct {
     double max_incr_err;     /* max |E_incr - E_full| / scale over all MCS */
     double max_update_err;   /* max |dE - (E_after - E_before)| / scale */
     int64_t n_decisions;
+    /* per-type magnetisation after every MCS (NULL: not recorded):
+     * n_steps*mcs_per_step*n_types*3, sites grouped by p->site_type */
+    double *type_mag;
+    /* spins at the end of every step (NULL: not recorded): n_steps*n*3 */
+    double *snapshots;
 } or_outputs;
 
 /* Philox4x32 with 10 rounds (Salmon, Moraes, Dror and Shaw, SC'11). */
