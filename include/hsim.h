@@ -204,6 +204,20 @@ enum {
 };
 hsim_status hsim_batch_set_policies(hsim_batch b, int32_t n_types, const int32_t *policy,
                                     const double *param, double sigma_min, double sigma_max);
+/* Optional outputs of later runs (paper, feature list of section "VEGAS
+ * software package": the statistics of each magnetic phase, and the final
+ * state of every temperature/field step), caller-owned device buffers:
+ *   d_type_mag: NULL, or double [n_rep][n_steps][mcs][n_types][3] of the
+ *     bound history's shape: the magnetisation of every site type
+ *     (hsim_plan_set_types; all sites type 0 without it) after every MCS;
+ *     every site type must be below n_types (1..8);
+ *   d_snapshots: NULL, or double [n_rep][n_steps][n_max][3], n_max the
+ *     largest lattice of the batch: every replica's spins in user order at
+ *     the end of every step.
+ * The library keeps a small scratch for the per-type sums.  With outputs
+ * bound, PERSISTENT launches run as PLAIN launches. */
+hsim_status hsim_batch_bind_outputs(hsim_batch b, int32_t n_types, double *d_type_mag,
+                                    double *d_snapshots);
 /* Current adaptive width of every replica, host double [n_rep] (synchronous;
  * the batch must be bound). */
 hsim_status hsim_batch_sigma(hsim_batch b, double *sigma_out);

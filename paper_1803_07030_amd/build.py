@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libhsim.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["sweep_kernels.hip", "rep_kernels.hip", "energy_kernels.hip", "analysis_kernels.hip",
-           "plan.cpp", "batch.cpp", "api.cpp"]
+           "output_kernels.hip", "plan.cpp", "batch.cpp", "api.cpp"]
 ARCH = os.environ.get("HSIM_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
           "-Wno-unused-result", f"--offload-arch={ARCH}",

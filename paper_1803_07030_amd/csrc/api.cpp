@@ -29,6 +29,7 @@ void plan_set_types_impl(hsim_plan, const int32_t *);
 void plan_set_site_terms_impl(hsim_plan, const double *, const double *);
 void batch_set_policies_impl(hsim_batch, int32_t, const int32_t *, const double *, double, double);
 void batch_sigma_impl(hsim_batch, double *);
+void batch_bind_outputs_impl(hsim_batch, int32_t, double *, double *);
 namespace hsim {
 void analysis_thermal_impl(const double *, int32_t, int32_t, int32_t, int32_t, int64_t,
                            const double *, int32_t, const double *, double *, hipStream_t);
@@ -185,6 +186,12 @@ hsim_status hsim_batch_set_policies(hsim_batch b, int32_t n_types, const int32_t
                                     const double *param, double sigma_min, double sigma_max)
 {
     return guarded([&] { batch_set_policies_impl(b, n_types, policy, param, sigma_min, sigma_max); });
+}
+
+hsim_status hsim_batch_bind_outputs(hsim_batch b, int32_t n_types, double *d_type_mag,
+                                    double *d_snapshots)
+{
+    return guarded([&] { batch_bind_outputs_impl(b, n_types, d_type_mag, d_snapshots); });
 }
 
 hsim_status hsim_batch_sigma(hsim_batch b, double *sigma_out)

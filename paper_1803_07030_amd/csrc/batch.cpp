@@ -353,6 +353,29 @@ void batch_set_policies_impl(hsim_batch b, int32_t nt, const int32_t *policy, co
     }
 }
 
+// Optional outputs: per-type magnetisation [R][S][M][n_types][3] and step-end
+// spins [R][S][n_max][3] (device buffers of the caller; NULL: off).
+void batch_bind_outputs_impl(hsim_batch b, int32_t n_types, double *type_mag, double *snapshots)
+{
+    if (!b) throw Error(HSIM_E_ARG, "bind_outputs: NULL batch");
+    if (type_mag && (n_types < 1 || n_types > hsim::kMaxTypes))
+        throw Error(HSIM_E_ARG, "bind_outputs: n_types must be 1..8");
+    if (type_mag)
+        for (auto p : b->plans)
+            for (int32_t t : p->type)
+                if (t >= n_types) throw Error(HSIM_E_PARAM, "a site type is beyond n_types");
+    b->type_mag = type_mag;
+    b->snapshots = snapshots;
+    b->tm_types = type_mag ? n_types : 0;
+    b->d_tm_part.release();
+    if (type_mag) {
+        int64_t mn = 0;
+        for (auto p : b->plans) mn = std::max(mn, p->n);
+        const int nblk = hsim::type_part_blocks(b->layout == HSIM_LAYOUT_REPLICA, (int)mn);
+        b->d_tm_part.alloc((size_t)b->R * nblk * n_types * 3 * 8);
+    }
+}
+
 void batch_sigma_impl(hsim_batch b, double *out)
 {
     if (!b || !out) throw Error(HSIM_E_ARG, "sigma: NULL argument");
@@ -375,6 +398,15 @@ hsim::RunArgs hsim_batch_s::run_args(uint32_t g0, int n_mcs, int P, uint32_t *tr
     }
     a.rec_win = rec_win;
     a.pol = pol;
+    a.type_mag = type_mag;
+    a.tm_part = (double *)d_tm_part.p;
+    a.tm_types = tm_types;
+    a.snapshots = snapshots;
+    {
+        int64_t mn = 0;
+        for (auto p : plans) mn = std::max(mn, p->n);
+        a.snap_n = (int32_t)mn;
+    }
     a.sigma = (double *)(ws + off_sigma);
     a.n_ad = (const double *)d_nad.p;
     a.history = history;
@@ -467,9 +499,28 @@ struct PhaseTimer {
 
 // Site layout: MCS t_off = 0..count-1 of a launch sequence starting at
 // ctl->g (efull, colour phases, per-MCS reduction), then ctl->g moves on.
+// Optional outputs after MCS t of a sequence: per-type magnetisation; the
+// spins at a step end, which the host knows from the sequence's first MCS gb
+// (plain launches) or the device checks (dev_check: captured graphs).
+void enqueue_outputs(hsim_batch b, const hsim::RunArgs &ra, int t, uint32_t gb, bool dev_check,
+                     hipStream_t st)
+{
+    const bool rep = b->layout == HSIM_LAYOUT_REPLICA;
+    const auto *reps = (const hsim::RepDesc *)b->d_reps.p;
+    if (b->type_mag) {
+        if (rep) hip_check(hsim::launch_type_mag_rep(st, b->la, t, ra), "type launch");
+        else hip_check(hsim::launch_type_mag_site(st, b->f64, reps, b->R, ra.snap_n, t, ra), "type launch");
+    }
+    if (b->snapshots && (dev_check || (gb + (uint32_t)t + 1) % (uint32_t)ra.M == 0)) {
+        if (rep) hip_check(hsim::launch_snapshot_rep(st, b->la, t, dev_check, ra), "snapshot launch");
+        else hip_check(hsim::launch_snapshot_site(st, b->f64, reps, b->R, ra.snap_n, t, dev_check, ra),
+                       "snapshot launch");
+    }
+}
+
 template <typename F>
 void enqueue_site_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F efull_mask,
-                           hipStream_t st)
+                           hipStream_t st, uint32_t gb, bool dev_check)
 {
     const auto *reps = (const hsim::RepDesc *)b->d_reps.p;
     const auto *tiles = (const hsim::Tile *)b->d_tiles.p;
@@ -488,6 +539,7 @@ void enqueue_site_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F e
         }
         hip_check(hsim::launch_site_reduce(st, (const int32_t *)b->d_rep_tiles.p, b->ncol_max, t, ra),
                   "reduce launch");
+        enqueue_outputs(b, ra, t, gb, dev_check, st);
     }
     if (count > 0) hip_check(hsim::launch_ctl_advance(st, ra.ctl, (uint32_t)count), "control launch");
 }
@@ -499,7 +551,7 @@ void enqueue_site_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F e
 // recompute.
 template <typename F>
 void enqueue_rep_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F efull_mask,
-                          hipStream_t st)
+                          hipStream_t st, uint32_t gb, bool dev_check)
 {
     const int W = b->rec_win;
     for (int t = 0; t < count; ++t) {
@@ -514,6 +566,7 @@ void enqueue_rep_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F ef
         }
         if (ra.pol.adaptive)
             hip_check(hsim::launch_rep_sigma(st, b->la, b->rep_ntiles, t, ra), "sigma launch");
+        enqueue_outputs(b, ra, t, gb, dev_check, st);
         if ((t + 1) % W == 0 || t == count - 1) {
             const int first = t - t % W;
             hip_check(hsim::launch_rep_reduce(st, b->la, b->rep_ntiles, first, t - first + 1,
@@ -534,8 +587,8 @@ void run_plain(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st, int from, 
     // ctl->g is at g0 + from here
     const uint32_t gb = ra.g0 + (uint32_t)from;
     auto mask = [&](int t) { return due(gb + (uint32_t)t, ra.M, ra.P); };
-    if (b->layout == HSIM_LAYOUT_REPLICA) enqueue_rep_sequence(b, ra, to - from, mask, st);
-    else enqueue_site_sequence(b, ra, to - from, mask, st);
+    if (b->layout == HSIM_LAYOUT_REPLICA) enqueue_rep_sequence(b, ra, to - from, mask, st, gb, false);
+    else enqueue_site_sequence(b, ra, to - from, mask, st, gb, false);
 }
 
 void run_graph(hsim_batch b, const hsim::RunArgs &ra, hipStream_t user_st)
@@ -573,8 +626,8 @@ void run_graph(hsim_batch b, const hsim::RunArgs &ra, hipStream_t user_st)
     hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
         auto mask = [&](int t) { return efull_each || t == 0; };
-        if (b->layout == HSIM_LAYOUT_REPLICA) enqueue_rep_sequence(b, ra, U, mask, st);
-        else enqueue_site_sequence(b, ra, U, mask, st);
+        if (b->layout == HSIM_LAYOUT_REPLICA) enqueue_rep_sequence(b, ra, U, mask, st, 0, true);
+        else enqueue_site_sequence(b, ra, U, mask, st, 0, true);
     } catch (...) {
         (void)hipStreamEndCapture(st, &graph);
         if (graph) (void)hipGraphDestroy(graph);
@@ -675,12 +728,13 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
         if (b->tuned_launch >= 0) mode = b->tuned_launch;
         else mode = HSIM_LAUNCH_GRAPH;
     }
-    // the persistent kernel runs the random move of the plain model only:
-    // with update policies, cubic constants or spin norms the same sweep runs
-    // as plain launches
+    // the persistent kernel runs the random move of the plain model without
+    // optional outputs: with update policies, cubic constants, spin norms or
+    // outputs bound the same sweep runs as plain launches
     bool xt = false;
     for (auto p : b->plans) xt |= !p->kcd.empty() || !p->mud.empty();
-    if (mode == HSIM_LAUNCH_PERSISTENT && (b->pol.n_types > 0 || xt)) mode = HSIM_LAUNCH_PLAIN;
+    if (mode == HSIM_LAUNCH_PERSISTENT && (b->pol.n_types > 0 || xt || b->type_mag || b->snapshots))
+        mode = HSIM_LAUNCH_PLAIN;
     if (mode == HSIM_LAUNCH_PERSISTENT) {
         if (b->layout != HSIM_LAYOUT_REPLICA)
             throw Error(HSIM_E_UNSUPPORTED, "persistent launch needs the replica layout");

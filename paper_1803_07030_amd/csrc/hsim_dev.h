@@ -110,6 +110,12 @@ struct RunArgs {
     double *sigma;        // [R] adaptive width (when pol.adaptive)
     const double *n_ad;   // [R] sites under the adaptive move per replica
     double *sig_part;     // replica layout: [kChunks][Rp] partial adaptive accepts
+    // optional outputs (NULL: off)
+    double *type_mag;     // [R][S_hist][M][tm_types][3] magnetisation per site type
+    double *tm_part;      // per-type partial sums
+    int32_t tm_types;
+    double *snapshots;    // [R][S_hist][snap_n][3] spins at each step end, user order
+    int32_t snap_n;
 };
 
 struct RepLaneArgs {
@@ -170,6 +176,15 @@ hipError_t launch_rep_sigma(hipStream_t st, const RepLaneArgs &a, int ntiles, in
 // of the current sequence (count <= rec_win); advance > 0 closes the sequence.
 hipError_t launch_rep_reduce(hipStream_t st, const RepLaneArgs &a, int ntiles, int t_first,
                              int count, int advance, const RunArgs &ra);
+// Optional outputs (output_kernels.hip).
+int type_part_blocks(bool replica_layout, int max_n);
+hipError_t launch_type_mag_site(hipStream_t st, bool f64, const RepDesc *reps, int R, int max_n,
+                                int t_off, const RunArgs &ra);
+hipError_t launch_type_mag_rep(hipStream_t st, const RepLaneArgs &a, int t_off, const RunArgs &ra);
+hipError_t launch_snapshot_site(hipStream_t st, bool f64, const RepDesc *reps, int R, int max_n,
+                                int t_off, bool check, const RunArgs &ra);
+hipError_t launch_snapshot_rep(hipStream_t st, const RepLaneArgs &a, int t_off, bool check,
+                               const RunArgs &ra);
 hipError_t launch_rep_persistent(hipStream_t st, int kmode, int fmode, const RepLaneArgs &a,
                                  int ntiles, int grid, const RunArgs &ra, uint32_t *flags,
                                  uint32_t spin_cap);

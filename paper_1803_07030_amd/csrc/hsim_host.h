@@ -137,6 +137,10 @@ struct hsim_batch_s {
     hsim::DevBuf d_nad;
     double sigma0 = 1.0;
     size_t off_sigma = 0;
+    // optional outputs (caller-owned device buffers) and their scratch
+    double *type_mag = nullptr, *snapshots = nullptr;
+    int32_t tm_types = 0;
+    hsim::DevBuf d_tm_part;
     void reset_sigma();             // every replica's adaptive width to sigma0
     int32_t rec_win = 2;              // replica layout: MCS per record window
     // replica layout: bytes of the record window, its chunk sums and totals,

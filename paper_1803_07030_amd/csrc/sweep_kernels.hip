@@ -559,6 +559,29 @@ __global__ __launch_bounds__(1024) void k_block_sweep(const RepDesc *__restrict_
             if (ra.pol.adaptive) adapt_sigma(ra, rep, v[5]);
         }
         __syncthreads();
+        // optional outputs: magnetisation per site type, spins at a step end
+        if (ra.type_mag) {
+            for (int t = 0; t < ra.tm_types; ++t) {
+                double q[3] = {0.0, 0.0, 0.0};
+                for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                    if ((rd.type ? rd.type[i] : 0) != t) continue;
+                    q[0] += (double)S[i];
+                    q[1] += (double)S[np + i];
+                    q[2] += (double)S[2 * np + i];
+                }
+                block_sum<3>(q, red);
+                if (threadIdx.x == 0)
+                    for (int c = 0; c < 3; ++c)
+                        ra.type_mag[((sidx * ra.M + m) * ra.tm_types + t) * 3 + c] = q[c];
+            }
+        }
+        if (ra.snapshots && m + 1 == (uint32_t)ra.M)
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                double *o = ra.snapshots + (sidx * ra.snap_n + rd.orig[i]) * 3;
+                o[0] = (double)S[i];
+                o[1] = (double)S[np + i];
+                o[2] = (double)S[2 * np + i];
+            }
     }
     if (threadIdx.x == 0) ra.ecarry[rep] = E;
     if (LDS) {

@@ -73,6 +73,7 @@ _SIGNATURES = {
     "hsim_plan_set_site_terms": [_vp, _vp, _vp],
     "hsim_batch_set_policies": [_vp, _i32, _vp, _vp, _dbl, _dbl],
     "hsim_batch_sigma": [_vp, _vp],
+    "hsim_batch_bind_outputs": [_vp, _i32, _vp, _vp],
     "hsim_batch_phase_times": [_vp, _vp, _vp, _vp],
     "hsim_energy_forward": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp],
     "hsim_energy_backward": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp,
@@ -234,6 +235,10 @@ def hsim_batch_set_policies(batch, policies, sigma_min=SIGMA_MIN, sigma_max=SIGM
     _check(lib().hsim_batch_set_policies(batch, len(policies), _ptr(pol) if len(pol) else None,
                                          _ptr(prm) if len(prm) else None, float(sigma_min),
                                          float(sigma_max)))
+
+
+def hsim_batch_bind_outputs(batch, n_types, type_mag, snapshots):
+    _check(lib().hsim_batch_bind_outputs(batch, n_types, _ptr(type_mag), _ptr(snapshots)))
 
 
 def hsim_batch_sigma(batch, n_rep):
@@ -422,6 +427,19 @@ class Batch:
         """policies: list of (POLICY_*, param) per site type; [] for the
         random move everywhere."""
         hsim_batch_set_policies(self.handle, policies, sigma_min, sigma_max)
+        return self
+
+    def bind_outputs(self, type_mag_types=0, snapshots=False):
+        """Allocate and attach the optional outputs: self.type_mag
+        [R][S][M][n_types][3] (type_mag_types > 0) and self.snapshots
+        [R][S][n_max][3] (snapshots=True); 0 / False detaches."""
+        S, M = self.n_steps, self.mcs
+        nmax = max(p.n for p in self.plans)
+        self.type_mag = (torch.zeros((self.R, S, M, type_mag_types, 3), dtype=torch.float64,
+                                     device=self.device) if type_mag_types > 0 else None)
+        self.snapshots = (torch.zeros((self.R, S, nmax, 3), dtype=torch.float64, device=self.device)
+                          if snapshots else None)
+        hsim_batch_bind_outputs(self.handle, type_mag_types, self.type_mag, self.snapshots)
         return self
 
     def sigma(self):
