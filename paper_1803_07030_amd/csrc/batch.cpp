@@ -439,6 +439,7 @@ void batch_init_impl(hsim_batch b, int32_t mode, const double *host, hipStream_t
         given.alloc(cnt * 8);
         hip_check(hipMemcpy(given.p, host, cnt * 8, hipMemcpyHostToDevice), "hipMemcpy");
     }
+    if (b->total_sites == 0) return;   // lattices without sites: nothing to set
     if (b->layout == HSIM_LAYOUT_REPLICA) {
         hip_check(hsim::launch_init_spins_rep(st, b->la, mode, (const double *)given.p, b->seed),
                   "init launch");
@@ -713,6 +714,19 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
 
     const uint32_t g0 = (uint32_t)first_step * (uint32_t)b->M;
     const int n_mcs = n_steps * b->M;
+    if (b->total_sites == 0) {
+        // lattices without sites: every record of the run is E = M = accepted = 0
+        // (and every per-type magnetisation)
+        const size_t rows = (size_t)n_steps * b->M;
+        for (int r = 0; r < b->R; ++r) {
+            const size_t row0 = ((size_t)r * b->S_hist + first_step) * b->M;
+            hip_check(hipMemsetAsync(b->history + row0 * 5, 0, rows * 5 * 8, st), "hipMemsetAsync");
+            if (b->type_mag)
+                hip_check(hipMemsetAsync(b->type_mag + row0 * b->tm_types * 3, 0, rows * b->tm_types * 3 * 8, st),
+                          "hipMemsetAsync");
+        }
+        return;
+    }
     const hsim::RunArgs ra = b->run_args(g0, n_mcs, P, want_trace ? trace : nullptr);
     hip_check(hsim::launch_ctl_set(st, ra.ctl, g0), "control launch");
 
@@ -748,8 +762,10 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
 
 void batch_to_user_impl(hsim_batch b, int32_t rep, double *out, hipStream_t st)
 {
-    if (!b || !out || rep < 0 || rep >= b->R) throw Error(HSIM_E_ARG, "spins_to_user: bad argument");
+    if (!b || rep < 0 || rep >= b->R) throw Error(HSIM_E_ARG, "spins_to_user: bad argument");
     if (!b->bound) throw Error(HSIM_E_STATE, "spins_to_user before bind");
+    if (b->plans[rep]->n == 0) return;
+    if (!out) throw Error(HSIM_E_ARG, "spins_to_user: NULL out");
     if (b->layout == HSIM_LAYOUT_REPLICA)
         hip_check(hsim::launch_to_user_rep(st, b->la, rep, out), "to_user launch");
     else
@@ -828,7 +844,18 @@ void autotune_impl(hsim_batch b, const char *cache_path, int32_t trial_mcs, hipS
     saved.alloc(spb);
     hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
     hip_check(hipMemcpy(saved.p, b->spins, spb, hipMemcpyDeviceToDevice), "hipMemcpy");
-    // keep the caller's binding to restore it afterwards
+    // keep the caller's binding, adaptive widths, outputs and phase timing to
+    // restore them afterwards; the trial runs write none of the caller's outputs
+    std::vector<double> sig0((size_t)b->R);
+    hip_check(hipMemcpy(sig0.data(), b->ws + b->off_sigma, (size_t)b->R * 8, hipMemcpyDeviceToHost),
+              "hipMemcpy");
+    hsim::Ctl ctl0{};   // status flags of the caller's earlier runs
+    hip_check(hipMemcpy(&ctl0, b->ws, sizeof(hsim::Ctl), hipMemcpyDeviceToHost), "hipMemcpy");
+    double *tm0 = b->type_mag, *snap0 = b->snapshots;
+    const int32_t every0 = b->time_every;
+    b->type_mag = nullptr;
+    b->snapshots = nullptr;
+    b->time_every = 0;
     const int32_t S0 = b->S_hist, M0 = b->M;
     char *ws0 = b->ws;
     void *sp0 = b->spins;
@@ -880,9 +907,15 @@ void autotune_impl(hsim_batch b, const char *cache_path, int32_t trial_mcs, hipS
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // restore spins and the caller's binding
+    // restore spins, the caller's binding, widths, outputs and timing
+    b->type_mag = tm0;
+    b->snapshots = snap0;
+    b->time_every = every0;
     hip_check(hipMemcpy(sp0, saved.p, spb, hipMemcpyDeviceToDevice), "hipMemcpy");
     batch_bind_impl(b, S0, M0, ws0, sp0, h0);
+    hip_check(hipMemcpy(b->ws + b->off_sigma, sig0.data(), (size_t)b->R * 8, hipMemcpyHostToDevice),
+              "hipMemcpy");
+    hip_check(hipMemcpy(b->ws, &ctl0, sizeof(hsim::Ctl), hipMemcpyHostToDevice), "hipMemcpy");
     b->h_beta = beta0;
     b->h_bfield = bf0;
     if (!err.empty()) throw Error(HSIM_E_DEVICE, "autotune: " + err);

@@ -390,6 +390,10 @@ void energy_forward_impl(hsim_plan P, int32_t batch, hsim_precision prec, const 
     if (prec != HSIM_FP32 && prec != HSIM_FP64_EXACT) throw Error(HSIM_E_ARG, "bad precision");
     if (!std::isfinite(B)) throw Error(HSIM_E_PARAM, "non-finite field");
     if (batch == 0) return;
+    if (P->n == 0) {   // no sites: every energy is 0
+        hsim::hip_check(hipMemsetAsync(E, 0, (size_t)batch * 8, st), "hipMemsetAsync");
+        return;
+    }
     const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd, prec == HSIM_FP64_EXACT);
     double *scr = energy_scratch(P, batch);
     hsim::hip_check(hsim::launch_energy_forward(st, prec == HSIM_FP64_EXACT, a, scr, 0, E),
@@ -407,6 +411,10 @@ void energy_backward_impl(hsim_plan P, int32_t batch, hsim_precision prec, const
     if (prec != HSIM_FP32 && prec != HSIM_FP64_EXACT) throw Error(HSIM_E_ARG, "bad precision");
     if (!std::isfinite(B)) throw Error(HSIM_E_PARAM, "non-finite field");
     if (batch == 0) return;
+    if (P->n == 0) {   // no sites, no bonds: the field gradient is 0, the rest empty
+        if (gB) hsim::hip_check(hipMemsetAsync(gB, 0, 8, st), "hipMemsetAsync");
+        return;
+    }
     const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd, prec == HSIM_FP64_EXACT);
     double *scr = energy_scratch(P, batch);
     hsim::hip_check(hsim::launch_energy_backward(st, prec == HSIM_FP64_EXACT, a, gE, gS, gJ, gk, gB,
