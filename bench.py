@@ -71,6 +71,36 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
 
 
+def copy_bandwidth(stream, resident_bytes):
+    """Device-copy bandwidth on this GPU, the practical ceilings the sweep is
+    compared with: a 1 GiB copy (2 GiB moved, far beyond the 256 MB
+    last-level cache: HBM-bound) and a copy whose source plus destination
+    equal the spin set (cache-resident like the sweep's data).  GB/s counts
+    bytes read plus bytes written."""
+    import torch
+    out = {}
+    for name, nbytes in (("hbm_copy", 1 << 30), ("resident_copy", resident_bytes // 2)):
+        n = nbytes // 4
+        with torch.cuda.stream(stream):
+            a = torch.ones(n, dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record(stream)
+            for _ in range(reps):
+                b.copy_(a)
+            e1.record(stream)
+        stream.synchronize()
+        out[name + "_GBps"] = 2 * 4 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+        out[name + "_bytes"] = 2 * 4 * n
+        del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 # Sources of the dominant kernel; the committed byte counts in
 # profiles/rep_phase_traffic.json are used only while these hash the same.
 KERNEL_SOURCES = ["paper_1803_07030_amd/csrc/rep_kernels.hip", "paper_1803_07030_amd/csrc/update.h",
@@ -217,6 +247,12 @@ def main():
     }
     if tr is not None:
         out["roofline"]["traffic_vs_algorithmic"] = tr["bytes_per_launch"] / (balg * upd_per_launch)
+    cb = copy_bandwidth(stream, 3 * 4 * lat.n * 64)
+    cb["frac_achieved_vs_hbm_copy"] = achieved / cb["hbm_copy_GBps"]
+    if tr is not None:
+        cb["traffic_GBps"] = tr["bytes_per_launch"] / (launch_ms / 1e3) / 1e9
+        cb["frac_traffic_vs_resident_copy"] = cb["traffic_GBps"] / cb["resident_copy_GBps"]
+    out["copy_roofline"] = cb
     if not args.no_plain:
         out["plain_launch"] = plain_launch(lat, T, args.plain_mcs, stream)
         out["vs_plain_launch"] = value / out["plain_launch"]["value"]

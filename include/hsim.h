@@ -63,7 +63,9 @@ typedef enum { HSIM_FP32 = 0, HSIM_FP64_EXACT = 1 } hsim_precision;
 
 /* Spin layouts.  SITE: one lane per site of one replica, spins [3][n] per
  * replica.  REPLICA: replicas sharing one lattice, one lane per replica of
- * one site, spins [3][n][R padded to 64]; FP32 only.  BLOCK: each replica
+ * one site, spins [n][3][R padded to 32 or a multiple of 64] (rows of all
+ * replicas for one component of one site; [3][n][..] when the array is 2 GiB
+ * or more); FP32 only.  BLOCK: each replica
  * owned by one workgroup for the whole run (spins staged in LDS when they
  * fit).  AUTO lets the library choose. */
 typedef enum {
@@ -86,6 +88,8 @@ enum { HSIM_INIT_GIVEN = 0, HSIM_INIT_COLD_Z = 1, HSIM_INIT_RANDOM = 2 };
 /* Ingest one lattice (paper, section "Material building": sites, exchange
  * links with their constants, a field axis per site; anisotropy file: a
  * constant and an axis per site).
+ *   n_sites >= 0 (a lattice without sites is allowed: its replicas record
+ *     zero energy, magnetisation and acceptance);
  *   row_ptr [n+1] int64, col [nnz] int32: both directions of every link,
  *     J [nnz]: the constant of each entry; J must be symmetric.
  *   k [n] (NULL: 0), axis [3n] unit (NULL: +z), field_dir [3n] unit (NULL: +z).
@@ -159,8 +163,10 @@ hsim_status hsim_batch_info(hsim_batch b, hsim_batch_info_t *out);
 hsim_status hsim_batch_sizes(hsim_batch b, int32_t n_steps, int32_t mcs_per_step,
                              size_t *workspace_bytes, size_t *spin_bytes,
                              size_t *history_bytes);
-/* Attach caller-owned device buffers (sizes from hsim_batch_sizes, 256-byte
- * aligned).  Must precede init/run; may be called again to re-attach. */
+/* Attach caller-owned device buffers (sizes from hsim_batch_sizes, at least
+ * 16-byte aligned, else HSIM_E_ARG).  Must precede init/run; may be called
+ * again to re-attach (this clears the device status and resets the adaptive
+ * widths). */
 hsim_status hsim_batch_bind(hsim_batch b, int32_t n_steps, int32_t mcs_per_step,
                             void *d_workspace, void *d_spins, void *d_history);
 /* Initial state (paper, section "File Formats": initial-state file).
@@ -231,15 +237,23 @@ hsim_status hsim_batch_time_phases(hsim_batch b, int32_t every);
  * launches processed; then clears the record. */
 hsim_status hsim_batch_phase_times(hsim_batch b, double *total_ms, int64_t *launches,
                                    int64_t *updates);
-/* Replica rep's spins in user order, double [n][3], into device memory. */
+/* Replica rep's spins in user order, double [n][3], into device memory
+ * (nothing is written for a lattice without sites; d_out may then be NULL). */
 hsim_status hsim_batch_spins_to_user(hsim_batch b, int32_t rep, double *d_out, void *stream);
 /* Device status word after the stream has been synchronised: 0, or
  * HSIM_E_NUMERIC / HSIM_E_TIMEOUT.  Clears it. */
 hsim_status hsim_batch_status(hsim_batch b, int32_t *device_status_out);
-/* Time the launch modes and tile shapes available for this batch on
- * trial_mcs MCS (restoring the spins afterwards) and keep the fastest for
- * HSIM_LAUNCH_AUTO.  The choice never changes spin trajectories.  Results
- * are cached in cache_path (NULL: no file). */
+/* Time the launch modes available for this batch on one step of trial_mcs
+ * MCS at each replica's first bound temperature and field (plain and graph;
+ * in the replica layout also persistent grids of 1, 2, 4 and 8 blocks per
+ * CU) and keep the fastest for HSIM_LAUNCH_AUTO.  The trials use scratch
+ * buffers the call allocates and frees; afterwards the batch's spins,
+ * binding, adaptive widths, optional outputs, phase timing and device status
+ * are as before the call.  Synchronises the stream.  The choice never
+ * changes spin trajectories.  The block layout has nothing to choose (the
+ * call returns at once).  With cache_path (NULL: no file) a choice recorded
+ * for the same GPU, layout, replica count, precision and lattice sizes is
+ * reused; a new choice is appended to the file. */
 hsim_status hsim_autotune(hsim_batch b, const char *cache_path, int32_t trial_mcs,
                           void *stream);
 void hsim_batch_destroy(hsim_batch b);

@@ -5,12 +5,21 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <fstream>
 #include <limits>
+#include <sstream>
 
 #include "hsim_host.h"
 
 using hsim::Error;
 using hsim::hip_check;
+
+// Replica layout: the three component rows of a site side by side
+// ([n][3][Rp]; 1 to 2% faster colour phases on SC 64^3 than [3][n][Rp]);
+// 0 selects the planar layout.
+#ifndef HSIM_REP_INTERLEAVED
+#define HSIM_REP_INTERLEAVED 1
+#endif
 
 namespace {
 
@@ -210,6 +219,11 @@ void hsim_batch_s::upload_tables()
         la.n = (int32_t)P->n;
         la.Rp = Rp;
         la.R = R;
+        // spin rows: component c of site i at c*cs + i*ss (interleaved while
+        // the whole array stays below 2 GiB, so byte offsets fit 32 bits)
+        const bool inter = HSIM_REP_INTERLEAVED && 3 * (int64_t)P->n * Rp * 4 < ((int64_t)1 << 31);
+        la.ss = inter ? 3 * Rp : Rp;
+        la.cs = inter ? (int64_t)Rp : (int64_t)P->n * Rp;
         la.ncol = P->ncol;
         la.ell_w = P->ell_w;
         for (int c = 0; c <= P->ncol; ++c) la.cls_off[c] = P->cls_off[c];
@@ -793,9 +807,6 @@ int32_t batch_status_impl(hsim_batch b)
 // the fastest choice for HSIM_LAUNCH_AUTO.  Every candidate runs the same
 // per-site update and the same reduction order, so the choice changes
 // neither spins nor history.
-#include <cstdio>
-#include <fstream>
-#include <sstream>
 
 namespace {
 

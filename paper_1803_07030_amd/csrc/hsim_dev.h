@@ -128,10 +128,12 @@ struct RepLaneArgs {
     const float *ell_J;
     const uint32_t *orig;
     const float *k, *ax, *nd;   // per-site (K_SITE / F_SITE)
-    float *spins;               // [3][n][Rp]
+    float *spins;               // row of Rp floats per (component c, site i) at c*cs + i*ss
     const uint32_t *rep_id;     // [Rp]
+    int64_t cs;                 // component stride (floats)
     float k0, e0x, e0y, e0z, n0x, n0y, n0z;
     int32_t n, Rp, R;
+    int32_t ss;                 // site stride (floats): Rp or 3*Rp
     int32_t ncol, ell_w;        // ell_w: padded row width (6 or 8), 0 = CSR walk
     int32_t cls_off[kMaxColours + 1];
     int32_t tile_off[kMaxColours + 1];   // first tile of each colour

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kOT) void k_type_part_rep(RepLaneArgs a, int nblk, 
     __shared__ double lds[4 * 64 * 3];
     const int b = blockIdx.x;
     const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
-    const size_t plane = (size_t)a.n * a.Rp;
+    const size_t plane = (size_t)a.cs;
     const int i0 = b * 64, i1 = min(a.n, i0 + 64);
     for (int r0 = 0; r0 < a.R; r0 += 64) {
         const int r = r0 + lane;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kOT) void k_type_part_rep(RepLaneArgs a, int nblk, 
             if (r < a.R)
                 for (int i = i0 + slice; i < i1; i += 4) {
                     if ((a.type ? a.type[i] : 0) != t) continue;
-                    const size_t o = (size_t)i * a.Rp + r;
+                    const size_t o = (size_t)i * a.ss + r;
                     v[0] += (double)a.spins[o];
                     v[1] += (double)a.spins[plane + o];
                     v[2] += (double)a.spins[2 * plane + o];
@@ -131,9 +131,9 @@ __global__ void k_snapshot_rep(RepLaneArgs a, int t_off, int check, RunArgs ra)
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     if (check && (g + 1) % (uint32_t)ra.M != 0) return;
     const int i = blockIdx.x;
-    const size_t plane = (size_t)a.n * a.Rp;
+    const size_t plane = (size_t)a.cs;
     for (int r = threadIdx.x; r < a.R; r += blockDim.x) {
-        const size_t src = (size_t)i * a.Rp + r;
+        const size_t src = (size_t)i * a.ss + r;
         double *o = ra.snapshots + (((size_t)r * ra.S_hist + g / (uint32_t)ra.M) * ra.snap_n +
                                     a.orig[i]) * 3;
         o[0] = (double)a.spins[src];

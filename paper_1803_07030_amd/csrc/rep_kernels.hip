@@ -1,7 +1,8 @@
 // Replica-lane sweep: replicas that share one lattice are updated together,
-// one lane per replica of one site.  Spins are [3][n][Rp] (Rp = replicas
-// padded to the lane-group width W), so every neighbour read of a wave is a
-// contiguous 4*W-byte row and the CSR row of a site (offsets, columns,
+// one lane per replica of one site.  Spins are rows of Rp floats (Rp =
+// replicas padded to the lane-group width W), component c of site i at
+// spins + c*cs + i*ss (planar [3][n][Rp] or interleaved [n][3][Rp]), so every
+// neighbour read of a wave is a contiguous 4*W-byte row and the CSR row of a site (offsets, columns,
 // constants) is read once for W replicas.
 //
 // Paper: Eq. 1-2 (energy), Eq. 4 (acceptance), section "Monte Carlo
@@ -130,19 +131,19 @@ struct RepXt {
     }
 };
 
-// Update site i for replica lane r (spin column r of the [3][n][Rp] array),
+// Update site i for replica lane r (spin column r of the rows),
 // generic CSR row walk (rows of any degree).
 template <int KM, int FM, int VAR>
 __device__ __forceinline__ void rep_site_update(const RepLaneArgs &a, int i, int r, uint32_t g,
                                                 float beta, float b, uint32_t rid, bool active,
                                                 float sigma, const RunArgs &ra, double (&acc)[6])
 {
-    const size_t plane = (size_t)a.n * a.Rp;
+    const size_t plane = (size_t)a.cs;
     float *S = a.spins + r;
     const int32_t rb = a.rp[i], re = a.rp[i + 1];
     float hx = 0.0f, hy = 0.0f, hz = 0.0f;
     for (int32_t p = rb; p < re; ++p) {
-        const size_t o = (size_t)a.ci[p] * a.Rp;
+        const size_t o = (size_t)a.ci[p] * a.ss;
         const float Jp = a.J[p];
         hx = fmaf(Jp, S[o], hx);
         hy = fmaf(Jp, S[plane + o], hy);
@@ -152,7 +153,7 @@ __device__ __forceinline__ void rep_site_update(const RepLaneArgs &a, int i, int
     hx = fmaf(b, sp.nx, hx);
     hy = fmaf(b, sp.ny, hy);
     hz = fmaf(b, sp.nz, hz);
-    const size_t oi = (size_t)i * a.Rp;
+    const size_t oi = (size_t)i * a.ss;
     const float sx = S[oi], sy = S[plane + oi], sz = S[2 * plane + oi];
     bool ad;
     const RepXt<false> xt = (VAR & VAR_XT) ? RepXt<false>(a, i) : RepXt<false>();
@@ -184,17 +185,17 @@ __device__ __forceinline__ T cload(const T *p, int64_t i)
 // site-major); a slot past the row's end holds the site itself with constant
 // 0, which leaves the fused multiply-add chain of the field unchanged
 // (h + 0*S == h), so the padded walk gives the same bits as the CSR walk.
-// Buffer resources over the three spin planes (raw buffers; the host keeps a
-// plane below 2 GiB so that byte offsets fit the 32-bit offset fields).
+// Buffer resources over the rows of the three spin components (raw buffers
+// from each component's first row to its last; the host keeps that extent
+// below 2 GiB so that byte offsets fit the 32-bit offset fields).
 struct SpinPlanes {
     __amdgpu_buffer_rsrc_t x, y, z;
     __device__ __forceinline__ SpinPlanes(const RepLaneArgs &a)
     {
-        const size_t plane = (size_t)a.n * a.Rp;
-        const int bytes = (int)(plane * 4);
+        const int bytes = (int)(((int64_t)(a.n - 1) * a.ss + a.Rp) * 4);
         x = __builtin_amdgcn_make_buffer_rsrc(a.spins, 0, bytes, 0x00020000);
-        y = __builtin_amdgcn_make_buffer_rsrc(a.spins + plane, 0, bytes, 0x00020000);
-        z = __builtin_amdgcn_make_buffer_rsrc(a.spins + 2 * plane, 0, bytes, 0x00020000);
+        y = __builtin_amdgcn_make_buffer_rsrc(a.spins + a.cs, 0, bytes, 0x00020000);
+        z = __builtin_amdgcn_make_buffer_rsrc(a.spins + 2 * a.cs, 0, bytes, 0x00020000);
     }
 };
 
@@ -233,13 +234,13 @@ __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const Spi
         hz[u] = 0.0f;
 #pragma unroll
         for (int sl = 0; sl < MAXD; ++sl) {
-            const int32_t ob = cload(a.ell_col, ic[u] * MAXD + sl) * a.Rp * 4;   // row byte offset
+            const int32_t ob = cload(a.ell_col, ic[u] * MAXD + sl) * a.ss * 4;   // row byte offset
             const float Jp = cload(a.ell_J, ic[u] * MAXD + sl);
             hx[u] = fmaf(Jp, bload(sp3.x, lane_b, ob), hx[u]);
             hy[u] = fmaf(Jp, bload(sp3.y, lane_b, ob), hy[u]);
             hz[u] = fmaf(Jp, bload(sp3.z, lane_b, ob), hz[u]);
         }
-        const int32_t oi = ic[u] * a.Rp * 4;
+        const int32_t oi = ic[u] * a.ss * 4;
         sx[u] = bload(sp3.x, lane_b, oi);
         sy[u] = bload(sp3.y, lane_b, oi);
         sz[u] = bload(sp3.z, lane_b, oi);
@@ -264,7 +265,7 @@ __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const Spi
         const bool ok = accept32(dE, beta, t.u) && live;
         acc[5] += (ok && ad) ? 1.0 : 0.0;
         if (live && dE != dE) atomicOr(&ra.ctl->status, 1u);
-        const int32_t oi = i * a.Rp * 4;
+        const int32_t oi = i * a.ss * 4;
         // every live lane stores (the old value when rejected): whole rows
         // reach memory faster than rows with holes, though more bytes
         if (live) {
@@ -284,7 +285,7 @@ __device__ __forceinline__ void rep_pair_update(const RepLaneArgs &a, int i0, in
                                                 bool active, float sigma, const RunArgs &ra,
                                                 double (&acc)[6])
 {
-    const size_t plane = (size_t)a.n * a.Rp;
+    const size_t plane = (size_t)a.cs;
     float *S = a.spins + r;
     float hx[2], hy[2], hz[2], sx[2], sy[2], sz[2];
     int ic[2];
@@ -298,13 +299,13 @@ __device__ __forceinline__ void rep_pair_update(const RepLaneArgs &a, int i0, in
         hz[u] = 0.0f;
 #pragma unroll
         for (int sl = 0; sl < MAXD; ++sl) {
-            const size_t o = (size_t)a.ell_col[ic[u] * MAXD + sl] * a.Rp;
+            const size_t o = (size_t)a.ell_col[ic[u] * MAXD + sl] * a.ss;
             const float Jp = valid[u] ? a.ell_J[ic[u] * MAXD + sl] : 0.0f;
             hx[u] = fmaf(Jp, S[o], hx[u]);
             hy[u] = fmaf(Jp, S[plane + o], hy[u]);
             hz[u] = fmaf(Jp, S[2 * plane + o], hz[u]);
         }
-        const size_t oi = (size_t)ic[u] * a.Rp;
+        const size_t oi = (size_t)ic[u] * a.ss;
         sx[u] = S[oi];
         sy[u] = S[plane + oi];
         sz[u] = S[2 * plane + oi];
@@ -329,7 +330,7 @@ __device__ __forceinline__ void rep_pair_update(const RepLaneArgs &a, int i0, in
         const bool ok = accept32(dE, beta, t.u) && live;
         acc[5] += (ok && ad) ? 1.0 : 0.0;
         if (live && dE != dE) atomicOr(&ra.ctl->status, 1u);
-        const size_t oi = (size_t)i * a.Rp;
+        const size_t oi = (size_t)i * a.ss;
         if (ok) {
             S[oi] = t.x;
             S[plane + oi] = t.y;
@@ -342,18 +343,18 @@ __device__ __forceinline__ void rep_pair_update(const RepLaneArgs &a, int i0, in
 template <int KM, int FM>
 __device__ __forceinline__ double rep_site_energy(const RepLaneArgs &a, int i, int r, double b)
 {
-    const size_t plane = (size_t)a.n * a.Rp;
+    const size_t plane = (size_t)a.cs;
     const float *S = a.spins + r;
     double hx = 0.0, hy = 0.0, hz = 0.0;
     for (int32_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
-        const size_t o = (size_t)a.ci[p] * a.Rp;
+        const size_t o = (size_t)a.ci[p] * a.ss;
         const double Jp = (double)a.J[p];
         hx += Jp * (double)S[o];
         hy += Jp * (double)S[plane + o];
         hz += Jp * (double)S[2 * plane + o];
     }
     const RepSite<KM, FM> sp(a, i);
-    const size_t oi = (size_t)i * a.Rp;
+    const size_t oi = (size_t)i * a.ss;
     const double sx = S[oi], sy = S[plane + oi], sz = S[2 * plane + oi];
     const double an = sx * (double)sp.ex + sy * (double)sp.ey + sz * (double)sp.ez;
     const double zn = sx * (double)sp.nx + sy * (double)sp.ny + sz * (double)sp.nz;
@@ -371,14 +372,14 @@ __device__ __forceinline__ double rep_site_energy_ell(const RepLaneArgs &a, cons
     double hx = 0.0, hy = 0.0, hz = 0.0;
 #pragma unroll
     for (int sl = 0; sl < MAXD; ++sl) {
-        const int32_t ob = cload(a.ell_col, i * MAXD + sl) * a.Rp * 4;
+        const int32_t ob = cload(a.ell_col, i * MAXD + sl) * a.ss * 4;
         const double Jp = (double)cload(a.ell_J, i * MAXD + sl);
         hx += Jp * (double)bload(sp3.x, lane_b, ob);
         hy += Jp * (double)bload(sp3.y, lane_b, ob);
         hz += Jp * (double)bload(sp3.z, lane_b, ob);
     }
     const RepSite<KM, FM, true> sp(a, i);
-    const int32_t oi = i * a.Rp * 4;
+    const int32_t oi = i * a.ss * 4;
     const double sx = bload(sp3.x, lane_b, oi), sy = bload(sp3.y, lane_b, oi),
                  sz = bload(sp3.z, lane_b, oi);
     const double an = sx * (double)sp.ex + sy * (double)sp.ey + sz * (double)sp.ez;
@@ -893,7 +894,7 @@ __global__ __launch_bounds__(kRepThreads) void k_rep_persistent(RepLaneArgs a, i
 __global__ void k_init_spins_rep(RepLaneArgs a, int mode, const double *given, uint64_t seed)
 {
     const int i = blockIdx.x;
-    const size_t plane = (size_t)a.n * a.Rp;
+    const size_t plane = (size_t)a.cs;
     for (int r = threadIdx.x; r < a.Rp; r += blockDim.x) {
         double x = 0.0, y = 0.0, z = 1.0;
         if (r < a.R) {
@@ -913,7 +914,7 @@ __global__ void k_init_spins_rep(RepLaneArgs a, int mode, const double *given, u
                 z = mu * z;
             }
         }
-        const size_t oi = (size_t)i * a.Rp + r;
+        const size_t oi = (size_t)i * a.ss + r;
         a.spins[oi] = (float)x;
         a.spins[plane + oi] = (float)y;
         a.spins[2 * plane + oi] = (float)z;
@@ -924,7 +925,7 @@ __global__ void k_to_user_rep(RepLaneArgs a, int rep, double *out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-    const size_t plane = (size_t)a.n * a.Rp, oi = (size_t)i * a.Rp + rep;
+    const size_t plane = (size_t)a.cs, oi = (size_t)i * a.ss + rep;
     const uint32_t o = a.orig[i];
     out[3 * (size_t)o] = a.spins[oi];
     out[3 * (size_t)o + 1] = a.spins[plane + oi];

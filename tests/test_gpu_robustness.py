@@ -287,3 +287,31 @@ def test_zero_and_infinite_temperature_replica_layout():
             if np.isinf(T[r]):
                 assert acc.all() and h[r, 0, 0, 4] == lat.n
         assert total <= 2
+
+
+# ------------------------------------------- planar spin rows (large arrays)
+def test_replica_layout_planar_rows_for_arrays_over_2gib():
+    """SC 142^3 (2.86M sites) with 64 replicas: the spin array passes 2 GiB,
+    so the replica layout keeps each component in a plane of its own; two
+    MCS give the same spins as the site layout, bit for bit."""
+    lat = synth.sc_periodic(142)
+    lat.k = np.full(lat.n, 0.1)
+    assert 3 * lat.n * 64 * 4 >= 1 << 31
+    plan = hsim.Plan(lat)
+    R = 64
+    T = np.linspace(0.2, 2.8, R)[:, None]
+    out = {}
+    for name, layout in (("rep", hsim.LAYOUT_REPLICA), ("site", hsim.LAYOUT_SITE)):
+        b = hsim.Batch([plan] * R, seed=23, precision=hsim.FP32, layout=layout).bind(1, 2)
+        b.init_spins(hsim.INIT_RANDOM)
+        b.run(T, 0.0, launch=hsim.LAUNCH_PLAIN)
+        torch.cuda.synchronize()
+        assert b.status() == 0, name
+        out[name] = [b.spins_user(r).cpu().numpy() for r in (0, 37, 63)]
+        h = b.history.cpu().numpy()
+        out[name + "_acc"] = h[..., 4]
+        del b
+        torch.cuda.empty_cache()
+    for x, y in zip(out["rep"], out["site"]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(out["rep_acc"], out["site_acc"])
