@@ -180,6 +180,8 @@ def main():
             batch.set_policies([pol])
         Tm = T[:, None]
         timed_phases = args.launch == "plain" and args.time_every > 0
+        if args.launch == "auto":
+            batch.autotune(trial_mcs=20)         # untimed: picks the launch AUTO runs use
 
         def one_step():
             batch.init_spins(hsim.INIT_COLD_Z)
@@ -271,8 +273,9 @@ def b_alg_site_lane(zbar, a):
 def films_bench(args, stream):
     """256 diluted films (L in 16..128, d in 2..10, 10% vacancies, per-bond J
     in [0.5, 1.5], K = 0.05 z), each film one replica at its own temperature
-    in [0.2, 2.0], single precision, site-lane layout, plain launches with the
-    colour-phase launches of every n-th MCS timed."""
+    in [0.2, 2.0], single precision, site-lane layout.  Plain launches time
+    the colour-phase launches of every n-th MCS; graph and autotuned launches
+    are timed per step."""
     import torch
     import synth
     from paper_1803_07030_amd import hsim
@@ -280,39 +283,53 @@ def films_bench(args, stream):
     films, Ts = synth.film_batch()
     nsites = sum(f.n for f in films)
     zbar = sum(f.nnz for f in films) / nsites
+    launch = dict(persistent=hsim.LAUNCH_PERSISTENT, graph=hsim.LAUNCH_GRAPH,
+                  plain=hsim.LAUNCH_PLAIN, auto=hsim.LAUNCH_AUTO)[args.launch]
+    if launch == hsim.LAUNCH_PERSISTENT:
+        sys.exit("the persistent launch needs the replica layout; films use the site layout")
+    timed_phases = launch == hsim.LAUNCH_PLAIN and args.time_every > 0
     with torch.cuda.stream(stream):
         plans = [hsim.Plan(f) for f in films]
         batch = hsim.Batch(plans, seed=3, precision=hsim.FP32, layout=hsim.LAYOUT_SITE).bind(1, mcs)
         Tm = np.asarray(Ts)[:, None]
+        if launch == hsim.LAUNCH_AUTO:
+            batch.autotune(trial_mcs=20)
         for _ in range(args.warmup):
             batch.init_spins(hsim.INIT_COLD_Z)
-            batch.run(Tm, 0.0, launch=hsim.LAUNCH_PLAIN)
+            batch.run(Tm, 0.0, launch=launch)
         stream.synchronize()
-        batch.phase_times()
-        batch.time_phases(args.time_every)
+        if timed_phases:
+            batch.phase_times()
+            batch.time_phases(args.time_every)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             batch.init_spins(hsim.INIT_COLD_Z)
-            batch.run(Tm, 0.0, launch=hsim.LAUNCH_PLAIN)
+            batch.run(Tm, 0.0, launch=launch)
         stream.synchronize()
         wall = time.perf_counter() - t0
         assert batch.status() == 0
-        ph_ms, ph_n, ph_upd = batch.phase_times()
-        batch.time_phases(0)
+        if timed_phases:
+            ph_ms, ph_n, ph_upd = batch.phase_times()
+            batch.time_phases(0)
         hist = batch.history.cpu().numpy()
     acc = float(hist[..., 4].sum() / (nsites * mcs))
     balg = b_alg_site_lane(zbar, acc)
-    achieved = balg * ph_upd / (ph_ms / 1e3) / 1e9
+    if timed_phases:
+        kernel, launch_ms, upd, n_timed = "k_site_phase", ph_ms / ph_n, ph_upd / ph_n, ph_n
+    else:
+        kernel, launch_ms, upd, n_timed = "step", wall / args.steps * 1e3, nsites * mcs, args.steps
+    achieved = balg * upd / (launch_ms / 1e3) / 1e9
     print(json.dumps({
         "metric": "spin updates/sec, site-lane films batch", "value": nsites * mcs * args.steps / wall,
         "unit": "spin updates/s", "steps": args.steps, "warmup": args.warmup,
-        "config": {"workload": f"256 diluted films, {nsites} sites, {mcs} MCS, f32, site-lane, plain launch",
-                   "sites": nsites, "mean_degree": zbar},
+        "config": {"workload": f"256 diluted films, {nsites} sites, {mcs} MCS, f32, site-lane, "
+                               f"{args.launch} launch",
+                   "sites": nsites, "mean_degree": zbar, "launch": args.launch},
         "acceptance": acc,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "kernel": "k_site_phase",
-                     "launch_ms": ph_ms / ph_n, "updates_per_launch": ph_upd / ph_n,
-                     "bytes_per_update": balg, "timed_launches": ph_n}}))
+                     "frac": achieved / HBM_PEAK_GBS, "kernel": kernel,
+                     "launch_ms": launch_ms, "updates_per_launch": upd,
+                     "bytes_per_update": balg, "timed_launches": n_timed}}))
 
 
 def policies_bench(args, stream):

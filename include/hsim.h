@@ -246,7 +246,8 @@ hsim_status hsim_batch_status(hsim_batch b, int32_t *device_status_out);
 /* Time the launch modes available for this batch on one step of trial_mcs
  * MCS at each replica's first bound temperature and field (plain and graph;
  * in the replica layout also persistent grids of 1, 2, 4 and 8 blocks per
- * CU) and keep the fastest for HSIM_LAUNCH_AUTO.  The trials use scratch
+ * CU) and keep the fastest for HSIM_LAUNCH_AUTO (another mode than plain
+ * only when it beats plain launches by more than 2%).  The trials use scratch
  * buffers the call allocates and frees; afterwards the batch's spins,
  * binding, adaptive widths, optional outputs, phase timing and device status
  * are as before the call.  Synchronises the stream.  The choice never
