@@ -204,10 +204,18 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t rs, int32_t lane_b
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, lane_b, row_b, 0));
 }
 
+// Spin rows are stored with the SC1 cache-policy bit (device scope): the
+// colour phases ran 3.4% faster than with default stores (59.1 against
+// 61.2 us on SC 64^3 x 64 replicas; NT, SC0|SC1 and NT|SC1 were no better or
+// slower).  The bit changes how the stores travel through the caches, not
+// what memory holds at the end of the launch.
+constexpr int kSpinStorePolicy = 16;
+
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t rs, int32_t lane_b, int32_t row_b,
                                        float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, lane_b, row_b, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, lane_b, row_b,
+                                          kSpinStorePolicy);
 }
 
 // kRepSitesPerStep sites of one 64-lane group at once, rows padded to MAXD:
