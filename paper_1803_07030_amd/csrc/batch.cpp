@@ -734,10 +734,14 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
         const size_t rows = (size_t)n_steps * b->M;
         for (int r = 0; r < b->R; ++r) {
             const size_t row0 = ((size_t)r * b->S_hist + first_step) * b->M;
-            hip_check(hipMemsetAsync(b->history + row0 * 5, 0, rows * 5 * 8, st), "hipMemsetAsync");
+            // a fill kernel, not a memset: callers may capture runs in graphs
+            hip_check(hsim::launch_fill_u32(st, (uint32_t *)(b->history + row0 * 5), 0u,
+                                            (int64_t)(rows * 5 * 2)),
+                      "fill launch");
             if (b->type_mag)
-                hip_check(hipMemsetAsync(b->type_mag + row0 * b->tm_types * 3, 0, rows * b->tm_types * 3 * 8, st),
-                          "hipMemsetAsync");
+                hip_check(hsim::launch_fill_u32(st, (uint32_t *)(b->type_mag + row0 * b->tm_types * 3), 0u,
+                                                (int64_t)(rows * b->tm_types * 3 * 2)),
+                          "fill launch");
         }
         return;
     }

@@ -391,7 +391,8 @@ void energy_forward_impl(hsim_plan P, int32_t batch, hsim_precision prec, const 
     if (!std::isfinite(B)) throw Error(HSIM_E_PARAM, "non-finite field");
     if (batch == 0) return;
     if (P->n == 0) {   // no sites: every energy is 0
-        hsim::hip_check(hipMemsetAsync(E, 0, (size_t)batch * 8, st), "hipMemsetAsync");
+        // a fill kernel, not a memset: callers may capture these calls in graphs
+        hsim::hip_check(hsim::launch_fill_u32(st, (uint32_t *)E, 0u, (int64_t)batch * 2), "fill launch");
         return;
     }
     const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd, prec == HSIM_FP64_EXACT);
@@ -412,7 +413,7 @@ void energy_backward_impl(hsim_plan P, int32_t batch, hsim_precision prec, const
     if (!std::isfinite(B)) throw Error(HSIM_E_PARAM, "non-finite field");
     if (batch == 0) return;
     if (P->n == 0) {   // no sites, no bonds: the field gradient is 0, the rest empty
-        if (gB) hsim::hip_check(hipMemsetAsync(gB, 0, 8, st), "hipMemsetAsync");
+        if (gB) hsim::hip_check(hsim::launch_fill_u32(st, (uint32_t *)gB, 0u, 2), "fill launch");
         return;
     }
     const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd, prec == HSIM_FP64_EXACT);
