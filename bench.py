@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -108,11 +109,19 @@ KERNEL_SOURCES = ["paper_1803_07030_amd/csrc/rep_kernels.hip", "paper_1803_07030
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rep_phase_traffic.json")
 
 
+def _code_only(text):
+    """C++ source without comments and with whitespace runs collapsed, so that
+    an edit of comments alone keeps the hash."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_hash():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -11,7 +11,8 @@
 // with its own temperature and field schedule.
 //
 // A tile is kRepTile consecutive sites of one colour class; wave w of the
-// tile's block takes kRepSitesPerWave of them, two at a time, in order.
+// tile's block takes kRepSitesPerWave of them in order (kRepSitesPerStep at
+// a time with 64-lane groups, two at a time with 32-lane groups).
 // Per-MCS history: every tile writes one record per replica; records are
 // summed in 64 fixed chunks of tiles, and the chunks in order, the same way in
 // every launch mode.  Plain and graph launches keep the records of a window of
