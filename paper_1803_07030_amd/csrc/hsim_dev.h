@@ -139,6 +139,15 @@ struct RepLaneArgs {
     int32_t tile_off[kMaxColours + 1];   // first tile of each colour
 };
 
+// XCD-aware bijection of [0, nt): blocks are dispatched round-robin over the
+// 8 XCDs, so block b runs on XCD b % 8; give each XCD a contiguous range of
+// tiles, so that a tile and the tiles holding its neighbours share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nt)
+{
+    const int q = nt >> 3, rm = nt & 7, x = b & 7, k = b >> 3;
+    return x * q + min(x, rm) + k;
+}
+
 // ------------------------------------------------------------- launchers
 // All return hipError_t of the launch.  Template choices are resolved inside.
 hipError_t launch_ctl_set(hipStream_t st, Ctl *ctl, uint32_t g);

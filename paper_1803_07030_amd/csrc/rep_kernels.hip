@@ -412,15 +412,6 @@ struct Lanes {
     }
 };
 
-// XCD-aware bijection of [0, nt): blocks are dispatched round-robin over the
-// 8 XCDs, so block b runs on XCD b % 8; give each XCD a contiguous range of
-// tiles, so that a tile and the tiles holding its neighbours share an L2.
-__device__ __forceinline__ int xcd_tile(int b, int nt)
-{
-    const int q = nt >> 3, rm = nt & 7, x = b & 7, k = b >> 3;
-    return x * q + min(x, rm) + k;
-}
-
 // One tile of one colour phase: the body shared by the per-phase kernel and
 // the persistent kernel.  red: LDS [kRepWaves][64][NQ].  MAXD > 0: rows padded
 // to MAXD entries; MAXD == 0: generic row walk.  VAR: VAR_POL update

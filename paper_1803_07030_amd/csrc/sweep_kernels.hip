@@ -355,7 +355,8 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_phase(const RepDesc *__rest
                                                            int tile_off, int t_off, RunArgs ra)
 {
     __shared__ double red[(kSiteBlock / 64) * 6];
-    const Tile t = tiles[tile_off + blockIdx.x];
+    const int tl = tile_off + xcd_tile((int)blockIdx.x, (int)gridDim.x);   // this block's tile
+    const Tile t = tiles[tl];
     const RepDesc &rd = reps[t.rep];
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     const uint32_t s_abs = g / (uint32_t)ra.M;
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_phase(const RepDesc *__rest
     double v[6] = {acc[0], acc[1], acc[2], acc[3], acc[4], ad};
     block_sum<6>(v, red);
     if (threadIdx.x == 0) {
-        double *rec = ra.partials + (size_t)(tile_off + blockIdx.x) * kRecSite;
+        double *rec = ra.partials + (size_t)tl * kRecSite;
 #pragma unroll
         for (int q = 0; q < 5; ++q) rec[q] = v[q];
         rec[6] = v[5];
@@ -387,7 +388,8 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_efull(const RepDesc *__rest
     __shared__ double red[(kSiteBlock / 64)];
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     if (!recompute_due(g % (uint32_t)ra.M, ra.P)) return;
-    const Tile t = tiles[blockIdx.x];
+    const int tl = xcd_tile((int)blockIdx.x, (int)gridDim.x);   // this block's tile
+    const Tile t = tiles[tl];
     const RepDesc &rd = reps[t.rep];
     const uint32_t s_abs = g / (uint32_t)ra.M;
     const double b = ra.bfield[(size_t)t.rep * ra.S_hist + s_abs];
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_efull(const RepDesc *__rest
     const int i = t.begin + (int)threadIdx.x;
     if (i < t.end) e[0] = site_energy<T, KM, FM>(rd, (const T *)rd.spins, i, b);
     block_sum<1>(e, red);
-    if (threadIdx.x == 0) ra.partials[(size_t)blockIdx.x * kRecSite + 5] = e[0];
+    if (threadIdx.x == 0) ra.partials[(size_t)tl * kRecSite + 5] = e[0];
 }
 
 // Per-MCS history: one wave per replica (four per block); lanes stride the
