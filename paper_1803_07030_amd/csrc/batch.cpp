@@ -110,10 +110,28 @@ hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
         if (lay == HSIM_LAYOUT_REPLICA) {
             hsim_plan P = plans[0];
             b->Rp = R > 32 ? (int32_t)((R + 63) / 64 * 64) : 32;
+            // sites per wave of a tile: the full kRepSitesPerWave while the
+            // largest colour phase has at least 4 blocks per CU, else halved
+            // (down to 4) so that small lattices still fill the GPU
+            const int cus = device_cus() > 0 ? device_cus() : 256;
+            const int cols = b->Rp % 64 == 0 ? b->Rp / 64 : 1;   // lane columns per tile
+            auto phase_blocks = [&](int spw) {
+                int64_t mx = 0;
+                for (int c = 0; c < P->ncol; ++c) {
+                    const int64_t sz = P->cls_off[c + 1] - P->cls_off[c];
+                    mx = std::max<int64_t>(mx, (sz + hsim::kRepWaves * spw - 1) / (hsim::kRepWaves * spw));
+                }
+                return mx * cols;
+            };
+            int spw = hsim::kRepSitesPerWave;
+            while (spw % 8 == 0 && spw / 2 % hsim::kRepSitesPerStep == 0 && phase_blocks(spw) < 4 * (int64_t)cus)
+                spw /= 2;
+            b->la.spw = spw;
+            const int tile = hsim::kRepWaves * spw;
             b->la.tile_off[0] = 0;
             for (int c = 0; c < P->ncol; ++c) {
                 const int sz = P->cls_off[c + 1] - P->cls_off[c];
-                b->la.tile_off[c + 1] = b->la.tile_off[c] + (sz + hsim::kRepTile - 1) / hsim::kRepTile;
+                b->la.tile_off[c + 1] = b->la.tile_off[c] + (sz + tile - 1) / tile;
             }
             b->rep_ntiles = b->la.tile_off[P->ncol];
             // records of up to 64 MCS, about 256 MiB at most (2 at least)

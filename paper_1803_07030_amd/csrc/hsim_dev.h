@@ -24,10 +24,10 @@ constexpr int kRepThreads = kRepWaves * 64;
 // sites whose loads a wave issues together (64-lane groups); divides the
 // sites per wave
 constexpr int kRepSitesPerStep = HSIM_REP_SITES_PER_STEP;
-static_assert(kRepSitesPerWave % kRepSitesPerStep == 0 && kRepSitesPerWave % 2 == 0,
-              "sites per wave must be a multiple of the sites per step and even");
+static_assert(kRepSitesPerWave % kRepSitesPerStep == 0 && kRepSitesPerWave % 4 == 0,
+              "sites per wave must be a multiple of the sites per step and of 4");
 constexpr int kMaxPersistentBlocks = 4096;   // barrier flags reserved in the workspace
-constexpr int kRepTile = kRepWaves * kRepSitesPerWave;   // sites per replica-lane tile
+constexpr int kRepTile = kRepWaves * kRepSitesPerWave;   // sites per replica-lane tile (at most)
 constexpr int kRecSite = 8;         // doubles per site-lane partial record
 constexpr int kRecFields = 7;       // dE, Mx, My, Mz, n_acc, E_full, adaptive accepts
 constexpr int kChunks = 64;         // replica layout: chunks of the per-MCS record sum
@@ -134,6 +134,7 @@ struct RepLaneArgs {
     float k0, e0x, e0y, e0z, n0x, n0y, n0z;
     int32_t n, Rp, R;
     int32_t ss;                 // site stride (floats): Rp or 3*Rp
+    int32_t spw;                // sites per wave of a tile: a multiple of 4, at most kRepSitesPerWave
     int32_t ncol, ell_w;        // ell_w: padded row width (6 or 8), 0 = CSR walk
     int32_t cls_off[kMaxColours + 1];
     int32_t tile_off[kMaxColours + 1];   // first tile of each colour

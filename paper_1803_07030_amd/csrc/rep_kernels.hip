@@ -10,8 +10,9 @@
 // (section "VEGAS software package").  Replicas are independent chains, each
 // with its own temperature and field schedule.
 //
-// A tile is kRepTile consecutive sites of one colour class; wave w of the
-// tile's block takes kRepSitesPerWave of them in order (kRepSitesPerStep at
+// A tile is kRepWaves * spw consecutive sites of one colour class (spw =
+// kRepSitesPerWave, or fewer for small lattices); wave w of the tile's block
+// takes spw of them in order (kRepSitesPerStep at
 // a time with 64-lane groups, two at a time with 32-lane groups).
 // Per-MCS history: every tile writes one record per replica; records are
 // summed in 64 fixed chunks of tiles, and the chunks in order, the same way in
@@ -422,12 +423,12 @@ __device__ __forceinline__ void rep_tile(const RepLaneArgs &a, int colour, int t
                                          uint32_t g, const RunArgs &ra, double *part,
                                          double *red)
 {
-    constexpr int SPL = kRepSitesPerWave * W / 64;   // sites per lane group
+    const int SPL = a.spw * W / 64;   // sites per lane group (even for W = 32)
     constexpr bool POL = (VAR & VAR_POL) != 0;
     constexpr int NQ = POL ? 6 : 5;
     const Lanes<W> L(group);
     const int ce = a.cls_off[colour + 1];
-    const int wbase = a.cls_off[colour] + tile * kRepTile + L.w * kRepSitesPerWave;
+    const int wbase = a.cls_off[colour] + tile * (kRepWaves * a.spw) + L.w * a.spw;
     const int base = wbase + L.sub * SPL;
     const bool active = L.r < a.R;
     const uint32_t s_abs = g / (uint32_t)ra.M;
@@ -484,13 +485,13 @@ __device__ __forceinline__ void rep_tile_energy(const RepLaneArgs &a, int tg, in
                                                 uint32_t g, const RunArgs &ra, double *part,
                                                 double *red)
 {
-    constexpr int SPL = kRepSitesPerWave * W / 64;
+    const int SPL = a.spw * W / 64;
     const Lanes<W> L(group);
     int colour = 0;
     while (colour + 1 < a.ncol && a.tile_off[colour + 1] <= tg) ++colour;
     const int tile = tg - a.tile_off[colour];
     const int ce = a.cls_off[colour + 1];
-    const int base = a.cls_off[colour] + tile * kRepTile + L.w * kRepSitesPerWave + L.sub * SPL;
+    const int base = a.cls_off[colour] + tile * (kRepWaves * a.spw) + L.w * a.spw + L.sub * SPL;
     double e = 0.0;
     if (L.r < a.R) {
         const double b = ra.bfield[(size_t)L.r * ra.S_hist + g / (uint32_t)ra.M];
