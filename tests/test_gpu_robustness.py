@@ -315,3 +315,29 @@ def test_replica_layout_planar_rows_for_arrays_over_2gib():
     for x, y in zip(out["rep"], out["site"]):
         assert np.array_equal(x, y)
     assert np.array_equal(out["rep_acc"], out["site_acc"])
+
+
+# ---------------------------------------------- tile sizes of the replica layout
+@pytest.mark.parametrize("L", [48, 56], ids=["sc48", "sc56"])
+def test_replica_tiles_of_every_size_match_the_site_layout(L):
+    """The replica layout sizes its tiles to the lattice (4 to 32 sites per
+    wave: SC 48^3 and 56^3 with 64 replicas take the intermediate sizes on a
+    256-CU GPU; smaller lattices in other tests take 4, SC 64^3 takes 32):
+    spins and accept counts equal the site layout's after 3 MCS."""
+    lat = synth.sc_periodic(L)
+    lat.k = np.full(lat.n, 0.1)
+    plan = hsim.Plan(lat)
+    R = 64
+    T = np.linspace(0.2, 2.8, R)[:, None]
+    out = {}
+    for name, layout in (("rep", hsim.LAYOUT_REPLICA), ("site", hsim.LAYOUT_SITE)):
+        b = hsim.Batch([plan] * R, seed=31, precision=hsim.FP32, layout=layout).bind(1, 3)
+        b.init_spins(hsim.INIT_RANDOM)
+        b.run(T, 0.1, launch=hsim.LAUNCH_PLAIN)
+        torch.cuda.synchronize()
+        assert b.status() == 0, name
+        out[name] = ([b.spins_user(r).cpu().numpy() for r in (0, 31, 63)], b.history.cpu().numpy())
+    for x, y in zip(out["rep"][0], out["site"][0]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(out["rep"][1][..., 4], out["site"][1][..., 4])
+    assert np.allclose(out["rep"][1][..., :4], out["site"][1][..., :4], rtol=0, atol=1e-9 * lat.n)
