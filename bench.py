@@ -50,10 +50,13 @@ def parse():
                     help="update policy of every site (sc64 workload): random (the headline), "
                          "flip, small step (30 degrees), Gaussian (sigma 0.5), Hinzke-Nowak "
                          "(30 degrees), adaptive (sigma from 1.0)")
-    ap.add_argument("--workload", default="sc64", choices=["sc64", "films", "policies"],
+    ap.add_argument("--workload", default="sc64",
+                    choices=["sc64", "films", "policies", "ball", "validation"],
                     help="sc64: the headline workload; films: 256 diluted films, one replica "
                          "each (site-lane layout), for the site-lane kernel's numbers; policies: "
-                         "equilibrium correlation times of every update policy")
+                         "equilibrium correlation times of every update policy; ball: the "
+                         "core/shell hysteresis run (32 seeds, 401 field steps); validation: the "
+                         "double-precision SC 8^3 run against the oracle's time")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (HBM byte-counter calibration)")
     return ap.parse_args()
@@ -174,6 +177,12 @@ def main():
         return
     if args.workload == "policies":
         policies_bench(args, stream)
+        return
+    if args.workload == "ball":
+        ball_bench(args, stream)
+        return
+    if args.workload == "validation":
+        validation_bench(args, stream)
         return
     lat, T = workload()
     launch = dict(persistent=hsim.LAUNCH_PERSISTENT, graph=hsim.LAUNCH_GRAPH,
@@ -339,6 +348,99 @@ def films_bench(args, stream):
                      "frac": achieved / HBM_PEAK_GBS, "kernel": kernel,
                      "launch_ms": launch_ms, "updates_per_launch": upd,
                      "bytes_per_update": balg, "timed_launches": n_timed}}))
+
+
+def ball_bench(args, stream):
+    """Core/shell sphere cut from SC (R = 20, 33,401 sites; core J = 1, shell
+    0.3, interface -0.5; core K = 0.01 z, radial K = 1 on surface sites), 32
+    seeds at T = 0.1, the field swept +2 -> -2 -> +2 in 401 steps of `mcs`
+    MCS (default 200), single precision, replica-lane layout with 32-lane
+    rows.  The spins (12.8 MB) stay in the caches: no HBM roofline."""
+    import torch
+    import synth
+    from paper_1803_07030_amd import hsim
+    R, S = 32, 401
+    M = args.mcs if args.mcs != MCS else 200
+    lat = synth.core_shell_ball()
+    Bs = synth.hysteresis_fields(S)
+    launch = dict(persistent=hsim.LAUNCH_PERSISTENT, graph=hsim.LAUNCH_GRAPH,
+                  plain=hsim.LAUNCH_PLAIN, auto=hsim.LAUNCH_AUTO)[args.launch]
+    timed = launch == hsim.LAUNCH_PLAIN and args.time_every > 0
+    with torch.cuda.stream(stream):
+        plan = hsim.Plan(lat)
+        b = hsim.Batch([plan] * R, seed=2, precision=hsim.FP32, layout=hsim.LAYOUT_REPLICA).bind(S, M)
+        if launch == hsim.LAUNCH_AUTO:
+            b.autotune(trial_mcs=20)
+        for _ in range(args.warmup):
+            b.init_spins(hsim.INIT_COLD_Z)
+            b.run(np.full((R, 2), 0.1), np.repeat(Bs[None, :2], R, 0), launch=launch)
+        stream.synchronize()
+        if timed:
+            b.phase_times()
+            b.time_phases(args.time_every)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.init_spins(hsim.INIT_COLD_Z)
+            b.run(np.full((R, S), 0.1), np.repeat(Bs[None, :], R, 0), launch=launch)
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+        assert b.status() == 0
+        ph = b.phase_times() if timed else None
+        b.time_phases(0)
+        mz = b.history.cpu().numpy()[..., -1, 3].mean(axis=0) / lat.n   # <M_z>/N at each step end
+    upd = R * S * M * lat.n * args.steps
+    print(json.dumps({
+        "metric": "spin updates/sec, core/shell hysteresis batch", "value": upd / wall,
+        "unit": "spin updates/s", "steps": args.steps, "warmup": args.warmup,
+        "config": {"workload": f"core/shell ball R=20, {lat.n} sites, 32 seeds, T=0.1, {S} field "
+                               f"steps x {M} MCS, f32, replica-lane, {args.launch} launch",
+                   "sites": lat.n, "launch": args.launch},
+        "phase_us": None if ph is None else ph[0] / ph[1] * 1e3,
+        "updates_per_phase": None if ph is None else ph[2] / ph[1],
+        "mz_at_B": {"+2": float(mz[0]), "0 (down)": float(mz[S // 4]), "-2": float(mz[S // 2]),
+                    "0 (up)": float(mz[3 * S // 4])}}))
+
+
+def validation_bench(args, stream):
+    """The double-precision validation run: SC 8^3, J = 1, random start
+    (seed 0), 20 temperatures 3.0 -> 0.1 of 1000 MCS, one replica in the
+    block layout (spins in LDS); its CPU baseline is the oracle on one host
+    thread over the same run, whose accept counts must equal the GPU's."""
+    import torch
+    import oracle
+    import synth
+    from paper_1803_07030_amd import hsim
+    lat = synth.sc_periodic(8)
+    T = synth.cooling_schedule(20)
+    M = 1000
+    with torch.cuda.stream(stream):
+        plan = hsim.Plan(lat)
+        b = hsim.Batch([plan], seed=0, precision=hsim.FP64_EXACT, layout=hsim.LAYOUT_BLOCK).bind(20, M)
+        for _ in range(max(args.warmup, 1)):
+            b.init_spins(hsim.INIT_RANDOM)
+            b.run(T, 0.0, launch=hsim.LAUNCH_PLAIN)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.init_spins(hsim.INIT_RANDOM)
+            b.run(T, 0.0, launch=hsim.LAUNCH_PLAIN)
+        stream.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        assert b.status() == 0
+        h = b.history.cpu().numpy()[0]
+    t0 = time.perf_counter()
+    ref = oracle.run(lat, T, 0.0, M, seed=0, init="random")
+    t_or = time.perf_counter() - t0
+    upd = lat.n * 20 * M
+    print(json.dumps({
+        "metric": "spin updates/sec, FP64 validation run", "value": upd / wall,
+        "unit": "spin updates/s", "steps": args.steps,
+        "config": {"workload": "sc8^3 J=1, random start seed 0, 20 temperatures 3.0..0.1 x 1000 MCS, "
+                               "f64, block layout, one replica"},
+        "ms_per_run": wall * 1e3,
+        "cpu_baseline": {"value": upd / t_or, "unit": "spin updates/s", "cores": 1, "kind": "oracle",
+                         "sample": "the whole run", "ms_per_run": t_or * 1e3,
+                         "accept_counts_equal": bool(np.array_equal(h[..., 4], ref["history"][..., 4]))}}))
 
 
 def policies_bench(args, stream):
