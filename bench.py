@@ -51,12 +51,13 @@ def parse():
                          "flip, small step (30 degrees), Gaussian (sigma 0.5), Hinzke-Nowak "
                          "(30 degrees), adaptive (sigma from 1.0)")
     ap.add_argument("--workload", default="sc64",
-                    choices=["sc64", "films", "policies", "ball", "validation"],
+                    choices=["sc64", "films", "policies", "ball", "validation", "energy"],
                     help="sc64: the headline workload; films: 256 diluted films, one replica "
                          "each (site-lane layout), for the site-lane kernel's numbers; policies: "
                          "equilibrium correlation times of every update policy; ball: the "
                          "core/shell hysteresis run (32 seeds, 401 field steps); validation: the "
-                         "double-precision SC 8^3 run against the oracle's time")
+                         "double-precision SC 8^3 run against the oracle's time; energy: the "
+                         "energy forward and backward over 1024 configurations of SC 32^3")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (HBM byte-counter calibration)")
     return ap.parse_args()
@@ -183,6 +184,9 @@ def main():
         return
     if args.workload == "validation":
         validation_bench(args, stream)
+        return
+    if args.workload == "energy":
+        energy_bench(args, stream)
         return
     lat, T = workload()
     launch = dict(persistent=hsim.LAUNCH_PERSISTENT, graph=hsim.LAUNCH_GRAPH,
@@ -441,6 +445,60 @@ def validation_bench(args, stream):
         "cpu_baseline": {"value": upd / t_or, "unit": "spin updates/s", "cores": 1, "kind": "oracle",
                          "sample": "the whole run", "ms_per_run": t_or * 1e3,
                          "accept_counts_equal": bool(np.array_equal(h[..., 4], ref["history"][..., 4]))}}))
+
+
+def energy_bench(args, stream):
+    """Energy forward and backward (dE/dS, dE/dJ, dE/dk, dE/dB) of 1024
+    configurations of SC 32^3 with per-bond J ~ N(1, 0.1), per-site K and
+    axes, B = 0.5 z, single precision.  Algorithmic bytes per
+    site-configuration: 12 read (forward), 12 read + 12 written (backward);
+    the lattice tables are shared by the batch and not counted."""
+    import torch
+    import synth
+    from paper_1803_07030_amd import hsim
+    lat = synth.gradient_lattice(L=32, seed=4)
+    nb = 1024
+    reps = max(args.steps, 1) * 10
+    with torch.cuda.stream(stream):
+        plan = hsim.Plan(lat)
+        _, _, Jb = lat.bonds()
+        S = torch.tensor(synth.random_spins(44, lat.n, batch=nb).astype(np.float32).transpose(0, 2, 1).copy(),
+                         device="cuda")
+        J = torch.tensor(Jb, dtype=torch.float32, device="cuda")
+        k = torch.tensor(lat.k, dtype=torch.float32, device="cuda")
+        ax = torch.tensor(lat.axis.T.copy(), dtype=torch.float32, device="cuda")
+        E = torch.empty(nb, dtype=torch.float64, device="cuda")
+        gE = torch.ones(nb, dtype=torch.float64, device="cuda")
+        gS, gJ, gk = torch.empty_like(S), torch.empty_like(J), torch.empty_like(k)
+        gB = torch.empty(1, dtype=torch.float64, device="cuda")
+
+        def fwd():
+            hsim.hsim_energy_forward(plan.handle, nb, hsim.FP32, S, J, k, ax, 0.5, None, E)
+
+        def bwd():
+            hsim.hsim_energy_backward(plan.handle, nb, hsim.FP32, S, J, k, ax, 0.5, None, gE,
+                                      gS, gJ, gk, gB)
+
+        res = {}
+        for name, fn, bytes_per in (("forward", fwd, 12.0), ("backward", bwd, 24.0)):
+            for _ in range(max(args.warmup, 1)):
+                fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            stream.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = bytes_per * nb * lat.n / (ms / 1e3) / 1e9
+            res[name] = {"ms_per_call": ms, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_site_config": bytes_per}
+    print(json.dumps({
+        "metric": "energy forward/backward bandwidth", "unit": "GB/s",
+        "config": {"workload": f"sc32^3, per-bond J ~ N(1, 0.1), per-site K and axes, B=0.5 z, "
+                               f"{nb} configurations, f32", "sites": lat.n, "batch": nb},
+        "calls_timed": reps, **res}))
 
 
 def policies_bench(args, stream):

@@ -42,89 +42,126 @@ __device__ __forceinline__ double bsum(double v, double *lds)
     return t;
 }
 
+// Lattice data of one site, read once and used for every configuration of
+// a batch chunk: up to kMaxNb neighbours (column, constant) in registers,
+// longer rows walked in the CSR for each configuration.
+constexpr int kMaxNb = 8;
 template <typename T>
-struct Site {
-    T sx, sy, sz, hx, hy, hz, k, ex, ey, ez, nx, ny, nz;
-};
-
-template <typename T>
-__device__ __forceinline__ Site<T> load_site(const EnergyArgs &a, int b, int64_t i)
-{
-    const T *S = (const T *)a.S + (size_t)b * 3 * a.n;
-    const T *Jb = (const T *)a.Jb;
-    Site<T> s;
-    s.sx = S[i];
-    s.sy = S[a.n + i];
-    s.sz = S[2 * a.n + i];
-    T hx = 0, hy = 0, hz = 0;
-    for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
-        const int64_t j = a.ci[p];
-        const T J = Jb[a.bond[p]];
-        hx += J * S[j];
-        hy += J * S[a.n + j];
-        hz += J * S[2 * a.n + j];
+struct SiteTables {
+    int64_t rb = 0;
+    int deg = 0;
+    int32_t col[kMaxNb];
+    T J[kMaxNb];
+    T k, ex, ey, ez, nx, ny, nz, kc;
+    __device__ __forceinline__ SiteTables(const EnergyArgs &a, int64_t i)
+    {
+        const T *Jb = (const T *)a.Jb;
+        rb = a.rp[i];
+        deg = (int)(a.rp[i + 1] - rb);
+#pragma unroll
+        for (int q = 0; q < kMaxNb; ++q) {
+            col[q] = q < deg ? a.ci[rb + q] : 0;
+            J[q] = q < deg ? Jb[a.bond[rb + q]] : T(0);
+        }
+        const T *kk = (const T *)a.k, *ax = (const T *)a.ax, *nd = (const T *)a.nd;
+        k = kk ? kk[i] : T(0);
+        ex = ax ? ax[i] : T(0);
+        ey = ax ? ax[a.n + i] : T(0);
+        ez = ax ? ax[2 * a.n + i] : T(1);
+        nx = nd ? nd[i] : T(0);
+        ny = nd ? nd[a.n + i] : T(0);
+        nz = nd ? nd[2 * a.n + i] : T(1);
+        kc = a.kc ? ((const T *)a.kc)[i] : T(0);
     }
-    s.hx = hx;
-    s.hy = hy;
-    s.hz = hz;
-    const T *kk = (const T *)a.k, *ax = (const T *)a.ax, *nd = (const T *)a.nd;
-    s.k = kk ? kk[i] : T(0);
-    s.ex = ax ? ax[i] : T(0);
-    s.ey = ax ? ax[a.n + i] : T(0);
-    s.ez = ax ? ax[2 * a.n + i] : T(1);
-    s.nx = nd ? nd[i] : T(0);
-    s.ny = nd ? nd[a.n + i] : T(0);
-    s.nz = nd ? nd[2 * a.n + i] : T(1);
-    return s;
-}
+    // exchange field of configuration S at site i, entries in CSR order
+    __device__ __forceinline__ void field(const EnergyArgs &a, const T *S, T &hx, T &hy, T &hz) const
+    {
+        const T *Jb = (const T *)a.Jb;
+        hx = T(0);
+        hy = T(0);
+        hz = T(0);
+        if (deg <= kMaxNb) {
+#pragma unroll
+            for (int q = 0; q < kMaxNb; ++q)
+                if (q < deg) {
+                    const int64_t j = col[q];
+                    hx += J[q] * S[j];
+                    hy += J[q] * S[a.n + j];
+                    hz += J[q] * S[2 * a.n + j];
+                }
+        } else {
+            for (int64_t p = rb; p < rb + deg; ++p) {
+                const int64_t j = a.ci[p];
+                const T Jp = Jb[a.bond[p]];
+                hx += Jp * S[j];
+                hy += Jp * S[a.n + j];
+                hz += Jp * S[2 * a.n + j];
+            }
+        }
+    }
+};
 
 }  // namespace
 
-// grid (site tiles, batch).  Forward: E partial per (config, tile).  Backward
-// (gE != NULL): also dE/dS of every site and the dE/dB partial.
+// grid (site tiles, batch chunks of kECfg configurations).  Forward: E
+// partial per (configuration, tile).  Backward (BWD): also dE/dS of every
+// site and the dE/dB partial.  The lattice tables of a site are read once
+// per chunk.
+constexpr int kECfg = 8;
 template <typename T, bool BWD>
 __global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const double *gE, T *gS,
                                                          double *partE, double *partB)
 {
     __shared__ double red[kEBlock / 64];
-    const int b = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * kEBlock + threadIdx.x;
-    double e = 0.0, zn = 0.0;
-    if (i < a.n) {
-        const Site<T> s = load_site<T>(a, b, i);
-        const double sx = s.sx, sy = s.sy, sz = s.sz;
-        const double an = sx * (double)s.ex + sy * (double)s.ey + sz * (double)s.ez;
-        zn = sx * (double)s.nx + sy * (double)s.ny + sz * (double)s.nz;
-        e = -0.5 * (sx * (double)s.hx + sy * (double)s.hy + sz * (double)s.hz) - a.B * zn -
-            (double)s.k * an * an;
-        // cubic term of Eq. 3, -kc (Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2)
-        if (a.kc) e -= (double)((const T *)a.kc)[i] * ((sx * sx * (sy * sy) + sy * sy * (sz * sz)) + sx * sx * (sz * sz));
-        if (BWD) {
-            const T g = (T)gE[b];
-            const T B = (T)a.B;
-            const T an_t = s.sx * s.ex + s.sy * s.ey + s.sz * s.ez;
-            const T two_ka = T(2) * s.k * an_t;
-            T *o = gS + (size_t)b * 3 * a.n;
-            T cx = T(0), cy = T(0), cz = T(0);
-            if (a.kc) {
-                const T kc2 = T(2) * ((const T *)a.kc)[i];
-                const T x2 = s.sx * s.sx, y2 = s.sy * s.sy, z2 = s.sz * s.sz;
-                cx = kc2 * s.sx * (y2 + z2);
-                cy = kc2 * s.sy * (x2 + z2);
-                cz = kc2 * s.sz * (x2 + y2);
+    const bool live = i < a.n;
+    const SiteTables<T> st(a, live ? i : 0);
+    const int b0 = (int)blockIdx.y * kECfg;
+    for (int c = 0; c < kECfg; ++c) {
+        const int b = b0 + c;
+        if (b >= a.batch) break;   // uniform over the block
+        double e = 0.0, zn = 0.0;
+        if (live) {
+            const T *S = (const T *)a.S + (size_t)b * 3 * a.n;
+            const T tsx = S[i], tsy = S[a.n + i], tsz = S[2 * a.n + i];
+            T thx, thy, thz;
+            st.field(a, S, thx, thy, thz);
+            const double sx = tsx, sy = tsy, sz = tsz;
+            const double an = sx * (double)st.ex + sy * (double)st.ey + sz * (double)st.ez;
+            zn = sx * (double)st.nx + sy * (double)st.ny + sz * (double)st.nz;
+            e = -0.5 * (sx * (double)thx + sy * (double)thy + sz * (double)thz) - a.B * zn -
+                (double)st.k * an * an;
+            // cubic term of Eq. 3, -kc (Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2)
+            if (a.kc) e -= (double)st.kc * ((sx * sx * (sy * sy) + sy * sy * (sz * sz)) + sx * sx * (sz * sz));
+            if (BWD) {
+                const T g = (T)gE[b];
+                const T B = (T)a.B;
+                const T an_t = tsx * st.ex + tsy * st.ey + tsz * st.ez;
+                const T two_ka = T(2) * st.k * an_t;
+                T *o = gS + (size_t)b * 3 * a.n;
+                T cx = T(0), cy = T(0), cz = T(0);
+                if (a.kc) {
+                    const T kc2 = T(2) * st.kc;
+                    const T x2 = tsx * tsx, y2 = tsy * tsy, z2 = tsz * tsz;
+                    cx = kc2 * tsx * (y2 + z2);
+                    cy = kc2 * tsy * (x2 + z2);
+                    cz = kc2 * tsz * (x2 + y2);
+                }
+                if (gS) {
+                    o[i] = g * (-thx - B * st.nx - two_ka * st.ex - cx);
+                    o[a.n + i] = g * (-thy - B * st.ny - two_ka * st.ey - cy);
+                    o[2 * a.n + i] = g * (-thz - B * st.nz - two_ka * st.ez - cz);
+                }
             }
-            o[i] = g * (-s.hx - B * s.nx - two_ka * s.ex - cx);
-            o[a.n + i] = g * (-s.hy - B * s.ny - two_ka * s.ey - cy);
-            o[2 * a.n + i] = g * (-s.hz - B * s.nz - two_ka * s.ez - cz);
         }
-    }
-    const double et = bsum(e, red);
-    double zt = 0.0;
-    if (BWD) zt = bsum(zn, red);
-    if (threadIdx.x == 0) {
-        const size_t t = (size_t)b * gridDim.x + blockIdx.x;
-        if (partE) partE[t] = et;
-        if (BWD) partB[t] = -gE[b] * zt;
+        const double et = bsum(e, red);
+        double zt = 0.0;
+        if (BWD) zt = bsum(zn, red);
+        if (threadIdx.x == 0) {
+            const size_t t = (size_t)b * gridDim.x + blockIdx.x;
+            if (partE) partE[t] = et;
+            if (BWD) partB[t] = -gE[b] * zt;
+        }
     }
 }
 
@@ -169,7 +206,7 @@ __global__ __launch_bounds__(256) void k_energy_finish(EnergyArgs a, int ntile, 
                                                        const double *partE, double *E,
                                                        const double *partK, const double *partJ,
                                                        const int32_t *fwd_entry, T *gJ, T *gk,
-                                                       const double *partB, double *gB)
+                                                       const double *partB, double *partBc)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (E && t < a.batch) {
@@ -188,26 +225,37 @@ __global__ __launch_bounds__(256) void k_energy_finish(EnergyArgs a, int ntile, 
         for (int c = 0; c < nchunk; ++c) v += partK[(size_t)c * a.n + t];
         gk[t] = (T)v;
     }
-    if (gB && t == 0) {
+    if (partBc && t < a.batch) {
         double v = 0.0;
-        for (int64_t k = 0; k < (int64_t)a.batch * ntile; ++k) v += partB[k];
-        gB[0] = v;
+        for (int k = 0; k < ntile; ++k) v += partB[(size_t)t * ntile + k];
+        partBc[t] = v;
     }
+}
+
+// dE/dB: the per-configuration sums in a fixed order (thread t takes
+// configurations t, t + 256, ... in order; then the block sum).
+__global__ __launch_bounds__(256) void k_energy_gB(int batch, const double *partBc, double *gB)
+{
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int t = threadIdx.x; t < batch; t += blockDim.x) v += partBc[t];
+    v = bsum(v, red);
+    if (threadIdx.x == 0) gB[0] = v;
 }
 
 int64_t energy_scratch_doubles(int64_t n, int64_t nnz, int batch, int)
 {
     const int64_t ntile = (n + kEBlock - 1) / kEBlock;
     const int64_t nchunk = (batch + kEChunk - 1) / kEChunk;
-    // partE, partB: batch*ntile each; partK: nchunk*n; partJ: nchunk*nnz
-    return 2 * (int64_t)batch * ntile + nchunk * n + nchunk * nnz;
+    // partE, partB: batch*ntile each; partK: nchunk*n; partJ: nchunk*nnz; partBc: batch
+    return 2 * (int64_t)batch * ntile + nchunk * n + nchunk * nnz + batch;
 }
 
 hipError_t launch_energy_forward(hipStream_t st, bool f64, const EnergyArgs &a, double *scratch,
                                  int, double *E)
 {
     const int ntile = (int)((a.n + kEBlock - 1) / kEBlock);
-    dim3 grid((unsigned)ntile, (unsigned)a.batch);
+    dim3 grid((unsigned)ntile, (unsigned)((a.batch + kECfg - 1) / kECfg));
     double *partE = scratch;
     if (f64)
         hipLaunchKernelGGL((k_energy_site<double, false>), grid, dim3(kEBlock), 0, st, a,
@@ -241,8 +289,9 @@ hipError_t launch_energy_backward(hipStream_t st, bool f64, const EnergyArgs &a,
     double *partB = partE + (size_t)a.batch * ntile;
     double *partK = partB + (size_t)a.batch * ntile;
     double *partJ = partK + (size_t)nchunk * a.n;
+    double *partBc = partJ + (size_t)nchunk * a.nnz;
     const int32_t *fwd = a.fwd_entry;
-    dim3 grid((unsigned)ntile, (unsigned)a.batch);
+    dim3 grid((unsigned)ntile, (unsigned)((a.batch + kECfg - 1) / kECfg));
     if (gS || gB) {
         if (f64)
             hipLaunchKernelGGL((k_energy_site<double, true>), grid, dim3(kEBlock), 0, st, a, gE,
@@ -264,16 +313,21 @@ hipError_t launch_energy_backward(hipStream_t st, bool f64, const EnergyArgs &a,
     }
     int64_t m = a.nb;
     if (a.n > m) m = a.n;
+    if (a.batch > m) m = a.batch;
     if (m < 1) m = 1;
     dim3 g3((unsigned)((m + 255) / 256));
+    double *bc = gB ? partBc : nullptr;
     if (f64)
         hipLaunchKernelGGL((k_energy_finish<double>), g3, dim3(256), 0, st, a, ntile, nchunk,
                            (const double *)nullptr, (double *)nullptr, partK, partJ, fwd,
-                           (double *)gJ, (double *)gk, (const double *)partB, gB);
+                           (double *)gJ, (double *)gk, (const double *)partB, bc);
     else
         hipLaunchKernelGGL((k_energy_finish<float>), g3, dim3(256), 0, st, a, ntile, nchunk,
                            (const double *)nullptr, (double *)nullptr, partK, partJ, fwd,
-                           (float *)gJ, (float *)gk, (const double *)partB, gB);
+                           (float *)gJ, (float *)gk, (const double *)partB, bc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !gB) return e;
+    hipLaunchKernelGGL(k_energy_gB, dim3(1), dim3(256), 0, st, a.batch, (const double *)partBc, gB);
     return hipGetLastError();
 }
 

@@ -341,3 +341,35 @@ def test_replica_tiles_of_every_size_match_the_site_layout(L):
         assert np.array_equal(x, y)
     assert np.array_equal(out["rep"][1][..., 4], out["site"][1][..., 4])
     assert np.allclose(out["rep"][1][..., :4], out["site"][1][..., :4], rtol=0, atol=1e-9 * lat.n)
+
+
+# ----------------------------------------------- energy backward, partial outputs
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_energy_backward_with_some_outputs_null(dtype):
+    """Any output of the backward may be NULL: dE/dB alone, dE/dS alone and
+    (dE/dJ, dE/dk) alone equal the same outputs of the full call."""
+    lat = synth.gradient_lattice(L=9, seed=5)
+    plan = hsim.Plan(lat)
+    nb = 37
+    prec = hsim.FP64_EXACT if dtype == torch.float64 else hsim.FP32
+    S = torch.tensor(synth.random_spins(3, lat.n, batch=nb).transpose(0, 2, 1).copy(), dtype=dtype,
+                     device="cuda")
+    _, _, Jb = lat.bonds()
+    J = torch.tensor(Jb, dtype=dtype, device="cuda")
+    k = torch.tensor(lat.k, dtype=dtype, device="cuda")
+    ax = torch.tensor(lat.axis.T.copy(), dtype=dtype, device="cuda")
+    gE = torch.linspace(0.5, 1.5, nb, dtype=torch.float64, device="cuda")
+
+    def call(want):
+        out = dict(gS=torch.full_like(S, 7.0), gJ=torch.full_like(J, 7.0), gk=torch.full_like(k, 7.0),
+                   gB=torch.full((1,), 7.0, dtype=torch.float64, device="cuda"))
+        args = {name: (out[name] if name in want else None) for name in out}
+        hsim.hsim_energy_backward(plan.handle, nb, prec, S, J, k, ax, 0.4, None, gE, **args)
+        torch.cuda.synchronize()
+        return {name: out[name].cpu().numpy() for name in want}
+
+    full = call(("gS", "gJ", "gk", "gB"))
+    for want in (("gB",), ("gS",), ("gJ", "gk")):
+        part = call(want)
+        for name in want:
+            assert np.array_equal(part[name], full[name]), (want, name)
