@@ -19,7 +19,6 @@ namespace hsim {
 namespace {
 
 constexpr int kEBlock = 256;
-constexpr int kEChunk = 64;   // configurations per batch chunk of the parameter gradients
 
 __device__ __forceinline__ double wsum(double v)
 {
@@ -107,16 +106,24 @@ struct SiteTables {
 // partial per (configuration, tile).  Backward (BWD): also dE/dS of every
 // site and the dE/dB partial.  The lattice tables of a site are read once
 // per chunk.
-constexpr int kECfg = 8;
+constexpr int kECfg = 32;
 template <typename T, bool BWD>
 __global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const double *gE, T *gS,
-                                                         double *partE, double *partB)
+                                                         double *partE, double *partB,
+                                                         double *partK, double *partJ)
 {
     __shared__ double red[kEBlock / 64];
     const int64_t i = (int64_t)blockIdx.x * kEBlock + threadIdx.x;
     const bool live = i < a.n;
     const SiteTables<T> st(a, live ? i : 0);
     const int b0 = (int)blockIdx.y * kECfg;
+    // backward, parameter gradients of the chunk: dE/dk_i and dE/dJ of the
+    // bonds whose lower end is i (rows up to kMaxNb entries here; longer rows
+    // below), summed over the chunk's configurations in order
+    const bool params = BWD && (partK || partJ);
+    double gk = 0.0, gj[kMaxNb];
+#pragma unroll
+    for (int q = 0; q < kMaxNb; ++q) gj[q] = 0.0;
     for (int c = 0; c < kECfg; ++c) {
         const int b = b0 + c;
         if (b >= a.batch) break;   // uniform over the block
@@ -152,6 +159,20 @@ __global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const dou
                     o[a.n + i] = g * (-thy - B * st.ny - two_ka * st.ey - cy);
                     o[2 * a.n + i] = g * (-thz - B * st.nz - two_ka * st.ez - cz);
                 }
+                if (params) {
+                    const double gb = gE[b];
+                    gk += gb * -(an * an);
+                    if (st.deg <= kMaxNb) {
+#pragma unroll
+                        for (int q = 0; q < kMaxNb; ++q)
+                            if (q < st.deg && st.col[q] > i) {
+                                const int64_t j = st.col[q];
+                                const double d = sx * (double)S[j] + sy * (double)S[a.n + j] +
+                                                 sz * (double)S[2 * a.n + j];
+                                gj[q] += gb * -d;
+                            }
+                    }
+                }
             }
         }
         const double et = bsum(e, red);
@@ -163,39 +184,28 @@ __global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const dou
             if (BWD) partB[t] = -gE[b] * zt;
         }
     }
-}
-
-// grid (site tiles, batch chunks): dE/dk_i and dE/dJ of the bonds whose lower
-// end is i, summed over the chunk's configurations.
-template <typename T>
-__global__ __launch_bounds__(kEBlock) void k_energy_params(EnergyArgs a, const double *gE,
-                                                           double *partK, double *partJ)
-{
-    const int64_t i = (int64_t)blockIdx.x * kEBlock + threadIdx.x;
-    if (i >= a.n) return;
-    const int c = blockIdx.y;
-    const int b0 = c * kEChunk, b1 = min(a.batch, b0 + kEChunk);
-    const T *ax = (const T *)a.ax;
-    const T ex = ax ? ax[i] : T(0), ey = ax ? ax[a.n + i] : T(0), ez = ax ? ax[2 * a.n + i] : T(1);
-    double gk = 0.0;
-    for (int b = b0; b < b1; ++b) {
-        const T *S = (const T *)a.S + (size_t)b * 3 * a.n;
-        const double an = (double)S[i] * (double)ex + (double)S[a.n + i] * (double)ey +
-                          (double)S[2 * a.n + i] * (double)ez;
-        gk += gE[b] * -(an * an);
-    }
-    partK[(size_t)c * a.n + i] = gk;
-    for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
-        const int64_t j = a.ci[p];
-        if (j <= i) continue;
-        double gj = 0.0;
-        for (int b = b0; b < b1; ++b) {
-            const T *S = (const T *)a.S + (size_t)b * 3 * a.n;
-            const double d = (double)S[i] * (double)S[j] + (double)S[a.n + i] * (double)S[a.n + j] +
-                             (double)S[2 * a.n + i] * (double)S[2 * a.n + j];
-            gj += gE[b] * -d;
+    if (!params || !live) return;
+    const size_t ch = blockIdx.y;   // this chunk's partial records
+    if (partK) partK[ch * a.n + i] = gk;
+    if (!partJ) return;
+    if (st.deg <= kMaxNb) {
+#pragma unroll
+        for (int q = 0; q < kMaxNb; ++q)
+            if (q < st.deg && st.col[q] > i) partJ[ch * a.nnz + st.rb + q] = gj[q];
+    } else {
+        const int b1 = min(a.batch, b0 + kECfg);
+        for (int64_t p = st.rb; p < st.rb + st.deg; ++p) {
+            const int64_t j = a.ci[p];
+            if (j <= i) continue;
+            double v = 0.0;
+            for (int b = b0; b < b1; ++b) {
+                const T *S = (const T *)a.S + (size_t)b * 3 * a.n;
+                const double d = (double)S[i] * (double)S[j] + (double)S[a.n + i] * (double)S[a.n + j] +
+                                 (double)S[2 * a.n + i] * (double)S[2 * a.n + j];
+                v += gE[b] * -d;
+            }
+            partJ[ch * a.nnz + p] = v;
         }
-        partJ[(size_t)c * a.nnz + p] = gj;
     }
 }
 
@@ -246,7 +256,7 @@ __global__ __launch_bounds__(256) void k_energy_gB(int batch, const double *part
 int64_t energy_scratch_doubles(int64_t n, int64_t nnz, int batch, int)
 {
     const int64_t ntile = (n + kEBlock - 1) / kEBlock;
-    const int64_t nchunk = (batch + kEChunk - 1) / kEChunk;
+    const int64_t nchunk = (batch + kECfg - 1) / kECfg;
     // partE, partB: batch*ntile each; partK: nchunk*n; partJ: nchunk*nnz; partBc: batch
     return 2 * (int64_t)batch * ntile + nchunk * n + nchunk * nnz + batch;
 }
@@ -259,10 +269,12 @@ hipError_t launch_energy_forward(hipStream_t st, bool f64, const EnergyArgs &a, 
     double *partE = scratch;
     if (f64)
         hipLaunchKernelGGL((k_energy_site<double, false>), grid, dim3(kEBlock), 0, st, a,
-                           (const double *)nullptr, (double *)nullptr, partE, (double *)nullptr);
+                           (const double *)nullptr, (double *)nullptr, partE, (double *)nullptr,
+                           (double *)nullptr, (double *)nullptr);
     else
         hipLaunchKernelGGL((k_energy_site<float, false>), grid, dim3(kEBlock), 0, st, a,
-                           (const double *)nullptr, (float *)nullptr, partE, (double *)nullptr);
+                           (const double *)nullptr, (float *)nullptr, partE, (double *)nullptr,
+                           (double *)nullptr, (double *)nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 g2((unsigned)((a.batch + 255) / 256));
@@ -284,33 +296,24 @@ hipError_t launch_energy_backward(hipStream_t st, bool f64, const EnergyArgs &a,
                                   int)
 {
     const int ntile = (int)((a.n + kEBlock - 1) / kEBlock);
-    const int nchunk = (a.batch + kEChunk - 1) / kEChunk;
+    const int nchunk = (a.batch + kECfg - 1) / kECfg;
     double *partE = scratch;
     double *partB = partE + (size_t)a.batch * ntile;
     double *partK = partB + (size_t)a.batch * ntile;
     double *partJ = partK + (size_t)nchunk * a.n;
     double *partBc = partJ + (size_t)nchunk * a.nnz;
     const int32_t *fwd = a.fwd_entry;
-    dim3 grid((unsigned)ntile, (unsigned)((a.batch + kECfg - 1) / kECfg));
-    if (gS || gB) {
-        if (f64)
-            hipLaunchKernelGGL((k_energy_site<double, true>), grid, dim3(kEBlock), 0, st, a, gE,
-                               (double *)gS, (double *)nullptr, partB);
-        else
-            hipLaunchKernelGGL((k_energy_site<float, true>), grid, dim3(kEBlock), 0, st, a, gE,
-                               (float *)gS, (double *)nullptr, partB);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (gJ || gk) {
-        dim3 g2((unsigned)ntile, (unsigned)nchunk);
-        if (f64)
-            hipLaunchKernelGGL(k_energy_params<double>, g2, dim3(kEBlock), 0, st, a, gE, partK, partJ);
-        else
-            hipLaunchKernelGGL(k_energy_params<float>, g2, dim3(kEBlock), 0, st, a, gE, partK, partJ);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    dim3 grid((unsigned)ntile, (unsigned)nchunk);
+    // one pass: dE/dS, the dE/dB partials and the dE/dk, dE/dJ chunk partials
+    double *pk = gk ? partK : nullptr, *pj = gJ ? partJ : nullptr;
+    if (f64)
+        hipLaunchKernelGGL((k_energy_site<double, true>), grid, dim3(kEBlock), 0, st, a, gE,
+                           (double *)gS, (double *)nullptr, partB, pk, pj);
+    else
+        hipLaunchKernelGGL((k_energy_site<float, true>), grid, dim3(kEBlock), 0, st, a, gE,
+                           (float *)gS, (double *)nullptr, partB, pk, pj);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
     int64_t m = a.nb;
     if (a.n > m) m = a.n;
     if (a.batch > m) m = a.batch;
