@@ -111,8 +111,12 @@ hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
             hsim_plan P = plans[0];
             b->Rp = R > 32 ? (int32_t)((R + 63) / 64 * 64) : 32;
             // sites per wave of a tile: the full kRepSitesPerWave while the
-            // largest colour phase has at least 4 blocks per CU, else halved
-            // (down to 4) so that small lattices still fill the GPU
+            // largest colour phase has at least 2 blocks per CU; else 8, or 4
+            // when 8 still gives fewer than 4 blocks per CU, so that small
+            // lattices fill the GPU.  Measured on SC L^3 x 64 replicas (us per
+            // phase): L = 56: 45.8 (32), 54.8 (16); L = 48: 37.4 (32), 34.0
+            // (16), 28.1 (8); L = 32: 17.6 (16), 12.6 (8), 11.9 (4); 16 sites
+            // per wave was never the best and is not used.
             const int cus = device_cus() > 0 ? device_cus() : 256;
             const int cols = b->Rp % 64 == 0 ? b->Rp / 64 : 1;   // lane columns per tile
             auto phase_blocks = [&](int spw) {
@@ -124,8 +128,12 @@ hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
                 return mx * cols;
             };
             int spw = hsim::kRepSitesPerWave;
-            while (spw % 8 == 0 && spw / 2 % hsim::kRepSitesPerStep == 0 && phase_blocks(spw) < 4 * (int64_t)cus)
-                spw /= 2;
+            if (phase_blocks(spw) < 2 * (int64_t)cus)
+                for (int cand : {8, 4})
+                    if (cand < spw && cand % hsim::kRepSitesPerStep == 0) {
+                        spw = cand;
+                        if (phase_blocks(cand) >= 4 * (int64_t)cus) break;
+                    }
             b->la.spw = spw;
             const int tile = hsim::kRepWaves * spw;
             b->la.tile_off[0] = 0;

@@ -320,10 +320,10 @@ def test_replica_layout_planar_rows_for_arrays_over_2gib():
 # ---------------------------------------------- tile sizes of the replica layout
 @pytest.mark.parametrize("L", [48, 56], ids=["sc48", "sc56"])
 def test_replica_tiles_of_every_size_match_the_site_layout(L):
-    """The replica layout sizes its tiles to the lattice (4 to 32 sites per
-    wave: SC 48^3 and 56^3 with 64 replicas take the intermediate sizes on a
-    256-CU GPU; smaller lattices in other tests take 4, SC 64^3 takes 32):
-    spins and accept counts equal the site layout's after 3 MCS."""
+    """The replica layout sizes its tiles to the lattice (4, 8 or 32 sites
+    per wave: on a 256-CU GPU SC 48^3 with 64 replicas takes 8 and SC 56^3
+    takes 32; the smaller lattices of other tests take 4): spins and accept
+    counts equal the site layout's after 3 MCS."""
     lat = synth.sc_periodic(L)
     lat.k = np.full(lat.n, 0.1)
     plan = hsim.Plan(lat)
