@@ -65,16 +65,20 @@ typedef enum { HSIM_FP32 = 0, HSIM_FP64_EXACT = 1 } hsim_precision;
  * replica.  REPLICA: replicas sharing one lattice, one lane per replica of
  * one site, spins [n][3][R padded to 32 or a multiple of 64] (rows of all
  * replicas for one component of one site; [3][n][..] when the array is 2 GiB
- * or more); FP32 only.  BLOCK: each replica
- * owned by one workgroup for the whole run (spins staged in LDS when they
- * fit).  AUTO lets the library choose. */
+ * or more); FP32 only.  BLOCK: each replica owned by one workgroup for the
+ * whole run (spins staged in LDS when they fit).  AUTO: REPLICA for FP32
+ * batches of at least 16 replicas on one lattice, else BLOCK when a replica
+ * fits in LDS, else SITE. */
 typedef enum {
     HSIM_LAYOUT_AUTO = 0, HSIM_LAYOUT_SITE = 1, HSIM_LAYOUT_REPLICA = 2, HSIM_LAYOUT_BLOCK = 3
 } hsim_layout;
 
 /* PLAIN: kernels enqueued one by one.  GRAPH: the same kernels captured once
  * into a hipGraph and replayed.  PERSISTENT: one launch that loops over MCS
- * and colours with device-wide barriers.  AUTO: the library's choice. */
+ * and colours with device-wide barriers (replica layout).  AUTO: the mode
+ * hsim_autotune chose for the batch, GRAPH before any autotuning.  The BLOCK
+ * layout always runs as one launch.  Every mode gives the same spins, and
+ * the same history within one layout. */
 typedef enum {
     HSIM_LAUNCH_PLAIN = 0, HSIM_LAUNCH_PERSISTENT = 1, HSIM_LAUNCH_GRAPH = 2, HSIM_LAUNCH_AUTO = 3
 } hsim_launch;
