@@ -373,3 +373,28 @@ def test_energy_backward_with_some_outputs_null(dtype):
         part = call(want)
         for name in want:
             assert np.array_equal(part[name], full[name]), (want, name)
+
+
+@pytest.mark.parametrize("R", [1, 33], ids=["one replica", "33 replicas"])
+def test_replica_layout_with_mostly_idle_lanes(R):
+    """One replica (31 idle lanes of a 32-lane row) and 33 replicas (31 idle
+    lanes of a 64-lane row): spins, accept counts and the adaptive widths of
+    a policy run equal the site layout's."""
+    lat = synth.diluted_film(13, 3, seed=7)
+    lat.k = np.full(lat.n, 0.05)
+    types = (np.arange(lat.n) % 2).astype(np.int32)
+    plan = hsim.Plan(lat)
+    plan.set_types(types)
+    T = np.linspace(0.5, 2.0, R)[:, None] * np.ones((1, 2))
+    out = {}
+    for name, layout in (("rep", hsim.LAYOUT_REPLICA), ("site", hsim.LAYOUT_SITE)):
+        b = hsim.Batch([plan] * R, seed=19, precision=hsim.FP32, layout=layout).bind(2, 6)
+        b.set_policies([(hsim.POLICY_ADAPTIVE, 0.7), (hsim.POLICY_RANDOM, 0.0)])
+        b.init_spins(hsim.INIT_RANDOM)
+        b.run(T, 0.1, launch=hsim.LAUNCH_PLAIN)
+        torch.cuda.synchronize()
+        assert b.status() == 0, name
+        out[name] = (_user(b, R), b.history.cpu().numpy()[..., 4], b.sigma())
+    assert np.array_equal(out["rep"][0], out["site"][0])
+    assert np.array_equal(out["rep"][1], out["site"][1])
+    assert np.array_equal(out["rep"][2], out["site"][2])
