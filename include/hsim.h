@@ -279,7 +279,11 @@ hsim_status hsim_energy_forward(hsim_plan plan, int32_t batch, hsim_precision pr
  *   d_gk [n]             = sum_b gE_b (-(S_i.e_i)^2)
  *   d_gB [1] (double)    = sum_b gE_b (-sum_i S_i.n_i)
  * Any output may be NULL.  Outputs are overwritten (not accumulated); gS, gJ
- * and gk have the precision of the inputs. */
+ * and gk have the precision of the inputs.  With the cubic term of
+ * hsim_plan_set_site_terms, dE/dS includes it.
+ * Both energy calls use a device scratch owned by the plan, grown when a call
+ * needs more; growing it synchronises the device, and two energy calls on
+ * one plan must not run concurrently on different streams. */
 hsim_status hsim_energy_backward(hsim_plan plan, int32_t batch, hsim_precision precision,
                                  const void *d_spins, const void *d_J_bond, const void *d_k,
                                  const void *d_axis, double B, const void *d_field_dir,
