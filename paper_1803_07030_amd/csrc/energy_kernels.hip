@@ -112,10 +112,14 @@ __global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const dou
                                                          double *partE, double *partB,
                                                          double *partK, double *partJ)
 {
-    __shared__ double red[kEBlock / 64];
+    // wave sums of every configuration of the chunk, added in wave order
+    // after the loop (one barrier per chunk instead of two per configuration)
+    constexpr int kW = kEBlock / 64;
+    __shared__ double ew[kECfg][kW], zw[BWD ? kECfg : 1][kW];
     const int64_t i = (int64_t)blockIdx.x * kEBlock + threadIdx.x;
     const bool live = i < a.n;
     const SiteTables<T> st(a, live ? i : 0);
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
     const int b0 = (int)blockIdx.y * kECfg;
     // backward, parameter gradients of the chunk: dE/dk_i and dE/dJ of the
     // bonds whose lower end is i (rows up to kMaxNb entries here; longer rows
@@ -175,14 +179,25 @@ __global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const dou
                 }
             }
         }
-        const double et = bsum(e, red);
-        double zt = 0.0;
-        if (BWD) zt = bsum(zn, red);
-        if (threadIdx.x == 0) {
-            const size_t t = (size_t)b * gridDim.x + blockIdx.x;
-            if (partE) partE[t] = et;
-            if (BWD) partB[t] = -gE[b] * zt;
+        e = wsum(e);
+        if (ln == 0) ew[c][wv] = e;
+        if (BWD) {
+            zn = wsum(zn);
+            if (ln == 0) zw[c][wv] = zn;
         }
+    }
+    __syncthreads();
+    const int nc = min(kECfg, a.batch - b0);
+    if ((int)threadIdx.x < nc) {
+        const int c = threadIdx.x, b = b0 + c;
+        const size_t t = (size_t)b * gridDim.x + blockIdx.x;
+        double et = 0.0, zt = 0.0;
+        for (int k = 0; k < kW; ++k) {
+            et += ew[c][k];
+            if (BWD) zt += zw[c][k];
+        }
+        if (partE) partE[t] = et;
+        if (BWD) partB[t] = -gE[b] * zt;
     }
     if (!params || !live) return;
     const size_t ch = blockIdx.y;   // this chunk's partial records
