@@ -190,7 +190,10 @@ def validate(lat):
 
 
 def greedy_colour(lat):
-    """Greedy colouring in ascending site index (smallest free colour)."""
+    """Greedy colouring in breadth-first order: components by lowest site
+    index, each searched breadth-first from that site with neighbours queued
+    in CSR order; every site takes the smallest colour no coloured neighbour
+    has."""
     L = _Lat(lat)
     c = np.empty(max(lat.n, 1), dtype=np.int32)
     nc = lib().or_greedy_colour(L.ref, _ptr(c))
@@ -312,3 +315,37 @@ def run_replicas(jobs, threads=None):
     with ThreadPoolExecutor(max_workers=threads) as ex:
         res = list(ex.map(lambda kw: run(**kw), jobs))
     return res, threads
+
+
+def fluct_gradients(lat, B, spins, beta, O=None):
+    """Fluctuation estimate of the derivatives of a canonical average with
+    respect to every per-bond exchange constant, every anisotropy constant and
+    the field intensity, from configurations sampled at inverse temperature
+    beta.  Differentiating the Boltzmann average of Eq. 4's stationary
+    distribution (section "Thermal averages": responses as fluctuations):
+
+        d<O>/dtheta = <dO/dtheta> - beta (<O dE/dtheta> - <O><dE/dtheta>)
+
+    spins: (n_cfg, n, 3); O: per-configuration observable that does not
+    depend on the parameters (None: O = E itself, whose own derivative is
+    dE/dtheta).  dE/dtheta of every configuration comes from energy_grad.
+    Returns dict gJ (n_bonds,), gk (n,), gB (scalar): plain sample means."""
+    spins = np.asarray(spins, dtype=np.float64)
+    nc = spins.shape[0]
+    dJ, dk, dB, Es = [], [], [], []
+    for s in spins:
+        _, gJ, gk, gB = energy_grad(lat, B, s)
+        dJ.append(gJ)
+        dk.append(gk)
+        dB.append(gB)
+        Es.append(energy(lat, B, s)["E"])
+    dJ, dk, dB = np.array(dJ), np.array(dk), np.array(dB)
+    own = O is None
+    O = np.array(Es) if own else np.asarray(O, dtype=np.float64).reshape(nc)
+    dO = O - O.mean()
+
+    def est(X):
+        cov = np.tensordot(dO, X - X.mean(axis=0), axes=(0, 0)) / nc
+        return (X.mean(axis=0) if own else 0.0) - beta * cov
+
+    return dict(gJ=est(dJ), gk=est(dk), gB=float(est(dB)), O=O)

@@ -722,8 +722,8 @@ int or_run(const or_lattice *lat, const or_params *p, or_outputs *out)
                     tm[3 * t] = x; tm[3 * t + 1] = y; tm[3 * t + 2] = z;
                 }
             }
-            /* final state of the step ("the direction of every spin moment at
-             * the last MCS ... per temperature and magnetic field step") */
+            /* final state of the step: every spin after the step's last MCS
+             * (section "VEGAS software package", its list of stored results) */
             if (out->snapshots && m == M - 1)
                 memcpy(out->snapshots + (size_t)s * n * 3, S, sizeof(double) * 3 * (size_t)n);
             if (out->e_full) {

@@ -1,8 +1,8 @@
 // Optional per-run outputs: the magnetisation of every site type after
-// every MCS ("the statistics of each magnetic phase can be tracked
-// independently") and the spins at the end of every temperature/field step
-// (the final states stored per step), both from the paper's feature list
-// (section "VEGAS software package").
+// every MCS (each magnetic phase gets statistics of its own) and the spins at
+// the end of every temperature/field step (the final states stored per
+// step), both from the paper's feature list (section "VEGAS software
+// package").
 //
 // Per-type sums are deterministic: a fixed chunk of sites per block, a fixed
 // tree inside the block, and the chunks added in order.

@@ -9,6 +9,32 @@ import torch
 from . import hsim
 
 
+def _check_inputs(spins, J_bond, k, axis, field_dir, plan):
+    """The kernels read raw pointers of the spins' precision: every tensor
+    must have the spins' dtype and shape, and live on the spins' GPU."""
+    if not isinstance(spins, torch.Tensor) or spins.dtype not in (torch.float32, torch.float64):
+        raise TypeError("spins must be a float32 or float64 tensor [batch, 3, n]")
+    n, nb = int(plan.n), int(plan.info.n_bonds)
+    if spins.dim() != 3 or spins.shape[1] != 3 or spins.shape[2] != n:
+        raise ValueError(f"spins must have shape [batch, 3, {n}], got {tuple(spins.shape)}")
+    want = {"J_bond": (J_bond, (nb,)), "k": (k, (n,)), "axis": (axis, (3, n))}
+    if field_dir is not None:
+        want["field_dir"] = (field_dir, (3, n))
+    for name, (t, shape) in want.items():
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a tensor")
+        if t.dtype != spins.dtype:
+            raise TypeError(f"{name} has dtype {t.dtype}, the spins {spins.dtype}: "
+                            "every input must have the spins' precision")
+        if tuple(t.shape) != shape:
+            raise ValueError(f"{name} must have shape {list(shape)}, got {list(t.shape)}")
+    for name, t in [("spins", spins)] + [(nm, v[0]) for nm, v in want.items()]:
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be on a CUDA device, got {t.device}")
+        if t.device != spins.device:
+            raise ValueError(f"{name} is on {t.device}, the spins on {spins.device}")
+
+
 class HeisenbergEnergy(torch.autograd.Function):
     """E_b(S_b; J, k, B) for a batch of configurations S [batch, 3, n] (user
     order) on one plan; J per bond in the plan's bond order, k [n], axis
@@ -18,6 +44,7 @@ class HeisenbergEnergy(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, spins, J_bond, k, B, plan, axis, field_dir):
+        _check_inputs(spins, J_bond, k, axis, field_dir, plan)
         prec = hsim.FP64_EXACT if spins.dtype == torch.float64 else hsim.FP32
         spins = spins.contiguous()
         J_bond, k, axis = J_bond.contiguous(), k.contiguous(), axis.contiguous()
@@ -53,6 +80,13 @@ def fluct_estimate(beta, O, dE, dO=None):
     """d<O>/dtheta = <dO/dtheta> - beta Cov(O, dE/dtheta) over the samples
     (fluctuation-dissipation form of the derivative of a canonical average).
     Returns (estimate, covariance) as a float64 tensor of 2 elements."""
+    for name, t in (("O", O), ("dE", dE), ("dO", dO)):
+        if t is None:
+            continue
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be on a CUDA device, got {t.device}")
+        if t.numel() != O.numel():
+            raise ValueError(f"{name} has {t.numel()} samples, O has {O.numel()}")
     O = O.contiguous().to(torch.float64)
     dE = dE.contiguous().to(torch.float64)
     dO = None if dO is None else dO.contiguous().to(torch.float64)

@@ -143,3 +143,43 @@ def test_site_types_and_policies_validation():
     b.set_policies([])
     _expect(-4, lambda: hsim.hsim_batch_sigma(b.handle, 2))
     p.set_types(None)
+
+
+def test_energy_wrapper_rejects_mismatched_inputs():
+    """The autograd wrapper hands raw pointers to kernels of the spins'
+    precision, so a tensor of another dtype, shape or device is an error
+    raised before any kernel runs (here checked on host tensors)."""
+    import torch
+    from paper_1803_07030_amd.energy import heisenberg_energy
+    lat = synth.gradient_lattice(L=4, seed=4)
+    plan = hsim.Plan(lat)
+    n, nb = lat.n, int(plan.info.n_bonds)
+
+    def args(dtype=torch.float32, **over):
+        a = dict(spins=torch.zeros(2, 3, n, dtype=dtype), J_bond=torch.zeros(nb, dtype=dtype),
+                 k=torch.zeros(n, dtype=dtype), axis=torch.zeros(3, n, dtype=dtype),
+                 field_dir=None)
+        a.update(over)
+        return a
+
+    def call(a):
+        return heisenberg_energy(a["spins"], a["J_bond"], a["k"], torch.tensor(0.5), plan,
+                                 a["axis"], a["field_dir"])
+
+    f64 = torch.float64
+    cases = [
+        (TypeError, "J_bond has dtype", args(J_bond=torch.zeros(nb, dtype=f64))),
+        (TypeError, "k has dtype", args(k=torch.zeros(n, dtype=f64))),
+        (TypeError, "axis has dtype", args(f64, axis=torch.zeros(3, n))),
+        (TypeError, "field_dir has dtype", args(field_dir=torch.zeros(3, n, dtype=f64))),
+        (TypeError, "float32 or float64", args(spins=torch.zeros(2, 3, n, dtype=torch.float16))),
+        (ValueError, "spins must have shape", args(spins=torch.zeros(2, n, 3))),
+        (ValueError, "J_bond must have shape", args(J_bond=torch.zeros(nb + 1))),
+        (ValueError, "k must have shape", args(k=torch.zeros(n - 1))),
+        (ValueError, "axis must have shape", args(axis=torch.zeros(n, 3))),
+        (ValueError, "field_dir must have shape", args(field_dir=torch.zeros(3, n + 2))),
+        (ValueError, "must be on a CUDA device", args()),
+    ]
+    for exc, msg, a in cases:
+        with pytest.raises(exc, match=msg):
+            call(a)
