@@ -87,6 +87,16 @@ enum { HSIM_INIT_GIVEN = 0, HSIM_INIT_COLD_Z = 1, HSIM_INIT_RANDOM = 2 };
 
 /* run_flags */
 #define HSIM_RUN_TRACE_ACCEPTS 0x1u   /* write the accept bitmap to d_trace */
+/* Failure-path checks (for tests of error handling; the run's results are
+ * meaningless and every kernel still exits normally):
+ *   DEBUG_NAN_FIELD: the run's field intensities are staged as NaN, so every
+ *     energy change is NaN and the device reports HSIM_E_NUMERIC through
+ *     hsim_batch_status;
+ *   DEBUG_WAIT_CAP: persistent launches bound every device barrier wait by a
+ *     single polling round, so a wait gives up, releases every later wait and
+ *     hsim_batch_status reports HSIM_E_TIMEOUT. */
+#define HSIM_RUN_DEBUG_NAN_FIELD 0x2u
+#define HSIM_RUN_DEBUG_WAIT_CAP 0x4u
 
 /* ------------------------------------------------------------------ plans */
 /* Ingest one lattice (paper, section "Material building": sites, exchange
@@ -264,6 +274,15 @@ hsim_status hsim_autotune(hsim_batch b, const char *cache_path, int32_t trial_mc
 void hsim_batch_destroy(hsim_batch b);
 
 /* ------------------------------------------------- energy and its gradient */
+/* Uploads the plan's energy tables (user-order rows, padded to 6 or 8 slots
+ * when every row fits) and allocates its fixed energy scratch: the partial
+ * records of one pass of up to 2048 configurations, at most about 128 MiB
+ * (more only when a single group of 32 configurations needs it).
+ * Synchronous and allocating; idempotent.  An energy call on a plan that was
+ * not prepared does this first; after it, energy calls only enqueue work,
+ * allocate nothing and may be captured in graphs.  Batches larger than a
+ * pass run as several passes over the same scratch. */
+hsim_status hsim_energy_prepare(hsim_plan plan);
 /* Eq. 1 for `batch` configurations of one lattice, precision HSIM_FP32
  * (float inputs, double accumulation) or HSIM_FP64_EXACT (double inputs).
  *   d_spins [batch][3][n] user order; d_J_bond [n_bonds] in hsim_plan_bonds
@@ -281,9 +300,9 @@ hsim_status hsim_energy_forward(hsim_plan plan, int32_t batch, hsim_precision pr
  * Any output may be NULL.  Outputs are overwritten (not accumulated); gS, gJ
  * and gk have the precision of the inputs.  With the cubic term of
  * hsim_plan_set_site_terms, dE/dS includes it.
- * Both energy calls use a device scratch owned by the plan, grown when a call
- * needs more; growing it synchronises the device, and two energy calls on
- * one plan must not run concurrently on different streams. */
+ * Both energy calls use the plan's fixed device scratch (hsim_energy_prepare);
+ * two energy calls on one plan must not run concurrently on different
+ * streams. */
 hsim_status hsim_energy_backward(hsim_plan plan, int32_t batch, hsim_precision precision,
                                  const void *d_spins, const void *d_J_bond, const void *d_k,
                                  const void *d_axis, double B, const void *d_field_dir,
@@ -296,6 +315,30 @@ hsim_status hsim_energy_backward(hsim_plan plan, int32_t batch, hsim_precision p
  * the estimate and the covariance term. */
 hsim_status hsim_fluct_estimate(int64_t n, double beta, const double *d_O, const double *d_dE,
                                 const double *d_dO, double *d_out, void *stream);
+
+/* Upstream weights that turn one hsim_energy_backward call into the
+ * fluctuation estimate of the derivatives of a thermal average with respect
+ * to every per-bond constant, every anisotropy constant and the field
+ * intensity at once (paper, section "Thermal averages": response functions
+ * as fluctuations of the equilibrium chain):
+ *   d<O>/dtheta = <dO/dtheta> - beta (<O dE/dtheta> - <O><dE/dtheta>)
+ *              = sum_k w_k dE_k/dtheta,   w_k = (c - beta (O_k - <O>)) / n
+ * for samples k = 0..n-1 drawn at inverse temperature beta, with c = 1 when
+ * O is the energy itself (its own derivative is dE/dtheta) and c = 0 when O
+ * does not depend on the parameters (e.g. a magnetisation).
+ *   d_O [n] double (device): the observable of each sample;
+ *   d_w [n] double (device): receives the weights (may not alias d_O).
+ * The mean <O> is summed in a fixed order.  HSIM_E_ARG for n < 1 or NULL
+ * buffers, HSIM_E_PARAM for a negative or non-finite beta or non-finite c. */
+hsim_status hsim_fluct_weights(int64_t n, double beta, const double *d_O, double c, double *d_w,
+                               void *stream);
+/* Layout conversion for the energy calls: site-major double spins
+ * d_in [n_cfg][n_sites][3] (the layout of hsim_batch_spins_to_user and of
+ * the step-end snapshots) into d_out [n_cfg][3][n_sites] of the given
+ * precision (float for HSIM_FP32, rounded to nearest; double for
+ * HSIM_FP64_EXACT), both device memory, caller-owned. */
+hsim_status hsim_spins_planar(int64_t n_cfg, int64_t n_sites, const double *d_in,
+                              hsim_precision precision, void *d_out, void *stream);
 
 /* ------------------------------------------------- analysis of the history */
 /* A series is the history of one replica at one step, MCS m0 .. mcs-1 of a

@@ -69,7 +69,8 @@ class _Outputs(ctypes.Structure):
                 ("accept", ctypes.c_void_p), ("e_full", ctypes.c_void_p),
                 ("near_ties", ctypes.c_int64), ("max_incr_err", ctypes.c_double),
                 ("max_update_err", ctypes.c_double), ("n_decisions", ctypes.c_int64),
-                ("type_mag", ctypes.c_void_p), ("snapshots", ctypes.c_void_p)]
+                ("type_mag", ctypes.c_void_p), ("snapshots", ctypes.c_void_p),
+                ("dE_trace", ctypes.c_void_p), ("u_trace", ctypes.c_void_p)]
 
 
 def lib():
@@ -246,7 +247,7 @@ def run(lat, T, B, mcs_per_step, seed, replica=0, init="random", spins=None,
         proposal=PROPOSAL_EXACT, first_step=0, recompute_every=100, order=None,
         colour=None, trace_accepts=False, full_energy=False, check_every_update=False,
         policies=None, site_type=None, sigma=None, sigma_min=SIGMA_MIN, sigma_max=SIGMA_MAX,
-        trace_sigma=False, type_mag=False, snapshots=False):
+        trace_sigma=False, type_mag=False, snapshots=False, decision_trace=False):
     """Colour-ordered Metropolis sweep of one replica over a T/B schedule.
 
     policies: None (random move everywhere) or a list of (policy, param) per
@@ -295,7 +296,10 @@ def run(lat, T, B, mcs_per_step, seed, replica=0, init="random", spins=None,
     nt = max(ntypes, 1)
     tm = np.zeros((S_steps, M, nt, 3)) if type_mag else None
     snap = np.zeros((S_steps, n, 3)) if snapshots else None
-    o = _Outputs(_ptr(sp), _ptr(hist), _ptr(acc), _ptr(ef), 0, 0.0, 0.0, 0, _ptr(tm), _ptr(snap))
+    dtr = np.zeros((S_steps * M, n)) if decision_trace else None
+    utr = np.zeros((S_steps * M, n)) if decision_trace else None
+    o = _Outputs(_ptr(sp), _ptr(hist), _ptr(acc), _ptr(ef), 0, 0.0, 0.0, 0, _ptr(tm), _ptr(snap),
+                 _ptr(dtr), _ptr(utr))
     rc = lib().or_run(L.ref, ctypes.byref(p), ctypes.byref(o))
     if rc != 0:
         raise ValueError(f"oracle run rejected its input (code {rc})")
@@ -303,7 +307,7 @@ def run(lat, T, B, mcs_per_step, seed, replica=0, init="random", spins=None,
     return dict(history=hist, spins=sp, accept=acc, e_full=ef, near_ties=o.near_ties,
                 max_incr_err=o.max_incr_err, max_update_err=o.max_update_err,
                 n_decisions=o.n_decisions, sigma=float(sg[0]) if has_ad else None,
-                sigma_trace=strace, type_mag=tm, snapshots=snap)
+                sigma_trace=strace, type_mag=tm, snapshots=snap, dE_trace=dtr, u_trace=utr)
 
 
 def run_replicas(jobs, threads=None):

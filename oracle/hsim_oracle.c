@@ -670,6 +670,8 @@ int or_run(const or_lattice *lat, const or_params *p, or_outputs *out)
                     if (fabs(u - pr) <= 4.0 * ulp) out->near_ties++;
                 }
                 out->n_decisions++;
+                if (out->dE_trace) out->dE_trace[rec * n + i] = dE;
+                if (out->u_trace) out->u_trace[rec * n + i] = u;
                 if (pol == OR_POLICY_ADAPTIVE) {
                     n_ad++;
                     acc_ad += acc;

@@ -97,6 +97,11 @@ typedef struct {
     double *type_mag;
     /* spins at the end of every step (NULL: not recorded): n_steps*n*3 */
     double *snapshots;
+    /* every decision's energy change and acceptance uniform (NULL: not
+     * recorded): (n_steps*mcs_per_step)*n each, user order; lets a caller
+     * find how far each decision was from its tie u = exp(-beta dE) */
+    double *dE_trace;
+    double *u_trace;
 } or_outputs;
 
 /* Philox4x32 with 10 rounds (Salmon, Moraes, Dror and Shaw, SC'11). */

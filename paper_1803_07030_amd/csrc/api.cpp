@@ -9,6 +9,7 @@
 
 hsim_plan plan_create_impl(int64_t, const int64_t *, const int32_t *, const double *,
                            const double *, const double *, const double *);
+void energy_prepare_impl(hsim_plan);
 void energy_forward_impl(hsim_plan, int32_t, hsim_precision, const void *, const void *,
                          const void *, const void *, double, const void *, double *, hipStream_t);
 void energy_backward_impl(hsim_plan, int32_t, hsim_precision, const void *, const void *,
@@ -229,6 +230,11 @@ hsim_status hsim_autotune(hsim_batch b, const char *cache_path, int32_t trial_mc
 
 void hsim_batch_destroy(hsim_batch b) { delete b; }
 
+hsim_status hsim_energy_prepare(hsim_plan plan)
+{
+    return guarded([&] { energy_prepare_impl(plan); });
+}
+
 hsim_status hsim_energy_forward(hsim_plan plan, int32_t batch, hsim_precision precision,
                                 const void *d_spins, const void *d_J_bond, const void *d_k,
                                 const void *d_axis, double B, const void *d_field_dir,
@@ -259,6 +265,31 @@ hsim_status hsim_fluct_estimate(int64_t n, double beta, const double *d_O, const
         if (n < 1 || !d_O || !d_dE || !d_out) throw hsim::Error(HSIM_E_ARG, "fluct_estimate: bad argument");
         if (!std::isfinite(beta) || beta < 0) throw hsim::Error(HSIM_E_PARAM, "beta must be finite and >= 0");
         hsim::hip_check(hsim::launch_fluct(S(stream), n, beta, d_O, d_dE, d_dO, d_out), "fluct launch");
+    });
+}
+
+hsim_status hsim_fluct_weights(int64_t n, double beta, const double *d_O, double c, double *d_w,
+                               void *stream)
+{
+    return guarded([&] {
+        if (n < 1 || !d_O || !d_w) throw hsim::Error(HSIM_E_ARG, "fluct_weights: bad argument");
+        if (!std::isfinite(beta) || beta < 0) throw hsim::Error(HSIM_E_PARAM, "beta must be finite and >= 0");
+        if (!std::isfinite(c)) throw hsim::Error(HSIM_E_PARAM, "c must be finite");
+        hsim::hip_check(hsim::launch_fluct_weights(S(stream), n, beta, d_O, c, d_w), "fluct weights launch");
+    });
+}
+
+hsim_status hsim_spins_planar(int64_t n_cfg, int64_t n_sites, const double *d_in,
+                              hsim_precision precision, void *d_out, void *stream)
+{
+    return guarded([&] {
+        if (n_cfg < 0 || n_sites < 0 || (n_cfg * n_sites > 0 && (!d_in || !d_out)))
+            throw hsim::Error(HSIM_E_ARG, "spins_planar: bad argument");
+        if (precision != HSIM_FP32 && precision != HSIM_FP64_EXACT)
+            throw hsim::Error(HSIM_E_ARG, "bad precision");
+        hsim::hip_check(hsim::launch_spins_planar(S(stream), precision == HSIM_FP64_EXACT, n_cfg,
+                                                  n_sites, d_in, d_out),
+                        "spins planar launch");
     });
 }
 

@@ -48,8 +48,23 @@ int device_cus()
 
 }  // namespace
 
+void hsim_batch_s::drop_graph()
+{
+    if (g_exec) {
+        if (g_done) (void)hipEventSynchronize(g_done);
+        (void)hipGraphExecDestroy(g_exec);
+    }
+    if (g_graph) (void)hipGraphDestroy(g_graph);
+    g_exec = nullptr;
+    g_graph = nullptr;
+    g_key.clear();
+}
+
 hsim_batch_s::~hsim_batch_s()
 {
+    drop_graph();
+    if (g_done) (void)hipEventDestroy(g_done);
+    if (g_cap) (void)hipStreamDestroy(g_cap);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (stage_done) {
         (void)hipEventSynchronize(stage_done);
@@ -299,6 +314,7 @@ void hsim_batch_s::upload_tables()
 void batch_bind_impl(hsim_batch b, int32_t S, int32_t M, void *ws, void *spins, void *hist)
 {
     if (!b || !ws || !spins || !hist) throw Error(HSIM_E_ARG, "bind: NULL buffer");
+    b->drop_graph();
     size_t wsb = 0;
     batch_sizes_impl(b, S, M, &wsb, nullptr, nullptr);
     if (((uintptr_t)ws | (uintptr_t)spins | (uintptr_t)hist) % 16)
@@ -372,6 +388,7 @@ void batch_set_policies_impl(hsim_batch b, int32_t nt, const int32_t *policy, co
     }
     if (P.adaptive && !(smin > 0.0 && smax >= smin && std::isfinite(smax)))
         throw Error(HSIM_E_PARAM, "adaptive width bounds must satisfy 0 < min <= max");
+    b->drop_graph();
     P.sigma_min = smin;
     P.sigma_max = smax;
     std::vector<double> nad((size_t)b->R, 0.0);
@@ -404,6 +421,7 @@ void batch_bind_outputs_impl(hsim_batch b, int32_t n_types, double *type_mag, do
         for (auto p : b->plans)
             for (int32_t t : p->type)
                 if (t >= n_types) throw Error(HSIM_E_PARAM, "a site type is beyond n_types");
+    b->drop_graph();
     b->type_mag = type_mag;
     b->snapshots = snapshots;
     b->tm_types = type_mag ? n_types : 0;
@@ -632,22 +650,27 @@ void run_plain(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st, int from, 
     else enqueue_site_sequence(b, ra, to - from, mask, st, gb, false);
 }
 
-void run_graph(hsim_batch b, const hsim::RunArgs &ra, hipStream_t user_st)
+// Whether work enqueued on st is being recorded into a caller's graph.
+bool capturing(hipStream_t st)
+{
+    if (st == nullptr) return false;   // the legacy stream cannot be captured
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hip_check(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing");
+    return cs != hipStreamCaptureStatusNone;
+}
+
+// GRAPH mode: one recompute period (U MCS) captured once and replayed; the
+// instantiated graph stays on the batch while its captured arguments stay the
+// same (rebinding, new policies or outputs drop it).  Nothing synchronises:
+// the capture runs on a private stream where nothing executes, and the
+// replays are enqueued on the caller's stream.
+void run_graph(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st)
 {
     const int total = ra.n_mcs_run;
-    // the legacy null stream cannot be captured: use a private stream ordered
-    // after the work already queued on the caller's stream
-    hipStream_t st = user_st;
-    hipStream_t own = nullptr;
-    if (user_st == nullptr) {
-        hip_check(hipStreamSynchronize(user_st), "hipStreamSynchronize");
-        hip_check(hipStreamCreateWithFlags(&own, hipStreamNonBlocking), "hipStreamCreate");
-        st = own;
+    if (capturing(st)) {   // inside a caller's capture: plain launches become its nodes
+        run_plain(b, ra, st, 0, total);
+        return;
     }
-    struct OwnStream {
-        hipStream_t s;
-        ~OwnStream() { if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); } }
-    } guard{own};
     int U;
     bool efull_each;
     if (ra.P > 0 && ra.M % ra.P == 0 && ra.P <= 512) {
@@ -662,38 +685,52 @@ void run_graph(hsim_batch b, const hsim::RunArgs &ra, hipStream_t user_st)
         run_plain(b, ra, st, 0, total);
         return;
     }
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    try {
-        auto mask = [&](int t) { return efull_each || t == 0; };
-        if (b->layout == HSIM_LAYOUT_REPLICA) enqueue_rep_sequence(b, ra, U, mask, st, 0, true);
-        else enqueue_site_sequence(b, ra, U, mask, st, 0, true);
-    } catch (...) {
-        (void)hipStreamEndCapture(st, &graph);
-        if (graph) (void)hipGraphDestroy(graph);
-        throw;
+    // the first MCS and the run length index only the accept trace; without
+    // it they are left out of the captured arguments, so later calls reuse
+    // the graph
+    hsim::RunArgs rc = ra;
+    if (!rc.trace) {
+        rc.g0 = 0;
+        rc.n_mcs_run = 0;
     }
-    hip_check(hipStreamEndCapture(st, &graph), "hipStreamEndCapture");
-    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        hip_check(e, "hipGraphInstantiate");
+    std::vector<unsigned char> key(sizeof rc + sizeof b->la + 2 * sizeof(int));
+    const int fe = efull_each ? 1 : 0;
+    std::memcpy(key.data(), &rc, sizeof rc);
+    std::memcpy(key.data() + sizeof rc, &b->la, sizeof b->la);
+    std::memcpy(key.data() + sizeof rc + sizeof b->la, &U, sizeof U);
+    std::memcpy(key.data() + sizeof rc + sizeof b->la + sizeof U, &fe, sizeof fe);
+    if (!b->g_exec || key != b->g_key) {
+        b->drop_graph();
+        if (!b->g_cap) hip_check(hipStreamCreateWithFlags(&b->g_cap, hipStreamNonBlocking), "hipStreamCreate");
+        if (!b->g_done) hip_check(hipEventCreateWithFlags(&b->g_done, hipEventDisableTiming), "hipEventCreate");
+        hipGraph_t graph = nullptr;
+        hip_check(hipStreamBeginCapture(b->g_cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+            auto mask = [&](int t) { return efull_each || t == 0; };
+            if (b->layout == HSIM_LAYOUT_REPLICA) enqueue_rep_sequence(b, rc, U, mask, b->g_cap, 0, true);
+            else enqueue_site_sequence(b, rc, U, mask, b->g_cap, 0, true);
+        } catch (...) {
+            (void)hipStreamEndCapture(b->g_cap, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        hip_check(hipStreamEndCapture(b->g_cap, &graph), "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            hip_check(e, "hipGraphInstantiate");
+        }
+        b->g_graph = graph;
+        b->g_exec = exec;
+        b->g_key.swap(key);
     }
-    for (int k = 0; k < reps; ++k) {
-        e = hipGraphLaunch(exec, st);
-        if (e != hipSuccess) break;
-    }
-    // the executable graph must outlive its queued launches
-    hipError_t e2 = hipStreamSynchronize(st);
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    hip_check(e, "hipGraphLaunch");
-    hip_check(e2, "hipStreamSynchronize");
+    for (int k = 0; k < reps; ++k) hip_check(hipGraphLaunch(b->g_exec, st), "hipGraphLaunch");
+    hip_check(hipEventRecord(b->g_done, st), "hipEventRecord");
     run_plain(b, ra, st, reps * U, total);
 }
 
-bool run_persistent(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st)
+bool run_persistent(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st, uint32_t spin_cap)
 {
     const int bpc = hsim::rep_persistent_blocks_per_cu(b->kmode, b->fmode, b->Rp % 64 == 0 ? 64 : 32, b->la.ell_w);
     const int cus = device_cus();
@@ -709,7 +746,7 @@ bool run_persistent(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st)
     // barrier flags follow the record window
     auto *flags = (uint32_t *)(b->ws + b->off_part + b->rep_rec_bytes());
     hip_check(hsim::launch_rep_persistent(st, b->kmode, b->fmode, b->la, b->rep_ntiles, grid, ra,
-                                          flags, 1u << 24),
+                                          flags, spin_cap),
               "persistent launch");
     return true;
 }
@@ -738,19 +775,42 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
             if (!std::isfinite(f)) throw Error(HSIM_E_PARAM, "non-finite field");
             const size_t k = (size_t)r * b->S_hist + first_step + s;
             b->h_beta[k] = t > 0.0 ? 1.0 / t : std::numeric_limits<double>::infinity();
-            b->h_bfield[k] = f;
+            b->h_bfield[k] = (flags & HSIM_RUN_DEBUG_NAN_FIELD)
+                                 ? std::numeric_limits<double>::quiet_NaN() : f;
         }
     if (n_steps == 0) return;
-    const size_t half = (size_t)b->R * b->S_hist;
-    hip_check(hipEventSynchronize(b->stage_done), "hipEventSynchronize");
-    std::memcpy(b->h_stage, b->h_beta.data(), half * 8);
-    std::memcpy(b->h_stage + half, b->h_bfield.data(), half * 8);
-    hip_check(hipMemcpyAsync(b->ws + b->off_beta, b->h_stage, half * 8, hipMemcpyHostToDevice, st),
-              "hipMemcpyAsync");
-    hip_check(hipMemcpyAsync(b->ws + b->off_bfield, b->h_stage + half, half * 8,
-                             hipMemcpyHostToDevice, st),
-              "hipMemcpyAsync");
-    hip_check(hipEventRecord(b->stage_done, st), "hipEventRecord");
+    const bool cap = capturing(st);
+    if (!cap) {
+        const size_t half = (size_t)b->R * b->S_hist;
+        hip_check(hipEventSynchronize(b->stage_done), "hipEventSynchronize");
+        std::memcpy(b->h_stage, b->h_beta.data(), half * 8);
+        std::memcpy(b->h_stage + half, b->h_bfield.data(), half * 8);
+        hip_check(hipMemcpyAsync(b->ws + b->off_beta, b->h_stage, half * 8, hipMemcpyHostToDevice, st),
+                  "hipMemcpyAsync");
+        hip_check(hipMemcpyAsync(b->ws + b->off_bfield, b->h_stage + half, half * 8,
+                                 hipMemcpyHostToDevice, st),
+                  "hipMemcpyAsync");
+        hip_check(hipEventRecord(b->stage_done, st), "hipEventRecord");
+    } else {
+        // recorded into a caller's graph: this run's schedule travels in the
+        // arguments of small kernels, so every replay writes the same values
+        // and no host buffer has to outlive the graph
+        const int cnt_all = b->R * n_steps;
+        for (int k0 = 0; k0 < cnt_all; k0 += hsim::kPutPairs) {
+            const int cnt = std::min(hsim::kPutPairs, cnt_all - k0);
+            hsim::PutPairs v{};
+            for (int j = 0; j < cnt; ++j) {
+                const int k = k0 + j, r = k / n_steps, s = k % n_steps;
+                const size_t off = (size_t)r * b->S_hist + first_step + s;
+                v.v[2 * j] = b->h_beta[off];
+                v.v[2 * j + 1] = b->h_bfield[off];
+            }
+            hip_check(hsim::launch_put_schedule(st, (double *)(b->ws + b->off_beta),
+                                                (double *)(b->ws + b->off_bfield), b->S_hist,
+                                                first_step, n_steps, k0, cnt, v),
+                      "schedule launch");
+        }
+    }
 
     const uint32_t g0 = (uint32_t)first_step * (uint32_t)b->M;
     const int n_mcs = n_steps * b->M;
@@ -796,8 +856,22 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
     if (mode == HSIM_LAUNCH_PERSISTENT) {
         if (b->layout != HSIM_LAYOUT_REPLICA)
             throw Error(HSIM_E_UNSUPPORTED, "persistent launch needs the replica layout");
-        if (!run_persistent(b, ra, st))
+        if (!run_persistent(b, ra, st, (flags & HSIM_RUN_DEBUG_WAIT_CAP) ? 1u : 1u << 24))
             throw Error(HSIM_E_UNSUPPORTED, "persistent launch cannot be made co-resident");
+        return;
+    }
+    if (cap) {
+        // recorded into a caller's graph: plain launches without the sampled
+        // phase timer (its events would become graph nodes)
+        const int every = b->time_every;
+        b->time_every = 0;
+        try {
+            run_plain(b, ra, st, 0, n_mcs);
+        } catch (...) {
+            b->time_every = every;
+            throw;
+        }
+        b->time_every = every;
         return;
     }
     if (mode == HSIM_LAUNCH_GRAPH && b->time_every == 0) run_graph(b, ra, st);

@@ -7,18 +7,30 @@
 // Layout (user order): spins [batch][3][n]; per-bond constants in the plan's
 // bond order; anisotropy axes and field directions [3][n].
 //
-// The work is a sparse gather (each site reads its neighbours), so it is
-// bandwidth-bound: spins stream from HBM once per pass while the lattice
-// tables (a few MB) stay in L2.  Sums over sites and configurations are done
-// in double precision in a fixed order (wave butterfly, waves in order,
-// tiles in order, batch chunks in order).
+// A sparse gather: every site reads its neighbours in each configuration.
+// Work items are (group of kEG configurations, tile of kEBlock sites); items
+// are dealt to the 8 XCDs in contiguous ranges (group-major), so the tiles
+// holding a tile's neighbours are processed by the same XCD at about the same
+// time and the neighbour reads hit its L2.  Rows of at most 8 entries are
+// read as padded rows (slot-major, padding = the site itself with constant
+// 0, which leaves every sum unchanged), so each configuration's gathers are
+// issued together without branches; kEU configurations are in flight at
+// once.  The lattice tables of a site are read once per group.  Sums over
+// sites and configurations are double precision in a fixed order: lanes by
+// recursive halving, waves in order, tiles lane-strided then butterfly,
+// groups and passes in order.  Batches larger than the plan's pass size run
+// in passes over a fixed scratch (no allocation per call).
+#include <algorithm>
+
 #include "hsim_dev.h"
 
 namespace hsim {
 
 namespace {
 
-constexpr int kEBlock = 256;
+constexpr int kEBlock = 256;   // sites per tile, one per thread
+constexpr int kEG = 32;        // configurations per work item
+constexpr int kEU = 2;         // configurations whose loads are in flight together
 
 __device__ __forceinline__ double wsum(double v)
 {
@@ -39,6 +51,49 @@ __device__ __forceinline__ double bsum(double v, double *lds)
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += lds[k];
     __syncthreads();
     return t;
+}
+
+// Wave sums of U values per lane by recursive halving: at each step a lane
+// keeps the half of its values selected by its lane bit and adds its
+// partner's copy of that half; once one value is left, a butterfly.  Lane l
+// ends with the wave sum of value halving_index<U>(l), the same in every lane
+// of its group of 64/U.
+template <int U>
+__device__ __forceinline__ double halving_sum(double (&v)[U], int ln)
+{
+    int cnt = U;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        if (cnt > 1) {
+            const int h = cnt / 2;
+            const bool up = (ln & m) != 0;
+#pragma unroll
+            for (int k = 0; k < U / 2; ++k)
+                if (k < h) {
+                    const double send = up ? v[k] : v[k + h];
+                    const double keep = up ? v[k + h] : v[k];
+                    v[k] = keep + __shfl_xor(send, m, 64);
+                }
+            cnt = h;
+        } else {
+            v[0] += __shfl_xor(v[0], m, 64);
+        }
+    }
+    return v[0];
+}
+
+template <int U>
+__device__ __forceinline__ int halving_index(int ln)
+{
+    int idx = 0, cnt = U;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        if (cnt > 1) {
+            const int h = cnt / 2;
+            if (ln & m) idx += h;
+            cnt = h;
+        }
+    return idx;
 }
 
 // Lattice data of one site, read once and used for every configuration of
@@ -102,25 +157,163 @@ struct SiteTables {
 
 }  // namespace
 
-// grid (site tiles, batch chunks of kECfg configurations).  Forward: E
-// partial per (configuration, tile).  Backward (BWD): also dE/dS of every
-// site and the dE/dB partial.  The lattice tables of a site are read once
-// per chunk.
-constexpr int kECfg = 32;
+// Padded rows of width W: one work item per block (XCD-aware order), each
+// thread one site and the kEG configurations of the item, kEU at a time.
+template <typename T, bool BWD, int W>
+__global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile, int items,
+                                                        const double *gE, T *gS, double *partE,
+                                                        double *partB, double *partK, double *partJ)
+{
+    const int u_item = xcd_tile((int)blockIdx.x, items);
+    const int grp = u_item / ntile, tile = u_item - grp * ntile;
+    constexpr int kW = kEBlock / 64;
+    __shared__ double ew[kEG][kW], zw[BWD ? kEG : 1][kW];
+    const int64_t i = (int64_t)tile * kEBlock + threadIdx.x;
+    const bool live = i < a.n;
+    const int64_t ii = live ? i : 0;
+    const T *Jb = (const T *)a.Jb;
+    int32_t col[W];
+    T J[W];
+    int32_t bid[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        col[q] = a.ecol[(size_t)q * a.n + ii];
+        bid[q] = a.ebond[(size_t)q * a.n + ii];
+        const T jv = Jb[bid[q] >= 0 ? bid[q] : 0];
+        J[q] = bid[q] >= 0 ? jv : T(0);
+    }
+    const T *kk = (const T *)a.k, *ax = (const T *)a.ax, *nd = (const T *)a.nd;
+    const T k = kk ? kk[ii] : T(0);
+    const T ex = ax ? ax[ii] : T(0), ey = ax ? ax[a.n + ii] : T(0), ez = ax ? ax[2 * a.n + ii] : T(1);
+    const T nx = nd ? nd[ii] : T(0), ny = nd ? nd[a.n + ii] : T(0), nz = nd ? nd[2 * a.n + ii] : T(1);
+    const T kc = a.kc ? ((const T *)a.kc)[ii] : T(0);
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int b0 = grp * kEG;
+    const int nc = min(kEG, a.batch - b0);
+    const bool params = BWD && (partK || partJ);
+    double gk = 0.0, gj[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) gj[q] = 0.0;
+#pragma unroll 1
+    for (int c0 = 0; c0 < nc; c0 += kEU) {
+        double ev[kEU], zv[kEU];
+        T own[kEU][3], nb[kEU][W][3];
+#pragma unroll
+        for (int u = 0; u < kEU; ++u) {
+            const int b = min(b0 + c0 + u, a.batch - 1);
+            const T *S = (const T *)a.S + (size_t)b * 3 * a.n;
+            own[u][0] = S[ii];
+            own[u][1] = S[a.n + ii];
+            own[u][2] = S[2 * a.n + ii];
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                nb[u][q][0] = S[col[q]];
+                nb[u][q][1] = S[a.n + col[q]];
+                nb[u][q][2] = S[2 * a.n + col[q]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kEU; ++u) {
+            const int c = c0 + u, b = b0 + c;
+            const bool ok = live && c < nc;
+            // exchange field, entries in CSR order (padding adds 0 * S_i)
+            T thx = T(0), thy = T(0), thz = T(0);
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                thx += J[q] * nb[u][q][0];
+                thy += J[q] * nb[u][q][1];
+                thz += J[q] * nb[u][q][2];
+            }
+            const T tsx = own[u][0], tsy = own[u][1], tsz = own[u][2];
+            const double sx = tsx, sy = tsy, sz = tsz;
+            const double an = sx * (double)ex + sy * (double)ey + sz * (double)ez;
+            const double zn = sx * (double)nx + sy * (double)ny + sz * (double)nz;
+            double e = -0.5 * (sx * (double)thx + sy * (double)thy + sz * (double)thz) - a.B * zn -
+                       (double)k * an * an;
+            // cubic term of Eq. 3, -kc (Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2)
+            if (a.kc) e -= (double)kc * ((sx * sx * (sy * sy) + sy * sy * (sz * sz)) + sx * sx * (sz * sz));
+            ev[u] = ok ? e : 0.0;
+            zv[u] = ok ? zn : 0.0;
+            if (BWD) {
+                const double gb = ok ? gE[b] : 0.0;
+                const T g = (T)gb;
+                const T B = (T)a.B;
+                const T an_t = tsx * ex + tsy * ey + tsz * ez;
+                const T two_ka = T(2) * k * an_t;
+                T cx = T(0), cy = T(0), cz = T(0);
+                if (a.kc) {
+                    const T kc2 = T(2) * kc;
+                    const T x2 = tsx * tsx, y2 = tsy * tsy, z2 = tsz * tsz;
+                    cx = kc2 * tsx * (y2 + z2);
+                    cy = kc2 * tsy * (x2 + z2);
+                    cz = kc2 * tsz * (x2 + y2);
+                }
+                if (gS && ok) {
+                    T *o = gS + (size_t)b * 3 * a.n;
+                    o[i] = g * (-thx - B * nx - two_ka * ex - cx);
+                    o[a.n + i] = g * (-thy - B * ny - two_ka * ey - cy);
+                    o[2 * a.n + i] = g * (-thz - B * nz - two_ka * ez - cz);
+                }
+                if (params) {
+                    gk += gb * -(an * an);
+                    // bonds whose lower end is i (padding: col == i, skipped)
+#pragma unroll
+                    for (int q = 0; q < W; ++q) {
+                        const double d = sx * (double)nb[u][q][0] + sy * (double)nb[u][q][1] +
+                                         sz * (double)nb[u][q][2];
+                        gj[q] += col[q] > i ? gb * -d : 0.0;
+                    }
+                }
+            }
+        }
+        const double es = halving_sum<kEU>(ev, ln);
+        const int cw = c0 + halving_index<kEU>(ln);
+        const bool wr = (ln & (64 / kEU - 1)) == 0 && cw < nc;
+        if (wr) ew[cw][wv] = es;
+        if (BWD) {
+            const double zs = halving_sum<kEU>(zv, ln);
+            if (wr) zw[cw][wv] = zs;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+        const int c = threadIdx.x, b = b0 + c;
+        const size_t t = (size_t)b * ntile + tile;
+        double et = 0.0, zt = 0.0;
+        for (int q = 0; q < kW; ++q) {
+            et += ew[c][q];
+            if (BWD) zt += zw[c][q];
+        }
+        if (partE) partE[t] = et;
+        if (BWD) partB[t] = -gE[b] * zt;
+    }
+    if (!params || !live) return;
+    if (partK) partK[(size_t)grp * a.n + i] = gk;
+    if (!partJ) return;
+#pragma unroll
+    for (int q = 0; q < W; ++q)
+        if (col[q] > i) partJ[(size_t)grp * a.nb + bid[q]] = gj[q];
+}
+
+// Rows longer than the padded width (any degree): grid (site tiles, chunks of
+// kEG configurations), each thread one site walking its CSR row for every
+// configuration of the chunk.  Forward: E partial per (configuration, tile).
+// Backward (BWD): also dE/dS of every site, the dE/dB partial and the chunk's
+// dE/dk, dE/dJ partials (per site, per bond).
 template <typename T, bool BWD>
-__global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const double *gE, T *gS,
+__global__ __launch_bounds__(kEBlock) void k_energy_csr(EnergyArgs a, const double *gE, T *gS,
                                                          double *partE, double *partB,
                                                          double *partK, double *partJ)
 {
     // wave sums of every configuration of the chunk, added in wave order
     // after the loop (one barrier per chunk instead of two per configuration)
     constexpr int kW = kEBlock / 64;
-    __shared__ double ew[kECfg][kW], zw[BWD ? kECfg : 1][kW];
+    __shared__ double ew[kEG][kW], zw[BWD ? kEG : 1][kW];
     const int64_t i = (int64_t)blockIdx.x * kEBlock + threadIdx.x;
     const bool live = i < a.n;
     const SiteTables<T> st(a, live ? i : 0);
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    const int b0 = (int)blockIdx.y * kECfg;
+    const int b0 = (int)blockIdx.y * kEG;
     // backward, parameter gradients of the chunk: dE/dk_i and dE/dJ of the
     // bonds whose lower end is i (rows up to kMaxNb entries here; longer rows
     // below), summed over the chunk's configurations in order
@@ -128,7 +321,7 @@ __global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const dou
     double gk = 0.0, gj[kMaxNb];
 #pragma unroll
     for (int q = 0; q < kMaxNb; ++q) gj[q] = 0.0;
-    for (int c = 0; c < kECfg; ++c) {
+    for (int c = 0; c < kEG; ++c) {
         const int b = b0 + c;
         if (b >= a.batch) break;   // uniform over the block
         double e = 0.0, zn = 0.0;
@@ -187,7 +380,7 @@ __global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const dou
         }
     }
     __syncthreads();
-    const int nc = min(kECfg, a.batch - b0);
+    const int nc = min(kEG, a.batch - b0);
     if ((int)threadIdx.x < nc) {
         const int c = threadIdx.x, b = b0 + c;
         const size_t t = (size_t)b * gridDim.x + blockIdx.x;
@@ -206,9 +399,9 @@ __global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const dou
     if (st.deg <= kMaxNb) {
 #pragma unroll
         for (int q = 0; q < kMaxNb; ++q)
-            if (q < st.deg && st.col[q] > i) partJ[ch * a.nnz + st.rb + q] = gj[q];
+            if (q < st.deg && st.col[q] > i) partJ[ch * a.nb + a.bond[st.rb + q]] = gj[q];
     } else {
-        const int b1 = min(a.batch, b0 + kECfg);
+        const int b1 = min(a.batch, b0 + kEG);
         for (int64_t p = st.rb; p < st.rb + st.deg; ++p) {
             const int64_t j = a.ci[p];
             if (j <= i) continue;
@@ -219,134 +412,202 @@ __global__ __launch_bounds__(kEBlock) void k_energy_site(EnergyArgs a, const dou
                                  (double)S[2 * a.n + i] * (double)S[2 * a.n + j];
                 v += gE[b] * -d;
             }
-            partJ[ch * a.nnz + p] = v;
+            partJ[ch * a.nb + a.bond[p]] = v;
         }
     }
 }
 
-// Sums in order: E[b] over tiles; gJ over chunks (at each bond's lower-end
-// entry); gk over chunks; gB over (config, tile) records.
+// Per-configuration sums of tile partials: one wave per configuration,
+// lanes over tiles lane-strided in order, then a butterfly.
+__global__ __launch_bounds__(256) void k_energy_tiles(int cnt, int ntile, const double *part,
+                                                      double *out)
+{
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6), ln = threadIdx.x & 63;
+    if (b >= cnt) return;
+    double v = 0.0;
+    for (int t = ln; t < ntile; t += 64) v += part[(size_t)b * ntile + t];
+    v = wsum(v);
+    if (ln == 0) out[b] = v;
+}
+
+// dE/dk and dE/dJ of a pass: the groups' partials summed in order, added to
+// the sums of the earlier passes (first: start them); the last pass writes
+// the outputs in the inputs' precision.
 template <typename T>
-__global__ __launch_bounds__(256) void k_energy_finish(EnergyArgs a, int ntile, int nchunk,
-                                                       const double *partE, double *E,
+__global__ __launch_bounds__(256) void k_energy_params(int64_t n, int64_t nb, int ngroups,
                                                        const double *partK, const double *partJ,
-                                                       const int32_t *fwd_entry, T *gJ, T *gk,
-                                                       const double *partB, double *partBc)
+                                                       double *accK, double *accJ, int first,
+                                                       int last, T *gk, T *gJ)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (E && t < a.batch) {
+    if (gJ && t < nb) {
         double v = 0.0;
-        for (int k = 0; k < ntile; ++k) v += partE[(size_t)t * ntile + k];
-        E[t] = v;
+        for (int g = 0; g < ngroups; ++g) v += partJ[(size_t)g * nb + t];
+        if (!first) v = accJ[t] + v;
+        if (last) gJ[t] = (T)v;
+        else accJ[t] = v;
     }
-    if (gJ && t < a.nb) {
-        const int64_t p = fwd_entry[t];
+    if (gk && t < n) {
         double v = 0.0;
-        for (int c = 0; c < nchunk; ++c) v += partJ[(size_t)c * a.nnz + p];
-        gJ[t] = (T)v;
-    }
-    if (gk && t < a.n) {
-        double v = 0.0;
-        for (int c = 0; c < nchunk; ++c) v += partK[(size_t)c * a.n + t];
-        gk[t] = (T)v;
-    }
-    if (partBc && t < a.batch) {
-        double v = 0.0;
-        for (int k = 0; k < ntile; ++k) v += partB[(size_t)t * ntile + k];
-        partBc[t] = v;
+        for (int g = 0; g < ngroups; ++g) v += partK[(size_t)g * n + t];
+        if (!first) v = accK[t] + v;
+        if (last) gk[t] = (T)v;
+        else accK[t] = v;
     }
 }
 
-// dE/dB: the per-configuration sums in a fixed order (thread t takes
-// configurations t, t + 256, ... in order; then the block sum).
-__global__ __launch_bounds__(256) void k_energy_gB(int batch, const double *partBc, double *gB)
+// dE/dB of a pass: its configurations' sums in a fixed order (thread t takes
+// t, t + 256, ...; then the block sum), added to the earlier passes'.
+__global__ __launch_bounds__(256) void k_energy_gB(int cnt, const double *pB, double *accB,
+                                                   int first, int last, double *gB)
 {
     __shared__ double red[4];
     double v = 0.0;
-    for (int t = threadIdx.x; t < batch; t += blockDim.x) v += partBc[t];
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) v += pB[t];
     v = bsum(v, red);
-    if (threadIdx.x == 0) gB[0] = v;
+    if (threadIdx.x == 0) {
+        if (!first) v = accB[0] + v;
+        if (last) gB[0] = v;
+        else accB[0] = v;
+    }
 }
 
-int64_t energy_scratch_doubles(int64_t n, int64_t nnz, int batch, int)
+EnergyLayout energy_layout(int64_t n, int64_t nb, int ell_w, int64_t cap_doubles, bool forward_only,
+                           int min_groups)
 {
-    const int64_t ntile = (n + kEBlock - 1) / kEBlock;
-    const int64_t nchunk = (batch + kECfg - 1) / kECfg;
-    // partE, partB: batch*ntile each; partK: nchunk*n; partJ: nchunk*nnz; partBc: batch
-    return 2 * (int64_t)batch * ntile + nchunk * n + nchunk * nnz + batch;
+    EnergyLayout L{};
+    L.ntile = (int)((n + kEBlock - 1) / kEBlock);
+    L.ell_w = ell_w;
+    // groups per pass: the partial records of a pass fit the scratch
+    const int64_t per_group = forward_only ? (int64_t)kEG * L.ntile
+                                           : 2 * (int64_t)kEG * L.ntile + n + nb + kEG;
+    const int64_t fixed = forward_only ? 0 : n + nb + 8;
+    int64_t g = (cap_doubles - fixed) / std::max<int64_t>(per_group, 1);
+    g = std::min<int64_t>(g, kEnergyMaxGroups);
+    L.groups = (int)std::max<int64_t>(g, min_groups);
+    L.pass_cfg = L.groups * kEG;
+    auto al = [](int64_t x) { return (x + 31) / 32 * 32; };   // 256-byte aligned blocks
+    int64_t off = 0;
+    L.off_partE = off;
+    off += al((int64_t)L.pass_cfg * L.ntile);
+    if (!forward_only) {
+        L.off_partB = off;
+        off += al((int64_t)L.pass_cfg * L.ntile);
+        L.off_partK = off;
+        off += al((int64_t)L.groups * n);
+        L.off_partJ = off;
+        off += al((int64_t)L.groups * nb);
+        L.off_accK = off;
+        off += al(n);
+        L.off_accJ = off;
+        off += al(nb);
+        L.off_pB = off;
+        off += al(L.pass_cfg);
+        L.off_accB = off;
+        off += 32;
+    }
+    L.doubles = off;
+    return L;
 }
 
-hipError_t launch_energy_forward(hipStream_t st, bool f64, const EnergyArgs &a, double *scratch,
-                                 int, double *E)
+namespace {
+
+template <typename T, bool BWD>
+hipError_t launch_site_kernel(hipStream_t st, const EnergyArgs &a, const EnergyLayout &L,
+                              const double *gE, T *gS, double *partE, double *partB,
+                              double *partK, double *partJ)
 {
-    const int ntile = (int)((a.n + kEBlock - 1) / kEBlock);
-    dim3 grid((unsigned)ntile, (unsigned)((a.batch + kECfg - 1) / kECfg));
-    double *partE = scratch;
-    if (f64)
-        hipLaunchKernelGGL((k_energy_site<double, false>), grid, dim3(kEBlock), 0, st, a,
-                           (const double *)nullptr, (double *)nullptr, partE, (double *)nullptr,
-                           (double *)nullptr, (double *)nullptr);
-    else
-        hipLaunchKernelGGL((k_energy_site<float, false>), grid, dim3(kEBlock), 0, st, a,
-                           (const double *)nullptr, (float *)nullptr, partE, (double *)nullptr,
-                           (double *)nullptr, (double *)nullptr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    dim3 g2((unsigned)((a.batch + 255) / 256));
-    if (f64)
-        hipLaunchKernelGGL((k_energy_finish<double>), g2, dim3(256), 0, st, a, ntile, 0, partE, E,
-                           (const double *)nullptr, (const double *)nullptr,
-                           (const int32_t *)nullptr, (double *)nullptr, (double *)nullptr,
-                           (const double *)nullptr, (double *)nullptr);
-    else
-        hipLaunchKernelGGL((k_energy_finish<float>), g2, dim3(256), 0, st, a, ntile, 0, partE, E,
-                           (const double *)nullptr, (const double *)nullptr,
-                           (const int32_t *)nullptr, (float *)nullptr, (float *)nullptr,
-                           (const double *)nullptr, (double *)nullptr);
+    const int ngroups = (a.batch + kEG - 1) / kEG;
+    if (L.ell_w == 6 || L.ell_w == 8) {
+        const int items = ngroups * L.ntile;
+        if (L.ell_w == 6)
+            hipLaunchKernelGGL((k_energy_ell<T, BWD, 6>), dim3((unsigned)items), dim3(kEBlock), 0, st, a,
+                               L.ntile, items, gE, gS, partE, partB, partK, partJ);
+        else
+            hipLaunchKernelGGL((k_energy_ell<T, BWD, 8>), dim3((unsigned)items), dim3(kEBlock), 0, st, a,
+                               L.ntile, items, gE, gS, partE, partB, partK, partJ);
+    } else {
+        hipLaunchKernelGGL((k_energy_csr<T, BWD>), dim3((unsigned)L.ntile, (unsigned)ngroups),
+                           dim3(kEBlock), 0, st, a, gE, gS, partE, partB, partK, partJ);
+    }
     return hipGetLastError();
+}
+
+// The pass [b0, b0 + cnt) of the batch: the arguments with the spins (and
+// their gradients) moved to the pass's first configuration.
+EnergyArgs pass_args(const EnergyArgs &a, bool f64, int b0, int cnt)
+{
+    EnergyArgs p = a;
+    const size_t es = f64 ? 8 : 4;
+    p.S = (const char *)a.S + (size_t)b0 * 3 * a.n * es;
+    p.batch = cnt;
+    return p;
+}
+
+}  // namespace
+
+hipError_t launch_energy_forward(hipStream_t st, bool f64, const EnergyArgs &a,
+                                 const EnergyLayout &L, double *scratch, double *E)
+{
+    if (L.pass_cfg < 1) return hipErrorInvalidValue;
+    for (int b0 = 0; b0 < a.batch; b0 += L.pass_cfg) {
+        const int cnt = std::min(L.pass_cfg, a.batch - b0);
+        const EnergyArgs p = pass_args(a, f64, b0, cnt);
+        double *partE = scratch + L.off_partE;
+        hipError_t e = f64 ? launch_site_kernel<double, false>(st, p, L, nullptr, nullptr, partE, nullptr, nullptr, nullptr)
+                           : launch_site_kernel<float, false>(st, p, L, nullptr, nullptr, partE, nullptr, nullptr, nullptr);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_energy_tiles, dim3((unsigned)((cnt + 3) / 4)), dim3(256), 0, st, cnt,
+                           L.ntile, (const double *)partE, E + b0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_energy_backward(hipStream_t st, bool f64, const EnergyArgs &a, const double *gE,
-                                  void *gS, void *gJ, void *gk, double *gB, double *scratch,
-                                  int)
+                                  void *gS, void *gJ, void *gk, double *gB, const EnergyLayout &L,
+                                  double *scratch)
 {
-    const int ntile = (int)((a.n + kEBlock - 1) / kEBlock);
-    const int nchunk = (a.batch + kECfg - 1) / kECfg;
-    double *partE = scratch;
-    double *partB = partE + (size_t)a.batch * ntile;
-    double *partK = partB + (size_t)a.batch * ntile;
-    double *partJ = partK + (size_t)nchunk * a.n;
-    double *partBc = partJ + (size_t)nchunk * a.nnz;
-    const int32_t *fwd = a.fwd_entry;
-    dim3 grid((unsigned)ntile, (unsigned)nchunk);
-    // one pass: dE/dS, the dE/dB partials and the dE/dk, dE/dJ chunk partials
-    double *pk = gk ? partK : nullptr, *pj = gJ ? partJ : nullptr;
-    if (f64)
-        hipLaunchKernelGGL((k_energy_site<double, true>), grid, dim3(kEBlock), 0, st, a, gE,
-                           (double *)gS, (double *)nullptr, partB, pk, pj);
-    else
-        hipLaunchKernelGGL((k_energy_site<float, true>), grid, dim3(kEBlock), 0, st, a, gE,
-                           (float *)gS, (double *)nullptr, partB, pk, pj);
-    hipError_t e0 = hipGetLastError();
-    if (e0 != hipSuccess) return e0;
-    int64_t m = a.nb;
-    if (a.n > m) m = a.n;
-    if (a.batch > m) m = a.batch;
-    if (m < 1) m = 1;
-    dim3 g3((unsigned)((m + 255) / 256));
-    double *bc = gB ? partBc : nullptr;
-    if (f64)
-        hipLaunchKernelGGL((k_energy_finish<double>), g3, dim3(256), 0, st, a, ntile, nchunk,
-                           (const double *)nullptr, (double *)nullptr, partK, partJ, fwd,
-                           (double *)gJ, (double *)gk, (const double *)partB, bc);
-    else
-        hipLaunchKernelGGL((k_energy_finish<float>), g3, dim3(256), 0, st, a, ntile, nchunk,
-                           (const double *)nullptr, (double *)nullptr, partK, partJ, fwd,
-                           (float *)gJ, (float *)gk, (const double *)partB, bc);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !gB) return e;
-    hipLaunchKernelGGL(k_energy_gB, dim3(1), dim3(256), 0, st, a.batch, (const double *)partBc, gB);
-    return hipGetLastError();
+    if (L.pass_cfg < 1) return hipErrorInvalidValue;
+    double *partB = scratch + L.off_partB, *partK = scratch + L.off_partK;
+    double *partJ = scratch + L.off_partJ, *accK = scratch + L.off_accK, *accJ = scratch + L.off_accJ;
+    double *pB = scratch + L.off_pB, *accB = scratch + L.off_accB;
+    const size_t es = f64 ? 8 : 4;
+    const int64_t m = std::max<int64_t>(std::max<int64_t>(a.n, a.nb), 1);
+    for (int b0 = 0; b0 < a.batch; b0 += L.pass_cfg) {
+        const int cnt = std::min(L.pass_cfg, a.batch - b0);
+        const int first = b0 == 0, last = b0 + cnt >= a.batch;
+        const EnergyArgs p = pass_args(a, f64, b0, cnt);
+        void *gSp = gS ? (char *)gS + (size_t)b0 * 3 * a.n * es : nullptr;
+        double *pk = gk ? partK : nullptr, *pj = gJ ? partJ : nullptr;
+        hipError_t e = f64 ? launch_site_kernel<double, true>(st, p, L, gE + b0, (double *)gSp, nullptr, partB, pk, pj)
+                           : launch_site_kernel<float, true>(st, p, L, gE + b0, (float *)gSp, nullptr, partB, pk, pj);
+        if (e != hipSuccess) return e;
+        if (gJ || gk) {
+            const int ng = (cnt + kEG - 1) / kEG;
+            const dim3 g3((unsigned)((m + 255) / 256));
+            if (f64)
+                hipLaunchKernelGGL((k_energy_params<double>), g3, dim3(256), 0, st, a.n, a.nb, ng,
+                                   (const double *)partK, (const double *)partJ, accK, accJ, first,
+                                   last, (double *)gk, (double *)gJ);
+            else
+                hipLaunchKernelGGL((k_energy_params<float>), g3, dim3(256), 0, st, a.n, a.nb, ng,
+                                   (const double *)partK, (const double *)partJ, accK, accJ, first,
+                                   last, (float *)gk, (float *)gJ);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (gB) {
+            hipLaunchKernelGGL(k_energy_tiles, dim3((unsigned)((cnt + 3) / 4)), dim3(256), 0, st, cnt,
+                               L.ntile, (const double *)partB, pB);
+            hipLaunchKernelGGL(k_energy_gB, dim3(1), dim3(256), 0, st, cnt, (const double *)pB, accB,
+                               first, last, gB);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
 // d<O>/dtheta = <dO> - beta (<O dE> - <O><dE>): one block, fixed-order sums.
@@ -382,6 +643,55 @@ hipError_t launch_fluct(hipStream_t st, int64_t n, double beta, const double *O,
                         const double *dO, double *out)
 {
     hipLaunchKernelGGL(k_fluct, dim3(1), dim3(1024), 0, st, n, beta, O, dE, dO, out);
+    return hipGetLastError();
+}
+
+// Upstream weights of the fluctuation estimator: w_k = (c - beta (O_k - <O>)) / n
+// (one block; the mean in a fixed order).
+__global__ __launch_bounds__(1024) void k_fluct_weights(int64_t n, double beta, const double *O,
+                                                        double c, double *w)
+{
+    __shared__ double red[16];
+    __shared__ double mean;
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) s += O[t];
+    s = bsum(s, red);
+    if (threadIdx.x == 0) mean = s / (double)n;
+    __syncthreads();
+    const double m = mean, inv = 1.0 / (double)n;
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) w[t] = (c - beta * (O[t] - m)) * inv;
+}
+
+hipError_t launch_fluct_weights(hipStream_t st, int64_t n, double beta, const double *O, double c,
+                                double *w)
+{
+    hipLaunchKernelGGL(k_fluct_weights, dim3(1), dim3(1024), 0, st, n, beta, O, c, w);
+    return hipGetLastError();
+}
+
+// Site-major double spins [cfg][n][3] -> planar [cfg][3][n] of type T.
+template <typename T>
+__global__ __launch_bounds__(256) void k_spins_planar(int64_t total, int64_t n, const double *in,
+                                                      T *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // cfg * n + i
+    if (t >= total) return;
+    const int64_t c = t / n, i = t - c * n;
+    const double *s = in + 3 * t;
+    T *o = out + 3 * c * n + i;
+    o[0] = (T)s[0];
+    o[n] = (T)s[1];
+    o[2 * n] = (T)s[2];
+}
+
+hipError_t launch_spins_planar(hipStream_t st, bool f64, int64_t n_cfg, int64_t n,
+                               const double *in, void *out)
+{
+    const int64_t total = n_cfg * n;
+    if (total == 0) return hipSuccess;
+    const dim3 grid((unsigned)((total + 255) / 256));
+    if (f64) hipLaunchKernelGGL(k_spins_planar<double>, grid, dim3(256), 0, st, total, n, in, (double *)out);
+    else hipLaunchKernelGGL(k_spins_planar<float>, grid, dim3(256), 0, st, total, n, in, (float *)out);
     return hipGetLastError();
 }
 

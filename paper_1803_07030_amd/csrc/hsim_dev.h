@@ -153,6 +153,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nt)
 // All return hipError_t of the launch.  Template choices are resolved inside.
 hipError_t launch_ctl_set(hipStream_t st, Ctl *ctl, uint32_t g);
 hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, uint32_t v, int64_t n);
+// Schedule values carried in kernel arguments (for runs recorded into a
+// caller's graph): entries k0 .. k0+cnt-1 of the flat (replica, step) order of
+// a run, each a (beta, field) pair, written to beta/bfield [R][S_hist].
+constexpr int kPutPairs = 112;
+struct PutPairs {
+    double v[2 * kPutPairs];
+};
+hipError_t launch_put_schedule(hipStream_t st, double *beta, double *bfield, int S_hist,
+                               int first_step, int n_steps, int k0, int cnt, const PutPairs &vals);
 
 hipError_t launch_init_spins(hipStream_t st, bool f64, const RepDesc *reps, int R,
                              int max_n, int mode, const double *given, const int64_t *given_off,
@@ -208,19 +217,37 @@ struct EnergyArgs {
     const int32_t *ci;      // nnz
     const int32_t *bond;    // nnz: bond id of each entry
     const int32_t *fwd_entry; // nb: the CSR entry of each bond at its lower end
+    const int32_t *ecol;    // [ell_w][n] padded rows, slot-major (padding: the site itself)
+    const int32_t *ebond;   // [ell_w][n] bond id of each slot (-1 past the row)
     int64_t n, nnz, nb;
     int batch;
     const void *S, *Jb, *k, *ax, *nd;
     const void *kc;         // NULL, or [n] cubic constants of the plan (user order)
     double B;
 };
-hipError_t launch_energy_forward(hipStream_t st, bool f64, const EnergyArgs &a, double *partial,
-                                 int nchunk, double *E);
-hipError_t launch_energy_backward(hipStream_t st, bool f64, const EnergyArgs &a,
-                                  const double *gE, void *gS, void *gJ, void *gk, double *gB,
-                                  double *scratch, int nchunk);
-int64_t energy_scratch_doubles(int64_t n, int64_t nb, int batch, int nchunk);
+// Scratch of the energy calls: partial records of one pass of at most
+// pass_cfg configurations (groups of 32), in doubles from the scratch start.
+constexpr int kEnergyMaxGroups = 64;
+struct EnergyLayout {
+    int ntile, ell_w, groups, pass_cfg;
+    int64_t off_partE, off_partB, off_partK, off_partJ, off_accK, off_accJ, off_pB, off_accB;
+    int64_t doubles;
+};
+// Layout for a plan of n sites and nb bonds in a scratch of about
+// cap_doubles, with at least min_groups groups per pass (0: groups = 0 when
+// not even one fits); forward_only: the forward's records alone.
+EnergyLayout energy_layout(int64_t n, int64_t nb, int ell_w, int64_t cap_doubles, bool forward_only,
+                           int min_groups);
+hipError_t launch_energy_forward(hipStream_t st, bool f64, const EnergyArgs &a,
+                                 const EnergyLayout &L, double *scratch, double *E);
+hipError_t launch_energy_backward(hipStream_t st, bool f64, const EnergyArgs &a, const double *gE,
+                                  void *gS, void *gJ, void *gk, double *gB, const EnergyLayout &L,
+                                  double *scratch);
 hipError_t launch_fluct(hipStream_t st, int64_t n, double beta, const double *O,
                         const double *dE, const double *dO, double *out);
+hipError_t launch_fluct_weights(hipStream_t st, int64_t n, double beta, const double *O, double c,
+                                double *w);
+hipError_t launch_spins_planar(hipStream_t st, bool f64, int64_t n_cfg, int64_t n,
+                               const double *in, void *out);
 
 }  // namespace hsim

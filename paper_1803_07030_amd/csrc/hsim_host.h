@@ -99,10 +99,19 @@ struct hsim_plan_s {
     hsim::DevBuf d_ell_col, d_ell_J, d_ellT_col, d_ellT_Jf, d_ellT_Jd, d_type;
     hsim::DevBuf d_kcf, d_kcd, d_muf, d_mud, d_ukcf, d_ukcd;
     void upload_terms();
-    hsim::DevBuf d_urp, d_uci, d_ubond, d_fwd, d_scratch;
+    hsim::DevBuf d_urp, d_uci, d_ubond, d_fwd;
+    // energy calls: padded rows of the user-order CSR (width 6 or 8 when
+    // every row fits, else 0: CSR walk), slot-major [e_w][n]; the fixed
+    // scratch and its pass layout, set up once by prepare_energy()
+    int e_w = 0;
+    std::vector<int32_t> uell_col, uell_bond;
+    hsim::DevBuf d_uell_col, d_uell_bond, d_escratch;
+    hsim::EnergyLayout elayout{};
+    bool energy_ready = false;
 
     void upload_sweep();
     void upload_energy();
+    void prepare_energy();
 };
 
 struct hsim_batch_s {
@@ -165,6 +174,16 @@ struct hsim_batch_s {
     std::vector<double> h_beta, h_bfield;   // [R][S_hist]
     double *h_stage = nullptr;              // pinned staging of beta and bfield
     hipEvent_t stage_done = nullptr;
+
+    // GRAPH launches: the instantiated graph of one recompute period, kept
+    // across calls while the captured arguments stay the same; captured on a
+    // private stream (nothing runs there) and replayed on the caller's
+    hipGraph_t g_graph = nullptr;
+    hipGraphExec_t g_exec = nullptr;
+    hipStream_t g_cap = nullptr;
+    hipEvent_t g_done = nullptr;          // recorded after the last enqueued replay
+    std::vector<unsigned char> g_key;
+    void drop_graph();                    // waits for enqueued replays, then frees
 
     // tuning
     int tuned_launch = -1;

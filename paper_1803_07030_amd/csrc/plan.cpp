@@ -218,6 +218,23 @@ hsim_plan plan_create_impl(int64_t n, const int64_t *rp, const int32_t *col, con
                 P->ubond[p] = P->ubond[q];
             }
         P->nb = (int64_t)P->fwd_entry.size();
+        // padded rows for the energy calls (slot-major; padding: the site
+        // itself with bond id -1, i.e. constant 0)
+        int64_t md = 0;
+        for (int64_t i = 0; i < n; ++i) md = std::max<int64_t>(md, rp[i + 1] - rp[i]);
+        P->e_w = md <= 6 ? 6 : (md <= 8 ? 8 : 0);
+        if (P->e_w > 0 && n > 0) {
+            const int W = P->e_w;
+            P->uell_col.assign((size_t)W * n, 0);
+            P->uell_bond.assign((size_t)W * n, -1);
+            for (int64_t i = 0; i < n; ++i)
+                for (int q = 0; q < W; ++q) {
+                    const int64_t p = rp[i] + q;
+                    const bool in = p < rp[i + 1];
+                    P->uell_col[(size_t)q * n + i] = in ? col[p] : (int32_t)i;
+                    P->uell_bond[(size_t)q * n + i] = in ? P->ubond[p] : -1;
+                }
+        }
     } catch (...) {
         delete P;
         throw;
@@ -308,7 +325,7 @@ void plan_set_site_terms_impl(hsim_plan P, const double *k_cubic, const double *
             P->muf[k] = (float)P->mud[k];
         }
     }
-    if (P->sweep_on_device) P->upload_terms();
+    if (P->sweep_on_device || P->energy_ready) P->upload_terms();
 }
 
 // Site types (user order, values 0 .. kMaxTypes-1) kept in internal order;
@@ -338,7 +355,24 @@ void hsim_plan_s::upload_energy()
     d_uci.upload(uci);
     d_ubond.upload(ubond);
     d_fwd.upload(fwd_entry);
+    if (e_w > 0) {
+        d_uell_col.upload(uell_col);
+        d_uell_bond.upload(uell_bond);
+    }
     energy_on_device = true;
+}
+
+// Energy tables on the device and the fixed scratch: at most about
+// kEnergyScratchDoubles, at least one group of configurations per pass.
+constexpr int64_t kEnergyScratchDoubles = (int64_t)16 << 20;   // 128 MiB
+void hsim_plan_s::prepare_energy()
+{
+    if (energy_ready) return;
+    upload_energy();
+    upload_terms();
+    elayout = hsim::energy_layout(n, nb, e_w, kEnergyScratchDoubles, false, 1);
+    d_escratch.alloc((size_t)elayout.doubles * sizeof(double));
+    energy_ready = true;
 }
 
 // ----------------------------------------------------------------- energy
@@ -347,13 +381,13 @@ namespace {
 hsim::EnergyArgs energy_args(hsim_plan P, int32_t batch, const void *S, const void *Jb,
                              const void *k, const void *ax, double B, const void *nd, bool f64)
 {
-    P->upload_energy();
-    P->upload_terms();
     hsim::EnergyArgs a{};
     a.rp = (const int64_t *)P->d_urp.p;
     a.ci = (const int32_t *)P->d_uci.p;
     a.bond = (const int32_t *)P->d_ubond.p;
     a.fwd_entry = (const int32_t *)P->d_fwd.p;
+    a.ecol = (const int32_t *)P->d_uell_col.p;
+    a.ebond = (const int32_t *)P->d_uell_bond.p;
     a.n = P->n;
     a.nnz = P->nnz;
     a.nb = P->nb;
@@ -366,17 +400,6 @@ hsim::EnergyArgs energy_args(hsim_plan P, int32_t batch, const void *S, const vo
     a.kc = P->ukcd.empty() ? nullptr : (f64 ? P->d_ukcd.p : P->d_ukcf.p);
     a.B = B;
     return a;
-}
-
-double *energy_scratch(hsim_plan P, int32_t batch)
-{
-    const size_t need = (size_t)hsim::energy_scratch_doubles(P->n, P->nnz, batch, 0) * sizeof(double);
-    if (P->d_scratch.bytes < need) {
-        // a smaller scratch may still be read by queued work
-        hsim::hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
-        P->d_scratch.alloc(need);
-    }
-    return (double *)P->d_scratch.p;
 }
 
 }  // namespace
@@ -395,9 +418,10 @@ void energy_forward_impl(hsim_plan P, int32_t batch, hsim_precision prec, const 
         hsim::hip_check(hsim::launch_fill_u32(st, (uint32_t *)E, 0u, (int64_t)batch * 2), "fill launch");
         return;
     }
+    P->prepare_energy();
     const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd, prec == HSIM_FP64_EXACT);
-    double *scr = energy_scratch(P, batch);
-    hsim::hip_check(hsim::launch_energy_forward(st, prec == HSIM_FP64_EXACT, a, scr, 0, E),
+    hsim::hip_check(hsim::launch_energy_forward(st, prec == HSIM_FP64_EXACT, a, P->elayout,
+                                                (double *)P->d_escratch.p, E),
                     "energy forward launch");
 }
 
@@ -416,9 +440,15 @@ void energy_backward_impl(hsim_plan P, int32_t batch, hsim_precision prec, const
         if (gB) hsim::hip_check(hsim::launch_fill_u32(st, (uint32_t *)gB, 0u, 2), "fill launch");
         return;
     }
+    P->prepare_energy();
     const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd, prec == HSIM_FP64_EXACT);
-    double *scr = energy_scratch(P, batch);
     hsim::hip_check(hsim::launch_energy_backward(st, prec == HSIM_FP64_EXACT, a, gE, gS, gJ, gk, gB,
-                                                 scr, 0),
+                                                 P->elayout, (double *)P->d_escratch.p),
                     "energy backward launch");
+}
+
+void energy_prepare_impl(hsim_plan P)
+{
+    if (!P) throw Error(HSIM_E_ARG, "energy_prepare: NULL plan");
+    if (P->n > 0) P->prepare_energy();
 }

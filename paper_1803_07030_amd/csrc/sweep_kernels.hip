@@ -281,6 +281,25 @@ hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, uint32_t v, int64_t n)
     return hipGetLastError();
 }
 
+__global__ void k_put_schedule(double *beta, double *bfield, int S_hist, int first_step,
+                               int n_steps, int k0, int cnt, PutPairs vals)
+{
+    const int j = threadIdx.x;
+    if (j >= cnt) return;
+    const int k = k0 + j, r = k / n_steps, s = k - r * n_steps;
+    const size_t off = (size_t)r * S_hist + first_step + s;
+    beta[off] = vals.v[2 * j];
+    bfield[off] = vals.v[2 * j + 1];
+}
+
+hipError_t launch_put_schedule(hipStream_t st, double *beta, double *bfield, int S_hist,
+                               int first_step, int n_steps, int k0, int cnt, const PutPairs &vals)
+{
+    hipLaunchKernelGGL(k_put_schedule, dim3(1), dim3(kPutPairs), 0, st, beta, bfield, S_hist,
+                       first_step, n_steps, k0, cnt, vals);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ initial state
 template <typename T>
 __global__ void k_init_spins(const RepDesc *reps, int mode, const double *given, uint64_t seed)

@@ -93,3 +93,46 @@ def fluct_estimate(beta, O, dE, dO=None):
     out = torch.empty(2, dtype=torch.float64, device=O.device)
     hsim.hsim_fluct_estimate(O.numel(), beta, O, dE, dO, out)
     return out
+
+
+def spins_planar(spins_site_major, dtype=torch.float64):
+    """Site-major double spins [n_cfg, n, 3] (snapshots, spins_user) as the
+    planar [n_cfg, 3, n] tensor of the energy calls, converted by the
+    library's kernel."""
+    s = spins_site_major
+    if s.dtype != torch.float64 or s.dim() != 3 or s.shape[2] != 3 or s.device.type != "cuda":
+        raise ValueError("spins must be a CUDA float64 tensor [n_cfg, n, 3]")
+    s = s.contiguous()
+    out = torch.empty((s.shape[0], 3, s.shape[1]), dtype=dtype, device=s.device)
+    prec = hsim.FP64_EXACT if dtype == torch.float64 else hsim.FP32
+    hsim.hsim_spins_planar(s.shape[0], s.shape[1], s, prec, out)
+    return out
+
+
+def fluct_gradients(plan, spins, J_bond, k, axis, B, beta, field_dir=None, O=None):
+    """Fluctuation estimate of d<O>/dJ_bond, d<O>/dk and d<O>/dB from
+    configurations spins [n_cfg, 3, n] sampled at inverse temperature beta:
+    d<O>/dtheta = <dO/dtheta> - beta Cov(O, dE/dtheta).  O [n_cfg] float64
+    (device) is an observable that does not depend on the parameters, or None
+    for the energy itself.  One forward (for O = E), one weight kernel and one
+    backward, all in the library.  Returns (gJ, gk, gB, O)."""
+    _check_inputs(spins, J_bond, k, axis, field_dir, plan)
+    prec = hsim.FP64_EXACT if spins.dtype == torch.float64 else hsim.FP32
+    spins, J_bond, k, axis = spins.contiguous(), J_bond.contiguous(), k.contiguous(), axis.contiguous()
+    fd = None if field_dir is None else field_dir.contiguous()
+    n_cfg = spins.shape[0]
+    c = 0.0
+    if O is None:
+        O = torch.empty(n_cfg, dtype=torch.float64, device=spins.device)
+        hsim.hsim_energy_forward(plan.handle, n_cfg, prec, spins, J_bond, k, axis, float(B), fd, O)
+        c = 1.0
+    elif O.dtype != torch.float64 or O.numel() != n_cfg or O.device != spins.device:
+        raise ValueError(f"O must be a float64 tensor of {n_cfg} samples on {spins.device}")
+    O = O.contiguous()
+    w = torch.empty(n_cfg, dtype=torch.float64, device=spins.device)
+    hsim.hsim_fluct_weights(n_cfg, beta, O, c, w)
+    gJ, gk = torch.empty_like(J_bond), torch.empty_like(k)
+    gB = torch.empty(1, dtype=torch.float64, device=spins.device)
+    hsim.hsim_energy_backward(plan.handle, n_cfg, prec, spins, J_bond, k, axis, float(B), fd, w,
+                              None, gJ, gk, gB)
+    return gJ, gk, gB, O

@@ -24,6 +24,7 @@ INIT_GIVEN, INIT_COLD_Z, INIT_RANDOM = 0, 1, 2
 SIGMA_MIN, SIGMA_MAX = 1e-4, 60.0
 THERMAL_FIELDS = ("e", "m_abs", "m2", "m4", "cv", "chi", "u4", "v1", "v2")
 RUN_TRACE_ACCEPTS = 0x1
+RUN_DEBUG_NAN_FIELD, RUN_DEBUG_WAIT_CAP = 0x2, 0x4
 LAYOUT_NAMES = {1: "site", 2: "replica", 3: "block"}
 
 STATUS = {0: "HSIM_OK", -1: "HSIM_E_ARG", -2: "HSIM_E_CSR", -3: "HSIM_E_PARAM",
@@ -75,10 +76,13 @@ _SIGNATURES = {
     "hsim_batch_sigma": [_vp, _vp],
     "hsim_batch_bind_outputs": [_vp, _i32, _vp, _vp],
     "hsim_batch_phase_times": [_vp, _vp, _vp, _vp],
+    "hsim_energy_prepare": [_vp],
     "hsim_energy_forward": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp],
     "hsim_energy_backward": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp,
                              _vp, _vp],
     "hsim_fluct_estimate": [_i64, _dbl, _vp, _vp, _vp, _vp, _vp],
+    "hsim_fluct_weights": [_i64, _dbl, _vp, _dbl, _vp, _vp],
+    "hsim_spins_planar": [_i64, _i64, _vp, _i32, _vp, _vp],
     "hsim_analysis_thermal": [_vp, _i32, _i32, _i32, _i32, _i64, _vp, _i32, _vp, _vp, _vp],
     "hsim_analysis_tau": [_vp, _i32, _i32, _i32, _i32, _i32, _dbl, _vp, _vp, _vp],
     "hsim_analysis_multihist": [_vp, _i32, _i32, _i32, _i32, _i64, _i32, _vp, _vp, _i32, _vp,
@@ -205,11 +209,11 @@ def hsim_batch_init_spins(batch, mode, host_spins=None):
 
 
 def hsim_batch_run(batch, first_step, T, B, recompute_every=100, launch=LAUNCH_AUTO,
-                   trace=None):
+                   trace=None, debug_flags=0):
     T = np.ascontiguousarray(T, dtype=np.float64)
     B = np.ascontiguousarray(np.broadcast_to(B, T.shape), dtype=np.float64)
     n_steps = T.shape[-1]
-    flags = RUN_TRACE_ACCEPTS if trace is not None else 0
+    flags = (RUN_TRACE_ACCEPTS if trace is not None else 0) | debug_flags
     _check(lib().hsim_batch_run(batch, first_step, n_steps, _ptr(T), _ptr(B), recompute_every,
                                 launch, flags, _ptr(trace), _stream()))
 
@@ -261,6 +265,10 @@ def hsim_batch_destroy(batch):
     lib().hsim_batch_destroy(batch)
 
 
+def hsim_energy_prepare(plan):
+    _check(lib().hsim_energy_prepare(plan))
+
+
 def hsim_energy_forward(plan, batch, precision, spins, J_bond, k, axis, B, field_dir, E):
     _check(lib().hsim_energy_forward(plan, batch, precision, _ptr(spins), _ptr(J_bond), _ptr(k),
                                      _ptr(axis), float(B), _ptr(field_dir), _ptr(E), _stream()))
@@ -276,6 +284,15 @@ def hsim_energy_backward(plan, batch, precision, spins, J_bond, k, axis, B, fiel
 def hsim_fluct_estimate(n, beta, O, dE, dO, out):
     _check(lib().hsim_fluct_estimate(n, float(beta), _ptr(O), _ptr(dE), _ptr(dO), _ptr(out),
                                      _stream()))
+
+
+def hsim_fluct_weights(n, beta, O, c, w):
+    _check(lib().hsim_fluct_weights(n, float(beta), _ptr(O), float(c), _ptr(w), _stream()))
+
+
+def hsim_spins_planar(n_cfg, n_sites, spins_in, precision, out):
+    _check(lib().hsim_spins_planar(n_cfg, n_sites, _ptr(spins_in), precision, _ptr(out),
+                                   _stream()))
 
 
 def hsim_version():
@@ -399,12 +416,13 @@ class Batch:
     def init_spins(self, mode, host_spins=None):
         hsim_batch_init_spins(self.handle, mode, host_spins)
 
-    def run(self, T, B, first_step=0, recompute_every=100, launch=LAUNCH_AUTO, trace=None):
+    def run(self, T, B, first_step=0, recompute_every=100, launch=LAUNCH_AUTO, trace=None,
+            debug_flags=0):
         T = np.asarray(T, dtype=np.float64)
         if T.ndim == 1:
             T = np.broadcast_to(T, (self.R, T.size))
         B = np.broadcast_to(np.asarray(B, dtype=np.float64), T.shape)
-        hsim_batch_run(self.handle, first_step, T, B, recompute_every, launch, trace)
+        hsim_batch_run(self.handle, first_step, T, B, recompute_every, launch, trace, debug_flags)
 
     def new_trace(self, n_steps_run):
         words = (max(p.n for p in self.plans) + 31) // 32

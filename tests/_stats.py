@@ -33,3 +33,52 @@ def after_burn_in(h, frac=0.2):
     """Drop the first frac of the MCS axis of a history (S, M, 5) or (M, 5)."""
     M = h.shape[-2]
     return h[..., int(frac * M):, :]
+
+
+def _jackknife(blocks, fn):
+    """Jackknife mean and standard error of fn over leave-one-block-out
+    samples (blocks: list of arrays)."""
+    nb = len(blocks)
+    full = fn(np.concatenate(blocks))
+    loo = np.array([fn(np.concatenate(blocks[:k] + blocks[k + 1:])) for k in range(nb)])
+    se = np.sqrt((nb - 1) / nb * np.sum((loo - loo.mean()) ** 2))
+    return float(full), float(se)
+
+
+OBSERVABLES = ("e", "m_abs", "mz", "chi", "cv", "acc")
+
+
+def chain_stats(h, n_sites, T, n_blocks=20, burn=0.2):
+    """Per-site thermal averages of one chain's history h (M, 5) at
+    temperature T after dropping the first `burn` of its MCS, each with a
+    standard error from n_blocks consecutive blocks (Flyvbjerg and Petersen
+    1989; jackknife over blocks for the fluctuations): <E>/N, <|M|>/N,
+    <M_z>/N, chi = beta (<|M|^2> - <|M|>^2)/N, C_v = beta^2 Var(E)/N and the
+    acceptance <n_acc>/N."""
+    h = np.asarray(h, dtype=np.float64)[int(burn * h.shape[0]):]
+    L = h.shape[0] // n_blocks
+    h = h[: n_blocks * L]
+    N = float(n_sites)
+    beta = 1.0 / T
+    E = h[:, 0]
+    Mabs = np.sqrt((h[:, 1:4] ** 2).sum(axis=1))
+    out = {}
+    for name, x in (("e", E / N), ("m_abs", Mabs / N), ("mz", h[:, 3] / N), ("acc", h[:, 4] / N)):
+        out[name] = block_mean_se(x, n_blocks)
+    bM = [Mabs[k * L:(k + 1) * L] for k in range(n_blocks)]
+    bE = [E[k * L:(k + 1) * L] for k in range(n_blocks)]
+    out["chi"] = _jackknife(bM, lambda m: beta * np.var(m) / N)
+    out["cv"] = _jackknife(bE, lambda e: beta ** 2 * np.var(e) / N)
+    return {k: (float(v[0]), float(v[1])) for k, v in out.items()}
+
+
+def grade(pairs, n_se=3.0, hard=5.0, p=0.0027):
+    """pairs: list of (mean_a, se_a, mean_b, se_b).  Returns the deviations in
+    combined SE, the number above n_se and the 99% binomial bound on that
+    number for a two-sided normal tail p; a set passes when the count is
+    within the bound and no deviation exceeds `hard`."""
+    from scipy import stats
+    z = np.array([abs(a - b) / np.hypot(sa, sb) if np.hypot(sa, sb) > 0 else
+                  (0.0 if a == b else np.inf) for a, sa, b, sb in pairs])
+    bound = int(stats.binom.ppf(0.99, len(z), p))
+    return z, int((z > n_se).sum()), bound

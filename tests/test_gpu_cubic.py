@@ -10,6 +10,7 @@ import torch
 import oracle
 import synth
 from paper_1803_07030_amd import hsim
+from _ties import check_one_mcs
 
 pytestmark = pytest.mark.gpu
 
@@ -74,17 +75,10 @@ def test_fp32_replica_lane_one_mcs_with_cubic_and_norms(R):
     b.run(T[:, None], 0.3, launch=hsim.LAUNCH_PLAIN)
     torch.cuda.synchronize()
     assert b.status() == 0
-    total = 0
+    colour = plan.colouring()
     for r in range(0, R, 3):
-        ref = oracle.run(lat, [T[r]], [0.3], 1, seed=33, replica=r, init="given", spins=start[r],
-                         proposal=oracle.PROPOSAL_F32MAP, trace_accepts=True)
-        got = b.spins_user(r).cpu().numpy()
-        moved = np.any(got != start[r], axis=1)
-        diff = moved != ref["accept"][0].astype(bool)
-        total += int(diff.sum())
-        same = ~diff
-        assert np.max(np.abs(got[same] - ref["spins"][same])) <= 8e-6
-    assert total <= 3
+        check_one_mcs(lat, colour, start[r], T[r], 0.3, 33, r, b.spins_user(r).cpu().numpy(),
+                      spin_tol=8e-6)
 
 
 def test_fp32_layouts_identical_and_starts_with_norms():

@@ -3,9 +3,10 @@
 Double-precision validation mode: the accept/reject sequence and the spins are
 bit-exact and the energies agree to 1e-12 of the energy scale (the two sides
 sum the per-MCS energy changes in different orders).  Single-precision
-production mode: one MCS from a shared state agrees site by site except at
-decisions the oracle flags as near ties (and the neighbours they change);
-different layouts and launch modes give bit-identical spins.
+production mode: one MCS from a shared state agrees site by site, a decision
+differing only within single-precision error of its tie or after a differing
+neighbour of an earlier colour (tests/_ties.py); different layouts and launch
+modes give bit-identical spins.
 """
 import numpy as np
 import pytest
@@ -14,6 +15,7 @@ import torch
 import oracle
 import synth
 from paper_1803_07030_amd import hsim
+from _ties import check_one_mcs
 
 pytestmark = pytest.mark.gpu
 
@@ -182,15 +184,6 @@ def test_fp32_layouts_and_launches_bit_identical(lat_kind):
         assert np.allclose(h[..., 0], out["site"][1][..., 0], rtol=0, atol=1e-9 * lat.n)
 
 
-def _near_tie_sites(lat, spins0, T, Bf, seed, rep, g, tol):
-    """Sites whose single-precision decision may legitimately differ: the
-    oracle's acceptance uniform lies within tol of the acceptance probability,
-    evaluated with the oracle's own fields on the shared start state."""
-    res = oracle.run(lat, [T], [Bf], 1, seed=seed, replica=rep, init="given", spins=spins0,
-                     proposal=oracle.PROPOSAL_F32MAP, trace_accepts=True)
-    return res
-
-
 @pytest.mark.parametrize("layout", [hsim.LAYOUT_SITE, hsim.LAYOUT_REPLICA, hsim.LAYOUT_BLOCK])
 def test_fp32_one_mcs_matches_oracle_site_by_site(layout):
     """One MCS from a shared start state: the single-precision kernels take
@@ -208,20 +201,9 @@ def test_fp32_one_mcs_matches_oracle_site_by_site(layout):
     b.init_spins(hsim.INIT_GIVEN, start.reshape(-1, 3))
     b.run(T[:, None], 0.3)
     torch.cuda.synchronize()
-    total_diff = 0
+    colour = plan.colouring()
     for r in range(R):
-        ref = oracle.run(lat, [T[r]], [0.3], 1, seed=33, replica=r, init="given", spins=start[r],
-                         proposal=oracle.PROPOSAL_F32MAP, trace_accepts=True)
-        got = _fp32_spins(b, r)
-        moved_gpu = np.any(got != start[r], axis=1)
-        moved_ref = ref["accept"][0].astype(bool)
-        diff = moved_gpu != moved_ref
-        total_diff += int(diff.sum())
-        same = ~diff
-        assert np.max(np.abs(got[same] - ref["spins"][same])) <= 2e-6
-    # a decision can flip only within ~1e-6 of a tie: with 16 x 1728
-    # decisions, at most a handful
-    assert total_diff <= 3
+        check_one_mcs(lat, colour, start[r], T[r], 0.3, 33, r, _fp32_spins(b, r), spin_tol=2e-6)
 
 
 def test_fp32_energy_history_consistent():
@@ -282,17 +264,6 @@ def test_energy_and_gradients_match_oracle(dtype):
     assert np.max(np.abs(Jt.grad.cpu().numpy() - gJ_ref)) <= tol * 20 * Bn
     assert np.max(np.abs(kt.grad.cpu().numpy() - gk_ref)) <= tol * 20 * Bn
     assert abs(Bt.grad.item() - gB_ref) <= tol * lat.n * Bn
-
-
-def test_fluct_estimate_formula():
-    from paper_1803_07030_amd.energy import fluct_estimate
-    rng = synth.uniform01(5, 3000, tag=1).reshape(3, 1000)
-    O, dE, dO = (torch.tensor(x, device="cuda") for x in rng)
-    out = fluct_estimate(0.7, O, dE, dO).cpu().numpy()
-    o, d, dd = rng
-    cov = np.mean((o - o.mean()) * (d - d.mean()))
-    assert abs(out[1] - cov) <= 1e-14
-    assert abs(out[0] - (dd.mean() - 0.7 * cov)) <= 1e-14
 
 
 @pytest.mark.parametrize("layout", [hsim.LAYOUT_SITE, hsim.LAYOUT_REPLICA])

@@ -11,6 +11,7 @@ import torch
 import oracle
 import synth
 from paper_1803_07030_amd import hsim
+from _ties import check_one_mcs
 
 pytestmark = pytest.mark.gpu
 
@@ -115,15 +116,10 @@ def test_replica_layout_two_lane_columns():
     b.init_spins(hsim.INIT_GIVEN, start.reshape(-1, 3))
     b.run(T, B, launch=hsim.LAUNCH_PLAIN)
     torch.cuda.synchronize()
-    total = 0
+    colour = plan.colouring()
     for r in (0, 1, 63, 64, 65, 99):
-        ref = oracle.run(lat, [T[r, 0]], [B[r, 0]], 1, seed=5, replica=r, init="given", spins=start[r],
-                         proposal=oracle.PROPOSAL_F32MAP, trace_accepts=True)
-        got = b.spins_user(r).cpu().numpy()
-        diff = np.any(got != start[r], axis=1) != ref["accept"][0].astype(bool)
-        total += int(diff.sum())
-        assert np.max(np.abs(got[~diff] - ref["spins"][~diff])) <= 8e-6
-    assert total <= 3
+        check_one_mcs(lat, colour, start[r], T[r, 0], B[r, 0], 5, r, b.spins_user(r).cpu().numpy(),
+                      spin_tol=8e-6)
 
 
 # ---------------------------------------------- sites of high degree
@@ -185,15 +181,10 @@ def test_fp32_hub_site_layouts_identical_and_match_oracle():
     b.init_spins(hsim.INIT_GIVEN, start.reshape(-1, 3))
     b.run(T, 0.2, launch=hsim.LAUNCH_PLAIN)
     torch.cuda.synchronize()
-    total = 0
+    colour = plan.colouring()
     for r in range(0, R, 9):
-        ref = oracle.run(lat, [T[r, 0]], [0.2], 1, seed=8, replica=r, init="given", spins=start[r],
-                         proposal=oracle.PROPOSAL_F32MAP, trace_accepts=True)
-        got = b.spins_user(r).cpu().numpy()
-        diff = np.any(got != start[r], axis=1) != ref["accept"][0].astype(bool)
-        total += int(diff.sum())
-        assert np.max(np.abs(got[~diff] - ref["spins"][~diff])) <= 8e-6
-    assert total <= 2
+        check_one_mcs(lat, colour, start[r], T[r, 0], 0.2, 8, r, b.spins_user(r).cpu().numpy(),
+                      spin_tol=8e-6)
 
 
 # ---------------------------------------------- lattices without sites
@@ -275,18 +266,12 @@ def test_zero_and_infinite_temperature_replica_layout():
         torch.cuda.synchronize()
         assert b.status() == 0
         h = b.history.cpu().numpy()
-        total = 0
+        colour = plan.colouring()
         for r in range(6):
-            ref = oracle.run(lat, [T[r]], [0.25], 1, seed=3, replica=r, init="given", spins=start[r],
-                             proposal=oracle.PROPOSAL_F32MAP, trace_accepts=True)
-            acc = ref["accept"][0].astype(bool)
             got = b.spins_user(r).cpu().numpy()
-            diff = np.any(got != start[r], axis=1) != acc
-            total += int(diff.sum())
-            assert np.max(np.abs(got[~diff] - ref["spins"][~diff])) <= 8e-6
+            check_one_mcs(lat, colour, start[r], T[r], 0.25, 3, r, got, spin_tol=8e-6)
             if np.isinf(T[r]):
-                assert acc.all() and h[r, 0, 0, 4] == lat.n
-        assert total <= 2
+                assert np.all(np.any(got != start[r], axis=1)) and h[r, 0, 0, 4] == lat.n
 
 
 # ------------------------------------------- planar spin rows (large arrays)
@@ -398,3 +383,51 @@ def test_replica_layout_with_mostly_idle_lanes(R):
     assert np.array_equal(out["rep"][0], out["site"][0])
     assert np.array_equal(out["rep"][1], out["site"][1])
     assert np.array_equal(out["rep"][2], out["site"][2])
+
+
+# ---------------------------------------------- failure paths
+@pytest.mark.parametrize("layout,launch", [(hsim.LAYOUT_REPLICA, hsim.LAUNCH_PLAIN),
+                                           (hsim.LAYOUT_REPLICA, hsim.LAUNCH_PERSISTENT),
+                                           (hsim.LAYOUT_SITE, hsim.LAUNCH_GRAPH),
+                                           (hsim.LAYOUT_BLOCK, hsim.LAUNCH_PLAIN)])
+def test_nan_energy_change_reports_numeric(layout, launch):
+    """A NaN field intensity staged by the debug flag makes every energy change
+    NaN: no move is taken, the device status reads HSIM_E_NUMERIC once (the
+    read clears it), and a normal run afterwards is clean."""
+    lat = synth.sc_periodic(8)
+    prec = hsim.FP64_EXACT if layout == hsim.LAYOUT_BLOCK else hsim.FP32
+    R = 1 if layout == hsim.LAYOUT_BLOCK else 32
+    b = hsim.Batch([hsim.Plan(lat)] * R, seed=1, precision=prec, layout=layout).bind(2, 8)
+    b.init_spins(hsim.INIT_COLD_Z)
+    b.run(np.full((R, 1), 1.0), 0.3, launch=launch, debug_flags=hsim.RUN_DEBUG_NAN_FIELD)
+    torch.cuda.synchronize()
+    assert b.status() == -8                     # HSIM_E_NUMERIC
+    assert b.status() == 0                      # cleared by the read
+    h = b.history.cpu().numpy()
+    assert np.all(h[:, 0, :, 4] == 0)           # nothing accepted
+    assert np.all(b.spins_user(0).cpu().numpy() == np.tile([0.0, 0.0, 1.0], (lat.n, 1)))
+    b.run(np.full((R, 1), 1.0), 0.3, first_step=1, launch=launch)
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    assert np.all(np.isfinite(b.history.cpu().numpy()[:, 1]))
+
+
+def test_persistent_barrier_wait_cap_reports_timeout():
+    """With the debug flag every device barrier wait of the persistent launch
+    gives up after one polling round: the first wait that has to wait
+    releases all later ones, the launch drains, and the device status reads
+    HSIM_E_TIMEOUT; a normal run afterwards is clean."""
+    lat = synth.sc_periodic(32)
+    R = 64
+    b = hsim.Batch([hsim.Plan(lat)] * R, seed=1, precision=hsim.FP32,
+                   layout=hsim.LAYOUT_REPLICA).bind(1, 20)
+    b.init_spins(hsim.INIT_COLD_Z)
+    b.run(np.full((R, 1), 1.0), 0.0, launch=hsim.LAUNCH_PERSISTENT,
+          debug_flags=hsim.RUN_DEBUG_WAIT_CAP)
+    torch.cuda.synchronize()
+    assert b.status() == -7                     # HSIM_E_TIMEOUT
+    assert b.status() == 0
+    b.init_spins(hsim.INIT_COLD_Z)
+    b.run(np.full((R, 1), 1.0), 0.0, launch=hsim.LAUNCH_PERSISTENT)
+    torch.cuda.synchronize()
+    assert b.status() == 0
