@@ -82,3 +82,22 @@ def grade(pairs, n_se=3.0, hard=5.0, p=0.0027):
                   (0.0 if a == b else np.inf) for a, sa, b, sb in pairs])
     bound = int(stats.binom.ppf(0.99, len(z), p))
     return z, int((z > n_se).sum()), bound
+
+
+def chain_means(hists, n_sites, T, burn=0.2):
+    """Per-chain averages of independent chains (histories (M, 5)) after
+    dropping the first `burn` of their MCS: arrays over chains of <E>/N,
+    <|M|>/N, <M_z>/N, chi, C_v and the acceptance (the chain's own
+    fluctuations for chi and C_v)."""
+    out = {k: [] for k in OBSERVABLES}
+    beta, N = 1.0 / T, float(n_sites)
+    for h in hists:
+        h = np.asarray(h, dtype=np.float64)[int(burn * len(h)):]
+        Mabs = np.sqrt((h[:, 1:4] ** 2).sum(axis=1))
+        out["e"].append(h[:, 0].mean() / N)
+        out["m_abs"].append(Mabs.mean() / N)
+        out["mz"].append(h[:, 3].mean() / N)
+        out["chi"].append(beta * Mabs.var() / N)
+        out["cv"].append(beta ** 2 * h[:, 0].var() / N)
+        out["acc"].append(h[:, 4].mean() / N)
+    return {k: np.array(v) for k, v in out.items()}
