@@ -292,6 +292,21 @@ hsim_status hsim_energy_forward(hsim_plan plan, int32_t batch, hsim_precision pr
                                 const void *d_spins, const void *d_J_bond, const void *d_k,
                                 const void *d_axis, double B, const void *d_field_dir,
                                 double *d_E, void *stream);
+/* For callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * hsim_energy_forward with the same arguments and results, whose partial
+ * records live in a fixed array the library keeps on each GPU (8 MiB per
+ * device, held until the process ends) instead of the plan's scratch.  It
+ * calls no allocating routine.  The plan must have been prepared
+ * (hsim_energy_prepare, HSIM_E_STATE otherwise); lattices of more than
+ * 8,388,608 sites are rejected with HSIM_E_ARG.  Batches of any size run in
+ * passes over the array.  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * ordered by the caller. */
+hsim_status hsim_energy_forward_noalloc(hsim_plan plan, int32_t batch, hsim_precision precision,
+                                        const void *d_spins, const void *d_J_bond,
+                                        const void *d_k, const void *d_axis, double B,
+                                        const void *d_field_dir, double *d_E, void *stream);
 /* Vector-Jacobian product of the energies with upstream d_gE [batch]:
  *   d_gS [batch][3][n]   = gE_b (-sum_j J_ij S_j - B n_i - 2 k_i (S_i.e_i) e_i)
  *   d_gJ_bond [n_bonds]  = sum_b gE_b (-S_i.S_j)

@@ -10,6 +10,9 @@
 hsim_plan plan_create_impl(int64_t, const int64_t *, const int32_t *, const double *,
                            const double *, const double *, const double *);
 void energy_prepare_impl(hsim_plan);
+void energy_forward_noalloc_impl(hsim_plan, int32_t, hsim_precision, const void *, const void *,
+                                 const void *, const void *, double, const void *, double *,
+                                 hipStream_t);
 void energy_forward_impl(hsim_plan, int32_t, hsim_precision, const void *, const void *,
                          const void *, const void *, double, const void *, double *, hipStream_t);
 void energy_backward_impl(hsim_plan, int32_t, hsim_precision, const void *, const void *,
@@ -243,6 +246,17 @@ hsim_status hsim_energy_forward(hsim_plan plan, int32_t batch, hsim_precision pr
     return guarded([&] {
         energy_forward_impl(plan, batch, precision, d_spins, d_J_bond, d_k, d_axis, B,
                             d_field_dir, d_E, S(stream));
+    });
+}
+
+hsim_status hsim_energy_forward_noalloc(hsim_plan plan, int32_t batch, hsim_precision precision,
+                                        const void *d_spins, const void *d_J_bond, const void *d_k,
+                                        const void *d_axis, double B, const void *d_field_dir,
+                                        double *d_E, void *stream)
+{
+    return guarded([&] {
+        energy_forward_noalloc_impl(plan, batch, precision, d_spins, d_J_bond, d_k, d_axis, B,
+                                    d_field_dir, d_E, S(stream));
     });
 }
 

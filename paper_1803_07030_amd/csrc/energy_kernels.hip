@@ -21,6 +21,7 @@
 // groups and passes in order.  Batches larger than the plan's pass size run
 // in passes over a fixed scratch (no allocation per call).
 #include <algorithm>
+#include <mutex>
 
 #include "hsim_dev.h"
 
@@ -607,6 +608,36 @@ hipError_t launch_energy_backward(hipStream_t st, bool f64, const EnergyArgs &a,
             if (e != hipSuccess) return e;
         }
     }
+    return hipSuccess;
+}
+
+// ------------------------------------------------ forward without allocation
+// Partial records of hsim_energy_forward_noalloc: a fixed device array that
+// lives as long as the process, one copy per GPU.  In host code the array's
+// name only stands for the symbol; its device address comes from
+// hipGetSymbolAddress, resolved once per device (with that device current)
+// and cached.
+static __device__ __align__(256) double scratch[kStaticEnergyScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_energy_scratch(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
     return hipSuccess;
 }
 

@@ -240,6 +240,11 @@ EnergyLayout energy_layout(int64_t n, int64_t nb, int ell_w, int64_t cap_doubles
                            int min_groups);
 hipError_t launch_energy_forward(hipStream_t st, bool f64, const EnergyArgs &a,
                                  const EnergyLayout &L, double *scratch, double *E);
+// The fixed device array of the allocation-free forward (8 MiB per GPU) and
+// its address on the current device (resolved on first use per device).
+constexpr int64_t kStaticEnergyScratchDoubles = (int64_t)1 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_energy_scratch(double **out);
 hipError_t launch_energy_backward(hipStream_t st, bool f64, const EnergyArgs &a, const double *gE,
                                   void *gS, void *gJ, void *gk, double *gB, const EnergyLayout &L,
                                   double *scratch);

@@ -452,3 +452,34 @@ void energy_prepare_impl(hsim_plan P)
     if (!P) throw Error(HSIM_E_ARG, "energy_prepare: NULL plan");
     if (P->n > 0) P->prepare_energy();
 }
+
+// Forward with its partial records in the library's fixed device array: no
+// allocation.  The plan's energy tables must already be on the device.
+void energy_forward_noalloc_impl(hsim_plan P, int32_t batch, hsim_precision prec, const void *S,
+                                 const void *Jb, const void *k, const void *ax, double B,
+                                 const void *nd, double *E, hipStream_t st)
+{
+    if (!P || batch < 0 || !E || (P->n > 0 && batch > 0 && !S) || (P->nb > 0 && !Jb))
+        throw Error(HSIM_E_ARG, "energy_forward_noalloc: bad argument");
+    if (prec != HSIM_FP32 && prec != HSIM_FP64_EXACT) throw Error(HSIM_E_ARG, "bad precision");
+    if (!std::isfinite(B)) throw Error(HSIM_E_PARAM, "non-finite field");
+    const hsim::EnergyLayout L =
+        hsim::energy_layout(P->n, P->nb, P->e_w, hsim::kStaticEnergyScratchDoubles, true, 0);
+    if (P->n > 0 && L.groups < 1)
+        throw Error(HSIM_E_ARG, "energy_forward_noalloc: the lattice is too large for the fixed "
+                                "scratch (at most " +
+                                    std::to_string(hsim::kStaticEnergyScratchDoubles / 32 * 256) +
+                                    " sites)");
+    if (batch == 0) return;
+    if (P->n == 0) {
+        hsim::hip_check(hsim::launch_fill_u32(st, (uint32_t *)E, 0u, (int64_t)batch * 2), "fill launch");
+        return;
+    }
+    if (!P->energy_ready)
+        throw Error(HSIM_E_STATE, "energy_forward_noalloc: call hsim_energy_prepare on the plan first");
+    double *scr = nullptr;
+    hsim::hip_check(hsim::static_energy_scratch(&scr), "hipGetSymbolAddress");
+    const hsim::EnergyArgs a = energy_args(P, batch, S, Jb, k, ax, B, nd, prec == HSIM_FP64_EXACT);
+    hsim::hip_check(hsim::launch_energy_forward(st, prec == HSIM_FP64_EXACT, a, L, scr, E),
+                    "energy forward launch");
+}

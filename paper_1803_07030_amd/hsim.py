@@ -77,6 +77,7 @@ _SIGNATURES = {
     "hsim_batch_bind_outputs": [_vp, _i32, _vp, _vp],
     "hsim_batch_phase_times": [_vp, _vp, _vp, _vp],
     "hsim_energy_prepare": [_vp],
+    "hsim_energy_forward_noalloc": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp],
     "hsim_energy_forward": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp],
     "hsim_energy_backward": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _dbl, _vp, _vp, _vp, _vp, _vp,
                              _vp, _vp],
@@ -272,6 +273,12 @@ def hsim_energy_prepare(plan):
 def hsim_energy_forward(plan, batch, precision, spins, J_bond, k, axis, B, field_dir, E):
     _check(lib().hsim_energy_forward(plan, batch, precision, _ptr(spins), _ptr(J_bond), _ptr(k),
                                      _ptr(axis), float(B), _ptr(field_dir), _ptr(E), _stream()))
+
+
+def hsim_energy_forward_noalloc(plan, batch, precision, spins, J_bond, k, axis, B, field_dir, E):
+    _check(lib().hsim_energy_forward_noalloc(plan, batch, precision, _ptr(spins), _ptr(J_bond),
+                                             _ptr(k), _ptr(axis), float(B), _ptr(field_dir),
+                                             _ptr(E), _stream()))
 
 
 def hsim_energy_backward(plan, batch, precision, spins, J_bond, k, axis, B, field_dir, gE,
