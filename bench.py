@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--size", type=int, default=L,
                     help="edge of the simple-cubic lattice of the sc64 workload (64: the headline)")
     ap.add_argument("--launch", default="plain", choices=["persistent", "graph", "plain", "auto"])
+    ap.add_argument("--shape", default=None,
+                    help="replica tiles: 'SPW,MASKED' (sites per wave 4/8/32, store policy 0/1)")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the tile shape and store policy before timing (untimed)")
     ap.add_argument("--time-every", type=int, default=10,
                     help="plain launch: time every n-th MCS's colour-phase launches with HIP events")
     ap.add_argument("--plain-mcs", type=int, default=8, help="MCS per replica of the plain-launch sample")
@@ -204,8 +208,13 @@ def main():
             batch.set_policies([pol])
         Tm = T[:, None]
         timed_phases = args.launch == "plain" and args.time_every > 0
-        if args.launch == "auto":
-            batch.autotune(trial_mcs=20)         # untimed: picks the launch AUTO runs use
+        if args.shape:
+            spw, masked = (int(x) for x in args.shape.split(","))
+            batch.set_shape(spw, masked)
+        if args.launch == "auto" or args.tune:
+            batch.init_spins(hsim.INIT_COLD_Z)
+            batch.run(Tm, 0.0, recompute_every=100, launch=hsim.LAUNCH_PLAIN)   # stage T for the trials
+            batch.autotune(trial_mcs=20)         # untimed: picks the shape and the launch AUTO uses
 
         def one_step():
             batch.init_spins(hsim.INIT_COLD_Z)
@@ -263,7 +272,10 @@ def main():
                                f"{args.launch} launch, replica-lane layout"
                                + ("" if args.policy == "random" else f", {args.policy} move"),
                    "sites": lat.n, "replicas": R, "mcs": args.mcs,
-                   "updates_per_step": n_upd_step, "launch": args.launch, "policy": args.policy},
+                   "updates_per_step": n_upd_step, "launch": args.launch, "policy": args.policy,
+                   "sites_per_wave": int(batch.info.sites_per_wave),
+                   "masked_store": int(batch.info.masked_store),
+                   "tuned": bool(args.launch == "auto" or args.tune)},
         "acceptance": acc,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

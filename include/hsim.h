@@ -168,8 +168,21 @@ typedef struct {
     int64_t total_sites;      /* sum of lattice sizes over replicas */
     int32_t lds_resident;     /* BLOCK layout: spins held in LDS */
     int32_t reserved;
+    /* REPLICA layout: sites per wave of a tile (4, 8 or 32) and the store
+     * policy (0: every live lane writes its row back, 1: accepted moves
+     * only); the launch mode and persistent grid AUTO uses (-1 / 0: not
+     * tuned). */
+    int32_t sites_per_wave, masked_store, tuned_launch, persistent_grid;
 } hsim_batch_info_t;
 hsim_status hsim_batch_info(hsim_batch b, hsim_batch_info_t *out);
+
+/* The replica layout's tile shape and store policy, the knobs hsim_autotune
+ * chooses, set by hand: sites_per_wave 4, 8 or 32 (HSIM_E_ARG otherwise),
+ * masked_store 0 or 1.  Neither changes any spin: every site's update is
+ * the same computation; the history's sums are grouped by tiles, so their
+ * last bits may differ.  HSIM_E_UNSUPPORTED outside the replica layout.  May
+ * be called while bound (the workspace covers every shape). */
+hsim_status hsim_batch_set_shape(hsim_batch b, int32_t sites_per_wave, int32_t masked_store);
 
 /* Device bytes the caller must provide for a history of n_steps steps of
  * mcs_per_step MCS.  History layout: double [n_rep][n_steps][mcs_per_step][5]
@@ -257,18 +270,22 @@ hsim_status hsim_batch_spins_to_user(hsim_batch b, int32_t rep, double *d_out, v
 /* Device status word after the stream has been synchronised: 0, or
  * HSIM_E_NUMERIC / HSIM_E_TIMEOUT.  Clears it. */
 hsim_status hsim_batch_status(hsim_batch b, int32_t *device_status_out);
-/* Time the launch modes available for this batch on one step of trial_mcs
- * MCS at each replica's first bound temperature and field (plain and graph;
- * in the replica layout also persistent grids of 1, 2, 4 and 8 blocks per
- * CU) and keep the fastest for HSIM_LAUNCH_AUTO (another mode than plain
- * only when it beats plain launches by more than 2%).  The trials use scratch
+/* Time the choices available for this batch on one step of trial_mcs MCS
+ * at each replica's first bound temperature and field and keep the fastest
+ * for HSIM_LAUNCH_AUTO.  In the replica layout first the tile shape (4, 8 or
+ * 32 sites per wave) and the store policy with plain launches, then, for
+ * that shape, graph launches and persistent grids of 1, 2, 4 and 8 blocks
+ * per CU; in the site layout plain and graph launches.  A choice replaces
+ * the current one only when it is more than 2% faster.  The trials use scratch
  * buffers the call allocates and frees; afterwards the batch's spins,
  * binding, adaptive widths, optional outputs, phase timing and device status
  * are as before the call.  Synchronises the stream.  The choice never
- * changes spin trajectories.  The block layout has nothing to choose (the
- * call returns at once).  With cache_path (NULL: no file) a choice recorded
- * for the same GPU, layout, replica count, precision and lattice sizes is
- * reused; a new choice is appended to the file. */
+ * changes spin trajectories (see hsim_batch_set_shape for the history).
+ * The block layout has nothing to choose (the call returns at once).  With
+ * cache_path (NULL: no file) a choice recorded for the same GPU, ROCm
+ * runtime and driver versions, layout, replica count, precision, update
+ * policies and lattice (a hash of its rows, constants, axes and field
+ * directions) is reused; a new choice is appended to the file. */
 hsim_status hsim_autotune(hsim_batch b, const char *cache_path, int32_t trial_mcs,
                           void *stream);
 void hsim_batch_destroy(hsim_batch b);

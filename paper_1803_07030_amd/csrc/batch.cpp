@@ -73,6 +73,85 @@ hsim_batch_s::~hsim_batch_s()
     if (h_stage) (void)hipHostFree(h_stage);
 }
 
+namespace {
+
+// Replica layout: blocks of the largest colour phase for tiles of
+// kRepWaves x spw sites (times the lane columns of a tile).
+int64_t rep_phase_blocks(hsim_batch b, int spw)
+{
+    hsim_plan P = b->plans[0];
+    const int cols = b->Rp % 64 == 0 ? b->Rp / 64 : 1;   // lane columns per tile
+    int64_t mx = 0;
+    for (int c = 0; c < P->ncol; ++c) {
+        const int64_t sz = P->cls_off[c + 1] - P->cls_off[c];
+        mx = std::max<int64_t>(mx, (sz + hsim::kRepWaves * spw - 1) / (hsim::kRepWaves * spw));
+    }
+    return mx * cols;
+}
+
+// Tiles of kRepWaves x spw sites per colour class and the record window that
+// goes with them: records of up to 64 MCS, about 256 MiB at most (2 at least).
+struct RepTiling {
+    int32_t tile_off[hsim::kMaxColours + 1];
+    int32_t ntiles, rec_win;
+};
+RepTiling rep_tiling(hsim_batch b, int spw)
+{
+    hsim_plan P = b->plans[0];
+    RepTiling t{};
+    const int tile = hsim::kRepWaves * spw;
+    t.tile_off[0] = 0;
+    for (int c = 0; c < P->ncol; ++c) {
+        const int sz = P->cls_off[c + 1] - P->cls_off[c];
+        t.tile_off[c + 1] = t.tile_off[c] + (sz + tile - 1) / tile;
+    }
+    t.ntiles = t.tile_off[P->ncol];
+    const size_t per_mcs = (size_t)t.ntiles * hsim::kRecFields * b->Rp * 8;
+    t.rec_win = (int32_t)std::max<size_t>(2, std::min<size_t>(64, (256u << 20) / std::max<size_t>(per_mcs, 1)));
+    return t;
+}
+
+}  // namespace
+
+// The replica layout's tile shape; the workspace is sized for every shape
+// the autotuner may pick, so a bound batch can switch.
+void set_rep_tiles(hsim_batch b, int spw)
+{
+    const RepTiling t = rep_tiling(b, spw);
+    b->la.spw = spw;
+    for (int c = 0; c <= hsim::kMaxColours; ++c) b->la.tile_off[c] = c <= b->plans[0]->ncol ? t.tile_off[c] : 0;
+    b->rep_ntiles = t.ntiles;
+    b->rec_win = t.rec_win;
+    b->drop_graph();
+}
+
+void batch_set_shape_impl(hsim_batch b, int32_t spw, int32_t masked)
+{
+    if (!b) throw Error(HSIM_E_ARG, "set_shape: NULL batch");
+    if (b->layout != HSIM_LAYOUT_REPLICA) throw Error(HSIM_E_UNSUPPORTED, "set_shape: replica layout only");
+    bool ok = false;
+    for (int c : hsim::kRepTileShapes) ok |= c == spw;
+    if (!ok || (masked != 0 && masked != 1)) throw Error(HSIM_E_ARG, "set_shape: bad shape");
+    if (spw != b->la.spw) set_rep_tiles(b, spw);
+    if (masked != b->la.masked_store) {
+        b->la.masked_store = masked;
+        b->drop_graph();
+    }
+}
+
+size_t rep_rec_bytes_max(hsim_batch b)
+{
+    size_t mx = 0;
+    for (int spw : hsim::kRepTileShapes) {
+        const RepTiling t = rep_tiling(b, spw);
+        const size_t bytes = ((size_t)t.rec_win * ((size_t)t.ntiles * hsim::kRecFields +
+                                                   (size_t)hsim::kChunks * 6 + 6) +
+                              (size_t)hsim::kChunks) * b->Rp * 8;
+        mx = std::max(mx, bytes);
+    }
+    return mx;
+}
+
 hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
                              const uint32_t *rep_id, hsim_precision prec, hsim_layout layout)
 {
@@ -123,7 +202,6 @@ hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
         }
         b->layout = lay;
         if (lay == HSIM_LAYOUT_REPLICA) {
-            hsim_plan P = plans[0];
             b->Rp = R > 32 ? (int32_t)((R + 63) / 64 * 64) : 32;
             // sites per wave of a tile: the full kRepSitesPerWave while the
             // largest colour phase has at least 2 blocks per CU; else 8, or 4
@@ -131,35 +209,17 @@ hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
             // lattices fill the GPU.  Measured on SC L^3 x 64 replicas (us per
             // phase): L = 56: 45.8 (32), 54.8 (16); L = 48: 37.4 (32), 34.0
             // (16), 28.1 (8); L = 32: 17.6 (16), 12.6 (8), 11.9 (4); 16 sites
-            // per wave was never the best and is not used.
+            // per wave was never the best and is not used.  hsim_autotune
+            // may pick another of these shapes.
             const int cus = device_cus() > 0 ? device_cus() : 256;
-            const int cols = b->Rp % 64 == 0 ? b->Rp / 64 : 1;   // lane columns per tile
-            auto phase_blocks = [&](int spw) {
-                int64_t mx = 0;
-                for (int c = 0; c < P->ncol; ++c) {
-                    const int64_t sz = P->cls_off[c + 1] - P->cls_off[c];
-                    mx = std::max<int64_t>(mx, (sz + hsim::kRepWaves * spw - 1) / (hsim::kRepWaves * spw));
-                }
-                return mx * cols;
-            };
             int spw = hsim::kRepSitesPerWave;
-            if (phase_blocks(spw) < 2 * (int64_t)cus)
+            if (rep_phase_blocks(b, spw) < 2 * (int64_t)cus)
                 for (int cand : {8, 4})
                     if (cand < spw && cand % hsim::kRepSitesPerStep == 0) {
                         spw = cand;
-                        if (phase_blocks(cand) >= 4 * (int64_t)cus) break;
+                        if (rep_phase_blocks(b, cand) >= 4 * (int64_t)cus) break;
                     }
-            b->la.spw = spw;
-            const int tile = hsim::kRepWaves * spw;
-            b->la.tile_off[0] = 0;
-            for (int c = 0; c < P->ncol; ++c) {
-                const int sz = P->cls_off[c + 1] - P->cls_off[c];
-                b->la.tile_off[c + 1] = b->la.tile_off[c] + (sz + tile - 1) / tile;
-            }
-            b->rep_ntiles = b->la.tile_off[P->ncol];
-            // records of up to 64 MCS, about 256 MiB at most (2 at least)
-            const size_t per_mcs = (size_t)b->rep_ntiles * hsim::kRecFields * b->Rp * 8;
-            b->rec_win = (int32_t)std::max<size_t>(2, std::min<size_t>(64, (256u << 20) / std::max<size_t>(per_mcs, 1)));
+            set_rep_tiles(b, spw);
         } else {
             b->spin_off.resize(R);
             int64_t off = 0;
@@ -211,7 +271,7 @@ void batch_sizes_impl(hsim_batch b, int32_t S, int32_t M, size_t *ws, size_t *sp
     size_t part = 0;
     if (b->layout == HSIM_LAYOUT_SITE) part = b->tiles.size() * hsim::kRecSite * 8;
     else if (b->layout == HSIM_LAYOUT_REPLICA)
-        part = b->rep_rec_bytes() +
+        part = rep_rec_bytes_max(b) +
                (size_t)hsim::kMaxPersistentBlocks * 128;   // barrier flags, one 128-byte line each
     off += align_up(std::max<size_t>(part, 8));
     if (ws) *ws = off;
@@ -744,7 +804,7 @@ bool run_persistent(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st, uint3
     grid = std::min(grid, max_phase_tiles * groups);
     grid = std::min(grid, hsim::kMaxPersistentBlocks);
     // barrier flags follow the record window
-    auto *flags = (uint32_t *)(b->ws + b->off_part + b->rep_rec_bytes());
+    auto *flags = (uint32_t *)(b->ws + b->off_part + rep_rec_bytes_max(b));
     hip_check(hsim::launch_rep_persistent(st, b->kmode, b->fmode, b->la, b->rep_ntiles, grid, ra,
                                           flags, spin_cap),
               "persistent launch");
@@ -916,15 +976,25 @@ namespace {
 
 std::string tune_key(hsim_batch b)
 {
-    int dev = 0;
+    int dev = 0, rt = 0, drv = 0;
     hipDeviceProp_t prop{};
     (void)hipGetDevice(&dev);
     (void)hipGetDeviceProperties(&prop, dev);
+    (void)hipRuntimeGetVersion(&rt);
+    (void)hipDriverGetVersion(&drv);
     std::ostringstream k;
-    k << prop.gcnArchName << ":" << prop.multiProcessorCount << ":L" << b->layout << ":R" << b->R
-      << ":P" << (b->f64 ? 64 : 32);
+    k << prop.gcnArchName << ":" << prop.multiProcessorCount << ":rt" << rt << ":drv" << drv
+      << ":L" << b->layout << ":R" << b->R << ":P" << (b->f64 ? 64 : 32) << ":pol";
+    const unsigned char *pb = (const unsigned char *)&b->pol;
+    uint64_t ph = 1469598103934665603ull;
+    for (size_t q = 0; q < sizeof b->pol; ++q) {
+        ph ^= pb[q];
+        ph *= 1099511628211ull;
+    }
+    k << std::hex << ph << std::dec;
     for (auto p : b->plans) {
-        k << ":" << p->n << "/" << p->nnz << "/" << p->ncol;
+        k << ":" << std::hex << p->hash << std::dec << "/" << (p->kcd.empty() ? 0 : 1)
+          << (p->mud.empty() ? 0 : 1) << (p->type.empty() ? 0 : 1);
         if (b->layout == HSIM_LAYOUT_REPLICA) break;
     }
     return k.str();
@@ -941,14 +1011,22 @@ void autotune_impl(hsim_batch b, const char *cache_path, int32_t trial_mcs, hipS
     const std::string key = tune_key(b);
     if (cache_path) {
         std::ifstream in(cache_path);
-        std::string k;
-        int mode, grid;
-        while (in >> k >> mode >> grid)
-            if (k == key) {
-                b->tuned_launch = mode;
-                b->persistent_grid = grid;
-                return;
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k;
+            int mode = 0, grid = 0, spw = 0, masked = 0;
+            if (!(ls >> k >> mode >> grid >> spw >> masked) || k != key) continue;
+            bool ok_spw = false;
+            for (int c : hsim::kRepTileShapes) ok_spw |= c == spw;
+            if (b->layout == HSIM_LAYOUT_REPLICA && ok_spw) {
+                set_rep_tiles(b, spw);
+                b->la.masked_store = masked ? 1 : 0;
             }
+            b->tuned_launch = mode;
+            b->persistent_grid = grid;
+            return;
+        }
     }
     // scratch binding: one step of trial_mcs MCS
     size_t wsb = 0, spb = 0, hb = 0;
@@ -982,53 +1060,78 @@ void autotune_impl(hsim_batch b, const char *cache_path, int32_t trial_mcs, hipS
         T[r] = (be > 0.0 && std::isfinite(be)) ? 1.0 / be : 1.0;
         B[r] = bf0.empty() ? 0.0 : bf0[(size_t)r * S0];
     }
-    struct Cand { int mode, grid; };
-    std::vector<Cand> cands = {{HSIM_LAUNCH_PLAIN, 0}, {HSIM_LAUNCH_GRAPH, 0}};
-    if (b->layout == HSIM_LAYOUT_REPLICA) {
-        const int bpc = hsim::rep_persistent_blocks_per_cu(b->kmode, b->fmode, b->Rp % 64 == 0 ? 64 : 32, b->la.ell_w);
-        const int cus = device_cus();
-        for (int f : {1, 2, 4, 8})
-            if (bpc >= f && cus > 0) cands.push_back({HSIM_LAUNCH_PERSISTENT, f * cus});
-    }
+    // replica layout: first the tile shape and store policy with plain
+    // launches, then the launch mode for the chosen shape
+    struct Cand { int mode, grid, spw, masked; };
+    const int spw0 = b->la.spw, masked0 = b->la.masked_store;
+    std::vector<Cand> shapes = {{HSIM_LAUNCH_PLAIN, 0, spw0, masked0}};
+    if (b->layout == HSIM_LAYOUT_REPLICA)
+        for (int spw : hsim::kRepTileShapes)
+            for (int m : {0, 1})
+                if (spw != spw0 || m != masked0) shapes.push_back({HSIM_LAUNCH_PLAIN, 0, spw, m});
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
-    float best = 1e30f;
-    Cand win = cands[0];
+    Cand win = shapes[0];
     std::string err;
     // recompute period of the trials: half the trial, so that a graph launch
     // is captured once and replayed twice, as in a run of many MCS
     const int32_t p_trial = std::max(1, trial_mcs / 2);
-    float plain_ms = 1e30f;
+    auto time_cand = [&](const Cand &c) -> float {
+        if (b->layout == HSIM_LAYOUT_REPLICA && (c.spw != b->la.spw)) set_rep_tiles(b, c.spw);
+        b->la.masked_store = c.masked;
+        b->persistent_grid = c.grid;
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            hip_check(hipMemcpyAsync(b->spins, saved.p, spb, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
+            hip_check(hipEventRecord(e0, st), "hipEventRecord");
+            batch_run_impl(b, 0, 1, T.data(), B.data(), p_trial, (hsim_launch)c.mode, 0, nullptr, st);
+            hip_check(hipEventRecord(e1, st), "hipEventRecord");
+            hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.0f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            ms_best = std::min(ms_best, ms);
+        }
+        if (batch_status_impl(b) != 0) return 1e30f;   // a timed-out barrier disqualifies
+        return ms_best;
+    };
     try {
         batch_bind_impl(b, 1, trial_mcs, ws.p, b->spins, hist.p);
-        for (const Cand &c : cands) {
-            b->persistent_grid = c.grid;
-            float ms_best = 1e30f;
-            for (int rep = 0; rep < 3; ++rep) {
-                hip_check(hipMemcpyAsync(b->spins, saved.p, spb, hipMemcpyDeviceToDevice, st), "hipMemcpyAsync");
-                hip_check(hipEventRecord(e0, st), "hipEventRecord");
-                batch_run_impl(b, 0, 1, T.data(), B.data(), p_trial, (hsim_launch)c.mode, 0, nullptr, st);
-                hip_check(hipEventRecord(e1, st), "hipEventRecord");
-                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
-                float ms = 0.0f;
-                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-                ms_best = std::min(ms_best, ms);
+        // another choice must beat the current one by more than timing noise
+        float best = time_cand(shapes[0]);
+        for (size_t q = 1; q < shapes.size(); ++q) {
+            const float ms = time_cand(shapes[q]);
+            if (ms < 0.98f * best) {
+                best = ms;
+                win = shapes[q];
             }
-            if (batch_status_impl(b) != 0) continue;   // a timed-out barrier disqualifies
-            if (c.mode == HSIM_LAUNCH_PLAIN) plain_ms = ms_best;
-            if (ms_best < best) {
-                best = ms_best;
+        }
+        std::vector<Cand> modes = {{HSIM_LAUNCH_GRAPH, 0, win.spw, win.masked}};
+        if (b->layout == HSIM_LAYOUT_REPLICA) {
+            const int bpc = hsim::rep_persistent_blocks_per_cu(b->kmode, b->fmode, b->Rp % 64 == 0 ? 64 : 32, b->la.ell_w);
+            const int cus = device_cus();
+            for (int f : {1, 2, 4, 8})
+                if (bpc >= f && cus > 0) modes.push_back({HSIM_LAUNCH_PERSISTENT, f * cus, win.spw, win.masked});
+        }
+        const float plain_ms = best;
+        for (const Cand &c : modes) {
+            const float ms = time_cand(c);
+            if (ms < best && ms < 0.98f * plain_ms) {
+                best = ms;
                 win = c;
             }
         }
-        // another mode must beat plain launches by more than timing noise
-        if (win.mode != HSIM_LAUNCH_PLAIN && best > 0.98f * plain_ms) win = cands[0];
     } catch (const std::exception &e) {
         err = e.what();
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // the chosen tile shape and store policy (the original ones after an error)
+    if (b->layout == HSIM_LAYOUT_REPLICA) {
+        const int spw = err.empty() ? win.spw : spw0, masked = err.empty() ? win.masked : masked0;
+        if (spw != b->la.spw) set_rep_tiles(b, spw);
+        b->la.masked_store = masked;
+    }
     // restore spins, the caller's binding, widths, outputs and timing
     b->type_mag = tm0;
     b->snapshots = snap0;
@@ -1045,7 +1148,7 @@ void autotune_impl(hsim_batch b, const char *cache_path, int32_t trial_mcs, hipS
     b->persistent_grid = win.grid;
     if (cache_path) {
         std::ofstream out(cache_path, std::ios::app);
-        out << key << " " << win.mode << " " << win.grid << "\n";
+        out << key << " " << win.mode << " " << win.grid << " " << win.spw << " " << win.masked << "\n";
     }
 }
 

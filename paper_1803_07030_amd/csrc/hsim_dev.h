@@ -28,6 +28,8 @@ static_assert(kRepSitesPerWave % kRepSitesPerStep == 0 && kRepSitesPerWave % 4 =
               "sites per wave must be a multiple of the sites per step and of 4");
 constexpr int kMaxPersistentBlocks = 4096;   // barrier flags reserved in the workspace
 constexpr int kRepTile = kRepWaves * kRepSitesPerWave;   // sites per replica-lane tile (at most)
+// tile shapes (sites per wave) the replica layout may use
+constexpr int kRepTileShapes[3] = {4, 8, kRepSitesPerWave};
 constexpr int kRecSite = 8;         // doubles per site-lane partial record
 constexpr int kRecFields = 7;       // dE, Mx, My, Mz, n_acc, E_full, adaptive accepts
 constexpr int kChunks = 64;         // replica layout: chunks of the per-MCS record sum
@@ -135,6 +137,7 @@ struct RepLaneArgs {
     int32_t n, Rp, R;
     int32_t ss;                 // site stride (floats): Rp or 3*Rp
     int32_t spw;                // sites per wave of a tile: a multiple of 4, at most kRepSitesPerWave
+    int32_t masked_store;       // 1: only accepted moves are stored; 0: every live lane writes its row
     int32_t ncol, ell_w;        // ell_w: padded row width (6 or 8), 0 = CSR walk
     int32_t cls_off[kMaxColours + 1];
     int32_t tile_off[kMaxColours + 1];   // first tile of each colour

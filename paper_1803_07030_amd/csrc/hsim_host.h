@@ -62,6 +62,7 @@ struct DevBuf {
 
 struct hsim_plan_s {
     int64_t n = 0, nnz = 0, nb = 0;
+    uint64_t hash = 0;                    // of the lattice as given (autotuner cache key)
     int32_t ncol = 0, maxdeg = 0;
     std::vector<int32_t> colour;          // user order
     std::vector<int32_t> perm;            // internal -> user

@@ -108,6 +108,24 @@ hsim_plan plan_create_impl(int64_t n, const int64_t *rp, const int32_t *col, con
     validate(n, rp, col, J, k, axis, fd);
     auto *P = new hsim_plan_s();
     try {
+        // FNV-1a over the lattice as given (the autotuner's cache key)
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&h](const void *p, size_t bytes) {
+            const unsigned char *c = (const unsigned char *)p;
+            for (size_t q = 0; q < bytes; ++q) {
+                h ^= c[q];
+                h *= 1099511628211ull;
+            }
+        };
+        mix(&n, sizeof n);
+        mix(rp, (size_t)(n + 1) * sizeof(int64_t));
+        mix(col, (size_t)rp[n] * sizeof(int32_t));
+        mix(J, (size_t)rp[n] * sizeof(double));
+        const double none = 0.0;
+        mix(k ? (const void *)k : &none, k ? (size_t)n * 8 : 8);
+        mix(axis ? (const void *)axis : &none, axis ? (size_t)n * 24 : 8);
+        mix(fd ? (const void *)fd : &none, fd ? (size_t)n * 24 : 8);
+        P->hash = h;
         P->n = n;
         P->nnz = rp[n];
         P->nb = P->nnz / 2;

@@ -277,8 +277,10 @@ __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const Spi
         if (live && dE != dE) atomicOr(&ra.ctl->status, 1u);
         const int32_t oi = i * a.ss * 4;
         // every live lane stores (the old value when rejected): whole rows
-        // reach memory faster than rows with holes, though more bytes
-        if (live) {
+        // reach memory faster than rows with holes while the spin set stays
+        // in the last-level cache; masked_store keeps the accepted moves
+        // only (fewer bytes once the rows stream from HBM).  Same values.
+        if (live && (ok || !a.masked_store)) {
             bstore(sp3.x, lane_b, oi, ok ? t.x : sx[u]);
             bstore(sp3.y, lane_b, oi, ok ? t.y : sy[u]);
             bstore(sp3.z, lane_b, oi, ok ? t.z : sz[u]);

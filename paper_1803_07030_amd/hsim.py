@@ -48,7 +48,9 @@ class PlanInfo(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("n_rep", ctypes.c_int32),
                 ("n_phases", ctypes.c_int32), ("total_sites", ctypes.c_int64),
-                ("lds_resident", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lds_resident", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sites_per_wave", ctypes.c_int32), ("masked_store", ctypes.c_int32),
+                ("tuned_launch", ctypes.c_int32), ("persistent_grid", ctypes.c_int32)]
 
 
 _lib = None
@@ -62,6 +64,7 @@ _SIGNATURES = {
     "hsim_plan_bonds": [_vp, _vp, _vp],
     "hsim_batch_create": [_vp, _i32, _vp, _u64, _vp, _i32, _i32],
     "hsim_batch_info": [_vp, _vp],
+    "hsim_batch_set_shape": [_vp, _i32, _i32],
     "hsim_batch_sizes": [_vp, _i32, _i32, _vp, _vp, _vp],
     "hsim_batch_bind": [_vp, _i32, _i32, _vp, _vp, _vp],
     "hsim_batch_init_spins": [_vp, _i32, _vp, _vp],
@@ -191,6 +194,10 @@ def hsim_batch_info(batch):
     info = BatchInfo()
     _check(lib().hsim_batch_info(batch, ctypes.byref(info)))
     return info
+
+
+def hsim_batch_set_shape(batch, sites_per_wave, masked_store):
+    _check(lib().hsim_batch_set_shape(batch, sites_per_wave, masked_store))
 
 
 def hsim_batch_sizes(batch, n_steps, mcs):
@@ -447,6 +454,12 @@ class Batch:
 
     def autotune(self, cache_path=None, trial_mcs=20):
         hsim_autotune(self.handle, cache_path, trial_mcs)
+        self.info = hsim_batch_info(self.handle)
+
+    def set_shape(self, sites_per_wave, masked_store=0):
+        """Replica layout: tile shape and store policy (the tuner's knobs)."""
+        hsim_batch_set_shape(self.handle, sites_per_wave, masked_store)
+        self.info = hsim_batch_info(self.handle)
 
     def set_policies(self, policies, sigma_min=SIGMA_MIN, sigma_max=SIGMA_MAX):
         """policies: list of (POLICY_*, param) per site type; [] for the
