@@ -246,6 +246,14 @@ hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
                 }
                 b->tile_off[C] = (int32_t)b->tiles.size();
                 if (b->tiles.size() > (size_t)INT32_MAX / 2) throw Error(HSIM_E_UNSUPPORTED, "too many tiles");
+                // trailing colour classes beyond the first two with fewer than
+                // two tiles per CU run inside the per-replica finish launch
+                // instead of a launch each (the extra colours of odd-size
+                // films: a few tiles per film, latency-bound as phases)
+                const int cus = device_cus() > 0 ? device_cus() : 256;
+                b->c_tail = C;
+                while (b->c_tail > 2 && b->tile_off[b->c_tail] - b->tile_off[b->c_tail - 1] < 2 * cus)
+                    --b->c_tail;
             } else {
                 b->lds = fits_lds;
                 b->lds_bytes = (size_t)(3 * pad64(max_n)) * elem;
@@ -649,15 +657,18 @@ void enqueue_site_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F e
                                               (int)b->tiles.size(), t, ra),
                       "efull launch");
         const bool timed = b->time_every > 0 && t % b->time_every == 0;
-        for (int c = 0; c < b->ncol_max; ++c) {
+        for (int c = 0; c < b->c_tail; ++c) {
             PhaseTimer pt(b, st, timed, c);
             hip_check(hsim::launch_site_phase(st, b->f64, b->kmode, b->fmode, ra.trace != nullptr,
                                               b->ellw, reps, tiles, b->tile_off[c],
                                               b->tile_off[c + 1] - b->tile_off[c], t, ra),
                       "phase launch");
         }
-        hip_check(hsim::launch_site_reduce(st, (const int32_t *)b->d_rep_tiles.p, b->ncol_max, t, ra),
-                  "reduce launch");
+        // trailing small colours and the per-MCS history
+        hip_check(hsim::launch_site_finish(st, b->f64, b->kmode, b->fmode, ra.trace != nullptr, b->ellw,
+                                           reps, (const int32_t *)b->d_rep_tiles.p, b->ncol_max,
+                                           b->c_tail, t, ra),
+                  "finish launch");
         enqueue_outputs(b, ra, t, gb, dev_check, st);
     }
     if (count > 0) hip_check(hsim::launch_ctl_advance(st, ra.ctl, (uint32_t)count), "control launch");

@@ -9,6 +9,7 @@ namespace hsim {
 
 constexpr int kMaxColours = 32;     // colour classes per lattice
 constexpr int kSiteBlock = 256;     // threads per block of the site-lane kernels
+constexpr int kFinThreads = 512;    // threads per block of the site-lane finish launch
 #ifndef HSIM_REP_WAVES
 #define HSIM_REP_WAVES 4
 #endif
@@ -180,8 +181,12 @@ hipError_t launch_site_phase(hipStream_t st, bool f64, int kmode, int fmode, boo
                              int t_off, const RunArgs &ra);
 hipError_t launch_site_efull(hipStream_t st, bool f64, int kmode, int fmode, const RepDesc *reps,
                              const Tile *tiles, int ntiles, int t_off, const RunArgs &ra);
-hipError_t launch_site_reduce(hipStream_t st, const int32_t *rep_tiles, int ncol_max, int t_off,
-                              const RunArgs &ra);
+// Colour classes c_tail .. ncol_max-1 (one block per replica) plus the
+// per-MCS history of every replica (the same results as a phase launch per
+// class).
+hipError_t launch_site_finish(hipStream_t st, bool f64, int kmode, int fmode, bool trace, int ellw,
+                              const RepDesc *reps, const int32_t *rep_tiles, int ncol_max, int c_tail,
+                              int t_off, const RunArgs &ra);
 hipError_t launch_ctl_advance(hipStream_t st, Ctl *ctl, uint32_t n);
 hipError_t launch_block_sweep(hipStream_t st, bool f64, int kmode, int fmode, bool trace,
                               int ellw, bool lds, int threads, size_t lds_bytes, const RepDesc *reps,

@@ -135,6 +135,7 @@ struct hsim_batch_s {
     std::vector<hsim::Tile> tiles;
     std::vector<int32_t> rep_tiles;   // [R][ncol_max][2]
     std::vector<int32_t> tile_off;    // ncol_max+1
+    int32_t c_tail = 0;               // colours >= c_tail run in the per-replica finish launch
     std::vector<int64_t> spin_off;    // elements, per replica
     int64_t spin_elems = 0;
     // replica layout

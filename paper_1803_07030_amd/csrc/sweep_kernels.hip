@@ -419,42 +419,6 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_efull(const RepDesc *__rest
     if (threadIdx.x == 0) ra.partials[(size_t)tl * kRecSite + 5] = e[0];
 }
 
-// Per-MCS history: one wave per replica (four per block); lanes stride the
-// replica's tiles colour by colour in table order, then a wave butterfly.
-// rep_tiles: [R][ncol_max][2] global tile ranges per colour.
-__global__ __launch_bounds__(256) void k_site_reduce(const int32_t *__restrict__ rep_tiles,
-                                                     int ncol_max, int t_off, RunArgs ra)
-{
-    const uint32_t g = ra.ctl->g + (uint32_t)t_off;
-    const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
-    const bool rec_due = recompute_due(m, ra.P);
-    const int lane = threadIdx.x & 63;
-    const int r = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    if (r >= ra.R) return;
-    double v[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int c = 0; c < ncol_max; ++c) {
-        const int tb = rep_tiles[(r * ncol_max + c) * 2], te = rep_tiles[(r * ncol_max + c) * 2 + 1];
-        for (int tt = tb + lane; tt < te; tt += 64) {
-            const double *rec = ra.partials + (size_t)tt * kRecSite;
-#pragma unroll
-            for (int q = 0; q < 7; ++q) v[q] += rec[q];
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < 7; ++q) v[q] = wave_sum(v[q]);
-    if (lane == 0 && ra.pol.adaptive) adapt_sigma(ra, r, v[6]);
-    if (lane == 0) {
-        const double E = (rec_due ? v[5] : ra.ecarry[r]) + v[0];
-        ra.ecarry[r] = E;
-        double *h = ra.history + (((size_t)r * ra.S_hist + s_abs) * ra.M + m) * 5;
-        h[0] = E;
-        h[1] = v[1];
-        h[2] = v[2];
-        h[3] = v[3];
-        h[4] = v[4];
-    }
-}
-
 __global__ void k_ctl_advance(Ctl *ctl, uint32_t n)
 {
     if (threadIdx.x == 0) ctl->g += n;
@@ -513,11 +477,86 @@ hipError_t launch_site_efull(hipStream_t st, bool f64, int kmode, int fmode, con
     return hipGetLastError();
 }
 
-hipError_t launch_site_reduce(hipStream_t st, const int32_t *rep_tiles, int ncol_max, int t_off,
-                              const RunArgs &ra)
+// The colour classes c_tail .. ncol-1 of every replica and then its per-MCS
+// history, in one launch of one block of kFinThreads threads per replica
+// (512: 1024 would spill the double-precision state and measured no faster
+// in single precision on the films).
+// Small trailing classes (the extra colours of odd-size films: a few hundred
+// sites per film) would otherwise cost a launch each, every one a single
+// dependent step of latency.  The block sweeps such a class with a stride of
+// its size (a block barrier between classes orders them) and keeps the
+// sums in registers; then every thread adds, at a stride of the block, the
+// records of the replica's phase-launched tiles (and, when the energy is
+// recomputed, every tile's recompute partial), and one block sum gives the
+// MCS totals.  The grouping of the additions depends only on the tables, so
+// plain and graph launches give identical history.
+template <typename T, int KM, int FM, bool TRACE, int MAXD>
+__global__ __launch_bounds__(kFinThreads) void k_site_finish(const RepDesc *__restrict__ reps,
+                                                    const int32_t *__restrict__ rep_tiles,
+                                                    int ncol_max, int c_tail, int t_off, RunArgs ra)
 {
-    hipLaunchKernelGGL(k_site_reduce, dim3((unsigned)((ra.R + 3) / 4)), dim3(256), 0, st, rep_tiles,
-                       ncol_max, t_off, ra);
+    __shared__ double red[(kFinThreads / 64) * 7];
+    const int r = blockIdx.x;
+    const RepDesc &rd = reps[r];
+    const uint32_t g = ra.ctl->g + (uint32_t)t_off;
+    const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double ad = 0.0;
+    if (c_tail < rd.ncol) {
+        const size_t sidx = (size_t)r * ra.S_hist + s_abs;
+        const T beta = (T)ra.beta[sidx];
+        const T b = (T)ra.bfield[sidx];
+        const double sigma = ra.pol.adaptive ? ra.sigma[r] : 0.0;
+        for (int c = c_tail; c < rd.ncol; ++c) {
+            const int ce = rd.cls_off[c + 1];
+            for (int i = rd.cls_off[c] + (int)threadIdx.x; i < ce; i += kFinThreads)
+                site_update<T, KM, FM, TRACE, MAXD>(rd, (T *)rd.spins, i, g, ra, r, beta, b, sigma, acc,
+                                                    ad);
+            __syncthreads();   // this class's stores are seen by the next class's reads
+        }
+    }
+    const bool rec_due = recompute_due(m, ra.P);
+    double v[7] = {acc[0], acc[1], acc[2], acc[3], acc[4], 0.0, ad};
+    for (int c = 0; c < ncol_max; ++c) {
+        const int tb = rep_tiles[(r * ncol_max + c) * 2], te = rep_tiles[(r * ncol_max + c) * 2 + 1];
+        if (c < c_tail) {
+            for (int tt = tb + (int)threadIdx.x; tt < te; tt += kFinThreads) {
+                const double *rec = ra.partials + (size_t)tt * kRecSite;
+#pragma unroll
+                for (int q = 0; q < 7; ++q) v[q] += rec[q];
+            }
+        } else if (rec_due) {
+            for (int tt = tb + (int)threadIdx.x; tt < te; tt += kFinThreads)
+                v[5] += ra.partials[(size_t)tt * kRecSite + 5];
+        }
+    }
+    block_sum<7>(v, red);
+    if (threadIdx.x != 0) return;
+    if (ra.pol.adaptive) adapt_sigma(ra, r, v[6]);
+    const double E = (rec_due ? v[5] : ra.ecarry[r]) + v[0];
+    ra.ecarry[r] = E;
+    double *h = ra.history + (((size_t)r * ra.S_hist + s_abs) * ra.M + m) * 5;
+    h[0] = E;
+    h[1] = v[1];
+    h[2] = v[2];
+    h[3] = v[3];
+    h[4] = v[4];
+}
+
+hipError_t launch_site_finish(hipStream_t st, bool f64, int kmode, int fmode, bool trace, int ellw,
+                              const RepDesc *reps, const int32_t *rep_tiles, int ncol_max, int c_tail,
+                              int t_off, const RunArgs &ra)
+{
+    const dim3 grid((unsigned)ra.R), blk(kFinThreads);
+    HSIM_DISPATCH_KF(kmode, fmode, HSIM_DISPATCH_W(ellw, {
+        if (f64) {
+            if (trace) hipLaunchKernelGGL((k_site_finish<double, KM, FM, true, MAXD>), grid, blk, 0, st, reps, rep_tiles, ncol_max, c_tail, t_off, ra);
+            else hipLaunchKernelGGL((k_site_finish<double, KM, FM, false, MAXD>), grid, blk, 0, st, reps, rep_tiles, ncol_max, c_tail, t_off, ra);
+        } else {
+            if (trace) hipLaunchKernelGGL((k_site_finish<float, KM, FM, true, MAXD>), grid, blk, 0, st, reps, rep_tiles, ncol_max, c_tail, t_off, ra);
+            else hipLaunchKernelGGL((k_site_finish<float, KM, FM, false, MAXD>), grid, blk, 0, st, reps, rep_tiles, ncol_max, c_tail, t_off, ra);
+        }
+    }));
     return hipGetLastError();
 }
 
