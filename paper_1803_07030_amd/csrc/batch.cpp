@@ -813,7 +813,7 @@ bool run_persistent(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st, uint3
     for (int c = 0; c < b->la.ncol; ++c)
         max_phase_tiles = std::max(max_phase_tiles, b->la.tile_off[c + 1] - b->la.tile_off[c]);
     grid = std::min(grid, max_phase_tiles * groups);
-    grid = std::min(grid, hsim::kMaxPersistentBlocks);
+    grid = std::min(grid, hsim::kMaxPersistentBlocks - hsim::kXBarLines);
     // barrier flags follow the record window
     auto *flags = (uint32_t *)(b->ws + b->off_part + rep_rec_bytes_max(b));
     hip_check(hsim::launch_rep_persistent(st, b->kmode, b->fmode, b->la, b->rep_ntiles, grid, ra,

@@ -28,6 +28,7 @@ constexpr int kRepSitesPerStep = HSIM_REP_SITES_PER_STEP;
 static_assert(kRepSitesPerWave % kRepSitesPerStep == 0 && kRepSitesPerWave % 4 == 0,
               "sites per wave must be a multiple of the sites per step and of 4");
 constexpr int kMaxPersistentBlocks = 4096;   // barrier flags reserved in the workspace
+constexpr int kXBarLines = 48;   // the flag region's last lines: per-XCD barrier words (3 x 16)
 constexpr int kRepTile = kRepWaves * kRepSitesPerWave;   // sites per replica-lane tile (at most)
 // tile shapes (sites per wave) the replica layout may use
 constexpr int kRepTileShapes[3] = {4, 8, kRepSitesPerWave};

@@ -772,8 +772,8 @@ __global__ __launch_bounds__(256) void k_rep_finals(RepLaneArgs a, int t_first, 
 }
 
 // ------------------------------------------------------------- persistent
-// One launch for the whole run.  Device-wide barrier without a contended
-// counter: every block publishes the barrier's epoch in its own 128-byte flag
+// One launch for the whole run.  Registration barrier (once per launch; the
+// run's barriers are xcd_barrier below), without a contended counter: every block publishes the barrier's epoch in its own 128-byte flag
 // (after a release fence); block 0 waits for all flags, then publishes the
 // epoch in one generation word, which the other blocks wait for (then an
 // acquire fence).  All polls are relaxed loads; every wait is bounded (cap
@@ -838,18 +838,110 @@ __device__ __forceinline__ void grid_barrier(Ctl *ctl, uint32_t *flags, uint32_t
     __syncthreads();
 }
 
-// Work items [0, NT) of one phase split XCD by XCD into contiguous ranges;
-// the blocks of an XCD stride through its range.
+// The blocks' barrier for the rest of the run, after a registration pass.
+// A release at agent scope writes back the L2 of the XCD that executes it,
+// whichever block of that XCD asks; with one release per block, the XCD's L2
+// would be written back once per resident block at every barrier.  Here one
+// leader block per XCD writes back on behalf of the XCD's blocks:
+//   1. every wave waits for its own stores (they are then in its XCD's L2);
+//      a non-leader block adds one to its XCD's arrival counter;
+//   2. the leader waits for the XCD's other blocks, writes the L2 back
+//      (agent release) and publishes the epoch in the XCD's line;
+//   3. the master (leader of the lowest XCD with blocks) waits for every
+//      XCD's line and publishes the epoch in the control word;
+//   4. every block waits for it and acquires at agent scope (this
+//      invalidates its CU's L1 and its XCD's L2: an invalidation at
+//      workgroup scope does not reach the L1 outside split-workgroup mode,
+//      and without it other CUs' stores were seen stale).
+// The XCD comes from the hardware register HW_REG_XCC_ID, so nothing rests
+// on how blocks are dealt to XCDs.  Every wait is bounded as in grid_barrier.
+struct XBar {
+    uint32_t *arr, *pub;         // per-XCD lines, 32 words apart
+    int x, slot, rank, nxcd;     // this block's XCD, its place there, the XCD's rank among used ones
+    uint32_t nx, present;        // blocks on this XCD; mask of XCDs with blocks
+    bool leader, master;
+};
+
+__device__ __forceinline__ uint32_t hw_xcc_id()
+{
+    // hardware register 20 (XCC_ID), bits 3:0
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u;
+}
+
+// Registration: each block takes a place on its XCD, then one full barrier
+// makes every count final.  Returns the state every later barrier uses.
+__device__ XBar xbar_register(Ctl *ctl, uint32_t *flags, uint32_t &epoch, uint32_t cap)
+{
+    __shared__ int sh[2];
+    uint32_t *reg = flags + (size_t)(kMaxPersistentBlocks - kXBarLines) * 32;
+    XBar xb;
+    xb.arr = reg + 16 * 32;
+    xb.pub = reg + 32 * 32;
+    if (threadIdx.x == 0) {
+        const uint32_t x = hw_xcc_id();
+        sh[0] = (int)x;
+        sh[1] = (int)__hip_atomic_fetch_add(&reg[x * 32], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    grid_barrier(ctl, flags, epoch, cap);
+    xb.x = sh[0];
+    xb.slot = sh[1];
+    xb.present = 0;
+    xb.rank = 0;
+    xb.nx = 1;
+    int first = -1;
+    for (int y = 0; y < 16; ++y) {
+        const uint32_t c = __hip_atomic_load(&reg[y * 32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (c == 0) continue;
+        xb.present |= 1u << y;
+        if (first < 0) first = y;
+        if (y < xb.x) ++xb.rank;
+        if (y == xb.x) xb.nx = c;
+    }
+    xb.nxcd = __popc(xb.present);
+    xb.leader = xb.slot == 0;
+    xb.master = xb.leader && xb.x == first;
+    return xb;
+}
+
+__device__ __forceinline__ void xcd_barrier(Ctl *ctl, const XBar &xb, uint32_t &epoch, uint32_t cap)
+{
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores are acknowledged by its L2
+    __syncthreads();
+    ++epoch;
+    if (threadIdx.x == 0) {
+        const int l = xb.x * 32;
+        if (!xb.leader) {
+            __hip_atomic_fetch_add(&xb.arr[l], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            // epoch 1 was the registration barrier: (epoch - 1) of these so far
+            barrier_wait(&xb.arr[l], (epoch - 1) * (xb.nx - 1), ctl, cap);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(&xb.pub[l], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (xb.master) {
+                for (int y = 0; y < 16; ++y)
+                    if ((xb.present >> y) & 1u) barrier_wait(&xb.pub[y * 32], epoch, ctl, cap);
+                __hip_atomic_store(&ctl->bar_arrive, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        barrier_wait(&ctl->bar_arrive, epoch, ctl, cap);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);   // done before any wave of the block loads
+    }
+    __syncthreads();
+}
+
+// Work items [0, NT) of one phase split into contiguous ranges, one per XCD
+// in use (by rank); the blocks of an XCD stride through its range by their
+// place on it.
 struct XcdRange {
     int u, end, step;
-    __device__ __forceinline__ XcdRange(int NT)
+    __device__ __forceinline__ XcdRange(int NT, const XBar &xb)
     {
-        const int G = gridDim.x, b = blockIdx.x, x = b & 7;
-        const int q = NT >> 3, rm = NT & 7;
+        const int q = NT / xb.nxcd, rm = NT % xb.nxcd, x = xb.rank;
         const int start = x * q + min(x, rm);
         end = start + q + (x < rm ? 1 : 0);
-        step = (G >> 3) + (x < (G & 7) ? 1 : 0);
-        u = start + (b >> 3);
+        step = (int)xb.nx;
+        u = start + xb.slot;
     }
 };
 
@@ -860,6 +952,7 @@ __global__ __launch_bounds__(kRepThreads) void k_rep_persistent(RepLaneArgs a, i
 {
     __shared__ double red[kRedDoubles];   // tile sums, reused by the reductions
     uint32_t epoch = 0;
+    const XBar xb = xbar_register(ra.ctl, flags, epoch, cap);
     const int groups = (a.Rp + W - 1) / W;
     for (int t = 0; t < ra.n_mcs_run; ++t) {
         const uint32_t g = ra.g0 + (uint32_t)t;
@@ -869,13 +962,13 @@ __global__ __launch_bounds__(kRepThreads) void k_rep_persistent(RepLaneArgs a, i
             for (int u = blockIdx.x; u < ntiles * groups; u += gridDim.x)
                 rep_tile_energy<KM, FM, W, MAXD>(a, u % ntiles, u / ntiles, g, ra, part, red);
             // the energy reads spins that colour 0 is about to change
-            grid_barrier(ra.ctl, flags, epoch, cap);
+            xcd_barrier(ra.ctl, xb, epoch, cap);
         }
         for (int c = 0; c < a.ncol; ++c) {
             const int nt = a.tile_off[c + 1] - a.tile_off[c];
-            for (XcdRange it(nt * groups); it.u < it.end; it.u += it.step)
+            for (XcdRange it(nt * groups, xb); it.u < it.end; it.u += it.step)
                 rep_tile<KM, FM, W, MAXD>(a, c, it.u % nt, it.u / nt, g, ra, part, red);
-            grid_barrier(ra.ctl, flags, epoch, cap);
+            xcd_barrier(ra.ctl, xb, epoch, cap);
             // the chunk sums of the previous MCS are complete once colour 0
             // of this one is: the last block adds them and writes its history
             if (c == 0 && t > 0 && blockIdx.x == gridDim.x - 1)
@@ -884,7 +977,7 @@ __global__ __launch_bounds__(kRepThreads) void k_rep_persistent(RepLaneArgs a, i
         }
         for (int k = blockIdx.x; k < kChunks; k += gridDim.x) rep_chunk_sum(a, ntiles, k, part, chk, red);
     }
-    grid_barrier(ra.ctl, flags, epoch, cap);
+    xcd_barrier(ra.ctl, xb, epoch, cap);
     if (blockIdx.x == gridDim.x - 1 && ra.n_mcs_run > 0) {
         const int t = ra.n_mcs_run - 1;
         rep_final(a, ra.g0 + (uint32_t)t, ra, rep_chunk_slot(ra, a, t & 1),
@@ -1037,8 +1130,11 @@ hipError_t launch_rep_persistent(hipStream_t st, int kmode, int fmode, const Rep
                                  int ntiles, int grid, const RunArgs &ra, uint32_t *flags,
                                  uint32_t spin_cap)
 {
-    if (grid > kMaxPersistentBlocks || ra.rec_win < 2) return hipErrorInvalidValue;
+    if (grid > kMaxPersistentBlocks - kXBarLines || ra.rec_win < 2) return hipErrorInvalidValue;
     hipError_t e = launch_fill_u32(st, flags, 0u, (int64_t)grid * 32);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32(st, flags + (size_t)(kMaxPersistentBlocks - kXBarLines) * 32, 0u,
+                        (int64_t)kXBarLines * 32);
     if (e != hipSuccess) return e;
     const int Wd = lane_width(a);
     HSIM_DISPATCH_KFW(kmode, fmode, Wd, HSIM_DISPATCH_D(a.ell_w, {

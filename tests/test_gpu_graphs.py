@@ -5,9 +5,12 @@
     later ones), with a rebind and new optional outputs in between, gives the
     spins and history of plain launches bit for bit.
   * A caller may record hsim_batch_run itself into a graph of its own (here a
-    torch CUDA graph, run made in AUTO mode): the schedule travels inside the
-    recorded work, and every replay, with eager work and synchronisation
-    between replays, equals the same run made eagerly.
+    torch CUDA graph, runs made in AUTO mode and as one persistent launch):
+    the schedule travels inside the recorded work, and every replay, with
+    eager work and synchronisation between replays, equals the same run made
+    eagerly in the same mode bit for bit (and, for the persistent launch, the
+    plain launches' spins and accept counts, with energies and
+    magnetisations within rounding).
 """
 import numpy as np
 import pytest
@@ -46,34 +49,46 @@ def test_graph_reused_across_calls_equals_plain(layout):
         assert np.array_equal(a, c)
 
 
-def test_caller_records_an_auto_run_into_its_own_graph():
+@pytest.mark.parametrize("launch", [hsim.LAUNCH_AUTO, hsim.LAUNCH_PERSISTENT])
+def test_caller_records_a_run_into_its_own_graph(launch):
     lat = synth.sc_periodic(12)
     lat.k = np.full(lat.n, 0.05)
     plan = hsim.Plan(lat)
     R, M, S = 24, 10, 2
     T = np.linspace(0.5, 2.0, R)[:, None] * np.ones((1, S))
     Bf = np.full((R, S), 0.2)
+    # eager references: the same launch mode (bit for bit) and, for the
+    # persistent launch, plain launches (the same spins and accept counts;
+    # energies and magnetisations within rounding)
+    eager = [hsim.LAUNCH_PLAIN] if launch == hsim.LAUNCH_AUTO else [launch, hsim.LAUNCH_PLAIN]
     rec = hsim.Batch([plan] * R, seed=4, precision=hsim.FP32).bind(S, M)
-    ref = hsim.Batch([plan] * R, seed=4, precision=hsim.FP32).bind(S, M)
+    refs = [hsim.Batch([plan] * R, seed=4, precision=hsim.FP32).bind(S, M) for _ in eager]
     assert rec.layout == "replica"
-    for b in (rec, ref):
+    for b in [rec] + refs:
         b.init_spins(hsim.INIT_RANDOM)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, capture_error_mode="thread_local"):
-        rec.run(T, Bf, recompute_every=5, launch=hsim.LAUNCH_AUTO)
+        rec.run(T, Bf, recompute_every=5, launch=launch)
     # nothing ran during the recording
     assert np.all(rec.history.cpu().numpy() == 0.0)
     for k in range(3):
         # a replay repeats the recorded steps (same random words) from the
-        # current spins; the eager reference does the same
+        # current spins; the eager references do the same
         g.replay()
-        ref.run(T, Bf, recompute_every=5, launch=hsim.LAUNCH_PLAIN)
+        for ref, mode in zip(refs, eager):
+            ref.run(T, Bf, recompute_every=5, launch=mode)
         torch.cuda.synchronize()
-        assert rec.status() == 0 and ref.status() == 0
+        assert rec.status() == 0 and all(ref.status() == 0 for ref in refs)
         # eager work between replays
-        assert np.array_equal(_spins(rec), _spins(ref)), k
-        assert np.array_equal(rec.history.cpu().numpy(), ref.history.cpu().numpy()), k
+        h = rec.history.cpu().numpy()
+        assert np.array_equal(_spins(rec), _spins(refs[0])), k
+        assert np.array_equal(h, refs[0].history.cpu().numpy()), k
+        if len(refs) > 1:
+            hp = refs[1].history.cpu().numpy()
+            assert np.array_equal(_spins(rec), _spins(refs[1])), k
+            assert np.array_equal(h[..., 4], hp[..., 4]), k
+            assert np.allclose(h, hp, rtol=0, atol=1e-9 * lat.n), (k, float(np.abs(h - hp).max()))
         # a run with another schedule between replays must not leak into them
         other = hsim.Batch([plan] * R, seed=5, precision=hsim.FP32).bind(S, M)
         other.init_spins(hsim.INIT_COLD_Z)
