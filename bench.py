@@ -361,7 +361,9 @@ def films_bench(args, stream):
         "unit": "spin updates/s", "steps": args.steps, "warmup": args.warmup,
         "config": {"workload": f"256 diluted films, {nsites} sites, {mcs} MCS, f32, site-lane, "
                                f"{args.launch} launch",
-                   "sites": nsites, "mean_degree": zbar, "launch": args.launch},
+                   "sites": nsites, "mean_degree": zbar, "launch": args.launch,
+                   "tuned_launch": {-1: None, 0: "plain", 1: "persistent", 2: "graph"}.get(
+                       int(batch.info.tuned_launch))},
         "acceptance": acc,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "kernel": kernel,

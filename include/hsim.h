@@ -211,7 +211,10 @@ hsim_status hsim_batch_init_spins(hsim_batch b, int32_t mode, const double *host
  *     step start).
  *   d_trace: NULL, or with HSIM_RUN_TRACE_ACCEPTS a zeroed uint32 bitmap
  *     [n_rep][n_steps*mcs_per_step][ceil(n/32)] receiving bit (site % 32) of
- *     word site/32 for every accepted move (SITE and BLOCK layouts).
+ *     word site/32 for every accepted move (site = user index; every layout,
+ *     in the replica layout only without update policies, cubic terms or
+ *     spin norms: HSIM_E_UNSUPPORTED otherwise; a traced persistent request
+ *     runs as plain launches).
  * Spins carry over between steps and between calls. */
 hsim_status hsim_batch_run(hsim_batch b, int32_t first_step, int32_t n_steps, const double *T,
                            const double *B, int32_t recompute_every, hsim_launch launch,

@@ -837,8 +837,13 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
     if (launch < HSIM_LAUNCH_PLAIN || launch > HSIM_LAUNCH_AUTO) throw Error(HSIM_E_ARG, "bad launch mode");
     const bool want_trace = (flags & HSIM_RUN_TRACE_ACCEPTS) != 0;
     if (want_trace && !trace) throw Error(HSIM_E_ARG, "run: trace requested without a buffer");
-    if (want_trace && b->layout == HSIM_LAYOUT_REPLICA)
-        throw Error(HSIM_E_UNSUPPORTED, "accept trace needs the site or block layout");
+    if (want_trace && b->layout == HSIM_LAYOUT_REPLICA) {
+        bool xt = b->pol.n_types > 0;
+        for (auto p : b->plans) xt |= !p->kcd.empty() || !p->mud.empty();
+        if (xt)
+            throw Error(HSIM_E_UNSUPPORTED,
+                        "accept trace in the replica layout: not with update policies, cubic terms or spin norms");
+    }
     for (int r = 0; r < b->R; ++r)
         for (int s = 0; s < n_steps; ++s) {
             const double t = T[(size_t)r * n_steps + s], f = B[(size_t)r * n_steps + s];
@@ -918,11 +923,12 @@ void batch_run_impl(hsim_batch b, int32_t first_step, int32_t n_steps, const dou
         else mode = HSIM_LAUNCH_GRAPH;
     }
     // the persistent kernel runs the random move of the plain model without
-    // optional outputs: with update policies, cubic constants, spin norms or
-    // outputs bound the same sweep runs as plain launches
+    // optional outputs: with update policies, cubic constants, spin norms,
+    // outputs bound or an accept trace the same sweep runs as plain launches
     bool xt = false;
     for (auto p : b->plans) xt |= !p->kcd.empty() || !p->mud.empty();
-    if (mode == HSIM_LAUNCH_PERSISTENT && (b->pol.n_types > 0 || xt || b->type_mag || b->snapshots))
+    if (mode == HSIM_LAUNCH_PERSISTENT &&
+        (b->pol.n_types > 0 || xt || b->type_mag || b->snapshots || want_trace))
         mode = HSIM_LAUNCH_PLAIN;
     if (mode == HSIM_LAUNCH_PERSISTENT) {
         if (b->layout != HSIM_LAYOUT_REPLICA)

@@ -83,8 +83,17 @@ struct RepSite {
 };
 
 // Kernel variants: bit 0 (VAR_POL) update policies, bit 1 (VAR_XT) cubic
-// anisotropy and / or spin norms.
-constexpr int VAR_POL = 1, VAR_XT = 2;
+// anisotropy and / or spin norms, bit 2 (VAR_TRACE) the accept bitmap (alone:
+// a traced run of the plain model).
+constexpr int VAR_POL = 1, VAR_XT = 2, VAR_TRACE = 4;
+
+// Accept bitmap of a traced run: bit (user site % 32) of word user site / 32
+// of row (replica, MCS of the run).
+__device__ __forceinline__ void rep_trace(const RunArgs &ra, int r, uint32_t g, uint32_t orig)
+{
+    atomicOr(&ra.trace[((size_t)r * ra.n_mcs_run + (g - ra.g0)) * ra.trace_words + (orig >> 5)],
+             1u << (orig & 31));
+}
 
 // Trial of site i for one lane: the random move, or (VAR_POL) the move of the
 // site's type, with the lane's replica width for the adaptive move; ad tells
@@ -171,6 +180,7 @@ __device__ __forceinline__ void rep_site_update(const RepLaneArgs &a, int i, int
         S[oi] = t.x;
         S[plane + oi] = t.y;
         S[2 * plane + oi] = t.z;
+        if constexpr ((VAR & VAR_TRACE) != 0) rep_trace(ra, r, g, a.orig[i]);
     }
     accumulate(acc, ok, active, dE, ok ? t.x : sx, ok ? t.y : sy, ok ? t.z : sz);
 }
@@ -285,6 +295,8 @@ __device__ __forceinline__ void rep_step_uniform(const RepLaneArgs &a, const Spi
             bstore(sp3.y, lane_b, oi, ok ? t.y : sy[u]);
             bstore(sp3.z, lane_b, oi, ok ? t.z : sz[u]);
         }
+        if constexpr ((VAR & VAR_TRACE) != 0)
+            if (ok) rep_trace(ra, r, g, cload(a.orig, i));
         accumulate(acc, ok, live, dE, ok ? t.x : sx[u], ok ? t.y : sy[u], ok ? t.z : sz[u]);
     }
 }
@@ -347,6 +359,7 @@ __device__ __forceinline__ void rep_pair_update(const RepLaneArgs &a, int i0, in
             S[oi] = t.x;
             S[plane + oi] = t.y;
             S[2 * plane + oi] = t.z;
+            if constexpr ((VAR & VAR_TRACE) != 0) rep_trace(ra, r, g, a.orig[i]);
         }
         accumulate(acc, ok, live, dE, ok ? t.x : sx[u], ok ? t.y : sy[u], ok ? t.z : sz[u]);
     }
@@ -1078,8 +1091,13 @@ hipError_t launch_rep_phase(hipStream_t st, int kmode, int fmode, int colour, in
     dim3 grid((unsigned)nt, (unsigned)(a.Rp / Wd));
     dim3 blk(kRepThreads);
     HSIM_DISPATCH_KFW(kmode, fmode, Wd, HSIM_DISPATCH_D(a.ell_w, {
-        const int var = (ra.pol.n_types > 0 ? VAR_POL : 0) | (a.kc || a.mu ? VAR_XT : 0);
-        if (var == 0)
+        const int var = (ra.pol.n_types > 0 ? VAR_POL : 0) | (a.kc || a.mu ? VAR_XT : 0) |
+                        (ra.trace ? VAR_TRACE : 0);
+        if ((var & VAR_TRACE) && var != VAR_TRACE) return hipErrorInvalidValue;
+        if (var == VAR_TRACE)
+            hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD, VAR_TRACE>), grid, blk, 0, st, a,
+                               colour, t_off, ntiles, ra);
+        else if (var == 0)
             hipLaunchKernelGGL((k_rep_phase<KM, FM, W, MAXD, 0>), grid, blk, 0, st, a, colour,
                                t_off, ntiles, ra);
         else if (var == VAR_POL)

@@ -344,12 +344,12 @@ def test_replica_layout_planar_rows_for_arrays_over_2gib():
 
 
 # ---------------------------------------------- tile sizes of the replica layout
-@pytest.mark.parametrize("L", [48, 56], ids=["sc48", "sc56"])
+@pytest.mark.parametrize("L", [48, 56, 64], ids=["sc48", "sc56", "sc64"])
 def test_replica_tiles_of_every_size_match_the_site_layout(L):
     """The replica layout sizes its tiles to the lattice (4, 8 or 32 sites
-    per wave: on a 256-CU GPU SC 48^3 with 64 replicas takes 8 and SC 56^3
-    takes 32; the smaller lattices of other tests take 4): spins and accept
-    counts equal the site layout's after 3 MCS."""
+    per wave: on a 256-CU GPU SC 48^3 with 64 replicas takes 8, SC 56^3 and
+    the SC 64^3 headline take 32; the smaller lattices of other tests take 4):
+    spins and accept counts equal the site layout's after 3 MCS."""
     lat = synth.sc_periodic(L)
     lat.k = np.full(lat.n, 0.1)
     plan = hsim.Plan(lat)
@@ -472,3 +472,47 @@ def test_persistent_barrier_wait_cap_reports_timeout():
     b.run(np.full((R, 1), 1.0), 0.0, launch=hsim.LAUNCH_PERSISTENT)
     torch.cuda.synchronize()
     assert b.status() == 0
+
+
+# --------------------------------------------- accept trace, replica layout
+@pytest.mark.parametrize("case", ["sc_r20", "sc_r64", "hub_r64"])
+def test_replica_layout_accept_trace_equals_site_layout(case):
+    """The accept bitmap of a replica-layout run (plain, graph and a
+    persistent request, which runs as plain launches) equals the site
+    layout's bit for bit over 2 steps x 6 MCS: rows of 32 lanes (R = 20), 64
+    lanes (R = 64) and the generic row walk (a site of degree 42).  With
+    update policies the replica layout refuses a trace."""
+    if case == "hub_r64":
+        lat = _hub_lattice()
+    else:
+        lat = synth.sc_periodic(10)
+        lat.k = 0.2 * synth.uniform01(7, lat.n, tag=1)
+        lat.axis = synth.unit_vectors(7, lat.n, tag=2)
+    R = 20 if case == "sc_r20" else 64
+    plan = hsim.Plan(lat)
+    S, M = 2, 6
+    T = np.linspace(0.3, 2.5, R)[:, None] * np.ones((1, S))
+    Bf = np.linspace(-0.4, 0.4, R)[:, None] * np.ones((1, S))
+    out = {}
+    for name, layout, launch in (("site", hsim.LAYOUT_SITE, hsim.LAUNCH_PLAIN),
+                                 ("rep", hsim.LAYOUT_REPLICA, hsim.LAUNCH_PLAIN),
+                                 ("rep_graph", hsim.LAYOUT_REPLICA, hsim.LAUNCH_GRAPH),
+                                 ("rep_persist", hsim.LAYOUT_REPLICA, hsim.LAUNCH_PERSISTENT)):
+        b = hsim.Batch([plan] * R, seed=17, precision=hsim.FP32, layout=layout).bind(S, M)
+        b.init_spins(hsim.INIT_RANDOM)
+        tr = b.new_trace(S)
+        b.run(T, Bf, recompute_every=3, launch=launch, trace=tr)
+        torch.cuda.synchronize()
+        assert b.status() == 0, name
+        out[name] = (tr.cpu().numpy(), b.history.cpu().numpy())
+    acc = hsim.unpack_trace(torch.from_numpy(out["site"][0]), lat.n)
+    assert acc.sum() > 0
+    for name, (tr, h) in out.items():
+        assert np.array_equal(tr, out["site"][0]), name
+        # the bitmap counts the history's accepted moves
+        got = hsim.unpack_trace(torch.from_numpy(tr), lat.n)
+        assert np.array_equal(got.sum(axis=-1).reshape(R, S, M), h[..., 4]), name
+    b = hsim.Batch([plan] * R, seed=17, precision=hsim.FP32, layout=hsim.LAYOUT_REPLICA).bind(1, 2)
+    b.set_policies([(hsim.POLICY_SMALL_STEP, 0.3)])
+    with pytest.raises(hsim.HsimError):
+        b.run(T[:, :1], 0.0, trace=b.new_trace(1))
