@@ -132,6 +132,16 @@ hsim_status hsim_plan_colouring(hsim_plan plan, int32_t *colour_out);
 /* Bonds i < j in row-major CSR order (the order of every per-bond array):
  * bond_ij_out [2*n_bonds] (may be NULL), *n_bonds_out (may be NULL). */
 hsim_status hsim_plan_bonds(hsim_plan plan, int32_t *bond_ij_out, int64_t *n_bonds_out);
+/* Half rows of the energy forward (Eq. 1 counts every bond once): each bond
+ * is given to the one of its ends that a closed-walk (Euler) orientation
+ * makes it leave, so a site of degree d holds at most ceil(d/2) bonds.
+ * *width_out: slots per site (half the padded row width; 0 when a site's
+ * degree exceeds 8 and the energy calls walk the CSR instead).
+ * col_out, bond_out [width][n] slot-major, user order, host memory (may be
+ * NULL): the far end and the bond id of each bond the site holds, in CSR
+ * order; empty slots name the site itself with bond id -1. */
+hsim_status hsim_plan_half_rows(hsim_plan plan, int32_t *width_out, int32_t *col_out,
+                                int32_t *bond_out);
 /* Site types (paper, section "Material building": every site belongs to a
  * magnetic phase, and each phase may use its own update policy).
  *   site_type [n] user order, values 0..7; NULL: type 0 everywhere.

@@ -125,6 +125,17 @@ hsim_status hsim_plan_bonds(hsim_plan p, int32_t *bond_ij_out, int64_t *n_bonds_
     });
 }
 
+hsim_status hsim_plan_half_rows(hsim_plan p, int32_t *width_out, int32_t *col_out, int32_t *bond_out)
+{
+    return guarded([&] {
+        if (!p) throw hsim::Error(HSIM_E_ARG, "plan_half_rows: NULL plan");
+        if (width_out) *width_out = p->h_w;
+        const size_t cnt = (size_t)p->h_w * (size_t)p->n;
+        if (col_out && cnt > 0) std::memcpy(col_out, p->uhalf_col.data(), cnt * sizeof(int32_t));
+        if (bond_out && cnt > 0) std::memcpy(bond_out, p->uhalf_bond.data(), cnt * sizeof(int32_t));
+    });
+}
+
 hsim_status hsim_plan_set_types(hsim_plan p, const int32_t *site_type)
 {
     return guarded([&] { plan_set_types_impl(p, site_type); });

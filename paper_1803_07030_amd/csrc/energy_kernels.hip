@@ -160,11 +160,12 @@ struct SiteTables {
 
 // Padded rows of width W: one work item per block (XCD-aware order), each
 // thread one site and the kEG configurations of the item, kEU at a time.
-template <typename T, bool BWD, int W>
+template <typename T, bool BWD, int W, bool HALF = false>
 __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile, int items,
                                                         const double *gE, T *gS, double *partE,
                                                         double *partB, double *partK, double *partJ)
 {
+    static_assert(!(HALF && BWD), "half rows serve the forward only");
     const int u_item = xcd_tile((int)blockIdx.x, items);
     const int grp = u_item / ntile, tile = u_item - grp * ntile;
     constexpr int kW = kEBlock / 64;
@@ -176,10 +177,11 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
     int32_t col[W];
     T J[W];
     int32_t bid[W];
+    const int32_t *tcol = HALF ? a.hcol : a.ecol, *tbond = HALF ? a.hbond : a.ebond;
 #pragma unroll
     for (int q = 0; q < W; ++q) {
-        col[q] = a.ecol[(size_t)q * a.n + ii];
-        bid[q] = a.ebond[(size_t)q * a.n + ii];
+        col[q] = tcol[(size_t)q * a.n + ii];
+        bid[q] = tbond[(size_t)q * a.n + ii];
         const T jv = Jb[bid[q] >= 0 ? bid[q] : 0];
         J[q] = bid[q] >= 0 ? jv : T(0);
     }
@@ -229,7 +231,10 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
             const double sx = tsx, sy = tsy, sz = tsz;
             const double an = sx * (double)ex + sy * (double)ey + sz * (double)ez;
             const double zn = sx * (double)nx + sy * (double)ny + sz * (double)nz;
-            double e = -0.5 * (sx * (double)thx + sy * (double)thy + sz * (double)thz) - a.B * zn -
+            // full rows count every bond from both ends (half each); half
+            // rows count it once, at the end it leaves
+            constexpr double kBond = HALF ? 1.0 : 0.5;
+            double e = -kBond * (sx * (double)thx + sy * (double)thy + sz * (double)thz) - a.B * zn -
                        (double)k * an * an;
             // cubic term of Eq. 3, -kc (Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2)
             if (a.kc) e -= (double)kc * ((sx * sx * (sy * sy) + sy * sy * (sz * sz)) + sx * sx * (sz * sz));
@@ -519,7 +524,16 @@ hipError_t launch_site_kernel(hipStream_t st, const EnergyArgs &a, const EnergyL
                               double *partK, double *partJ)
 {
     const int ngroups = (a.batch + kEG - 1) / kEG;
-    if (L.ell_w == 6 || L.ell_w == 8) {
+    if (!BWD && a.hcol && (L.ell_w == 6 || L.ell_w == 8)) {
+        // the forward needs every bond once: half rows of width ell_w / 2
+        const int items = ngroups * L.ntile;
+        if (L.ell_w == 6)
+            hipLaunchKernelGGL((k_energy_ell<T, false, 3, true>), dim3((unsigned)items), dim3(kEBlock), 0,
+                               st, a, L.ntile, items, gE, gS, partE, partB, partK, partJ);
+        else
+            hipLaunchKernelGGL((k_energy_ell<T, false, 4, true>), dim3((unsigned)items), dim3(kEBlock), 0,
+                               st, a, L.ntile, items, gE, gS, partE, partB, partK, partJ);
+    } else if (L.ell_w == 6 || L.ell_w == 8) {
         const int items = ngroups * L.ntile;
         if (L.ell_w == 6)
             hipLaunchKernelGGL((k_energy_ell<T, BWD, 6>), dim3((unsigned)items), dim3(kEBlock), 0, st, a,

@@ -228,6 +228,8 @@ struct EnergyArgs {
     const int32_t *fwd_entry; // nb: the CSR entry of each bond at its lower end
     const int32_t *ecol;    // [ell_w][n] padded rows, slot-major (padding: the site itself)
     const int32_t *ebond;   // [ell_w][n] bond id of each slot (-1 past the row)
+    const int32_t *hcol;    // [ell_w/2][n] half rows: the bonds each site leaves (forward)
+    const int32_t *hbond;   // [ell_w/2][n] their bond ids (-1 past the row)
     int64_t n, nnz, nb;
     int batch;
     const void *S, *Jb, *k, *ax, *nd;

@@ -106,7 +106,12 @@ struct hsim_plan_s {
     // scratch and its pass layout, set up once by prepare_energy()
     int e_w = 0;
     std::vector<int32_t> uell_col, uell_bond;
-    hsim::DevBuf d_uell_col, d_uell_bond, d_escratch;
+    // the forward's half rows: every bond once, at the end an Euler
+    // orientation makes it leave (at most ceil(deg/2) per site), slot-major
+    // [h_w][n] with h_w = e_w / 2
+    int h_w = 0;
+    std::vector<int32_t> uhalf_col, uhalf_bond;
+    hsim::DevBuf d_uell_col, d_uell_bond, d_uhalf_col, d_uhalf_bond, d_escratch;
     hsim::EnergyLayout elayout{};
     bool energy_ready = false;
 

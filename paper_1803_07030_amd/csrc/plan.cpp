@@ -102,6 +102,90 @@ int32_t bfs_greedy(int64_t n, const int64_t *rp, const int32_t *col, std::vector
 
 }  // namespace
 
+// Half rows for the energy forward, where each bond is needed once.  Every
+// bond is given a direction by closed walks: odd-degree sites of a component
+// are joined to one extra vertex (there is an even number of them), so every
+// degree is even; a walk that takes unused edges from a vertex can only stop
+// where it started, so along each walk every vertex is left as often as it
+// is entered, and a site of degree d leaves at most ceil(d / 2) of its bonds.
+// A site's row lists the bonds it leaves, in CSR order.
+void half_rows(hsim_plan P, const int64_t *rp, const int32_t *col)
+{
+    const int64_t n = P->n;
+    // adjacency: CSR entries, then one virtual edge per odd site (to vertex n)
+    std::vector<int64_t> odd;
+    for (int64_t i = 0; i < n; ++i)
+        if ((rp[i + 1] - rp[i]) & 1) odd.push_back(i);
+    const int64_t nb = P->nb, ne = nb + (int64_t)odd.size();
+    std::vector<int64_t> vodd(n, -1);
+    for (size_t k = 0; k < odd.size(); ++k) vodd[odd[k]] = (int64_t)k;
+    // per vertex: CSR entries (target, edge) and, for odd sites, the virtual edge
+    auto deg_of = [&](int64_t v) -> int64_t {
+        return v == n ? (int64_t)odd.size() : (rp[v + 1] - rp[v]) + (vodd[v] >= 0 ? 1 : 0);
+    };
+    auto entry = [&](int64_t v, int64_t q, int64_t &to, int64_t &edge) {
+        if (v == n) {
+            to = odd[q];
+            edge = nb + q;
+        } else if (q < rp[v + 1] - rp[v]) {
+            to = col[rp[v] + q];
+            edge = P->ubond[rp[v] + q];
+        } else {
+            to = n;
+            edge = nb + vodd[v];
+        }
+    };
+    std::vector<uint8_t> used(ne, 0);
+    std::vector<int64_t> next(n + 1, 0);
+    std::vector<uint8_t> leaves(nb, 0);   // 1: the bond leaves its lower end
+    for (int64_t s = 0; s <= n; ++s) {
+        for (;;) {
+            // a closed walk from s over unused edges
+            int64_t v = s;
+            bool moved = false;
+            for (;;) {
+                int64_t to = -1, edge = -1;
+                const int64_t d = deg_of(v);
+                while (next[v] < d) {
+                    entry(v, next[v]++, to, edge);
+                    if (!used[edge]) break;
+                    edge = -1;
+                }
+                if (edge < 0) break;
+                used[edge] = 1;
+                if (edge < nb) leaves[edge] = v < to ? 1 : 0;
+                v = to;
+                moved = true;
+            }
+            if (!moved || v != s) break;
+        }
+    }
+    std::vector<int32_t> outn(n, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            const int32_t b = P->ubond[p];
+            if ((col[p] > i) == (leaves[b] != 0)) ++outn[i];
+        }
+    int32_t hw = 0;
+    for (int64_t i = 0; i < n; ++i) hw = std::max(hw, outn[i]);
+    if (hw > P->e_w / 2) throw Error(HSIM_E_UNSUPPORTED, "internal: bond orientation left a site unbalanced");
+    P->h_w = P->e_w / 2;
+    const int W = P->h_w;
+    P->uhalf_col.assign((size_t)W * n, 0);
+    P->uhalf_bond.assign((size_t)W * n, -1);
+    for (int64_t i = 0; i < n; ++i) {
+        int q = 0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            const int32_t b = P->ubond[p];
+            if ((col[p] > i) != (leaves[b] != 0)) continue;
+            P->uhalf_col[(size_t)q * n + i] = col[p];
+            P->uhalf_bond[(size_t)q * n + i] = b;
+            ++q;
+        }
+        for (; q < W; ++q) P->uhalf_col[(size_t)q * n + i] = (int32_t)i;
+    }
+}
+
 hsim_plan plan_create_impl(int64_t n, const int64_t *rp, const int32_t *col, const double *J,
                            const double *k, const double *axis, const double *fd)
 {
@@ -252,6 +336,7 @@ hsim_plan plan_create_impl(int64_t n, const int64_t *rp, const int32_t *col, con
                     P->uell_col[(size_t)q * n + i] = in ? col[p] : (int32_t)i;
                     P->uell_bond[(size_t)q * n + i] = in ? P->ubond[p] : -1;
                 }
+            half_rows(P, rp, col);
         }
     } catch (...) {
         delete P;
@@ -376,6 +461,8 @@ void hsim_plan_s::upload_energy()
     if (e_w > 0) {
         d_uell_col.upload(uell_col);
         d_uell_bond.upload(uell_bond);
+        d_uhalf_col.upload(uhalf_col);
+        d_uhalf_bond.upload(uhalf_bond);
     }
     energy_on_device = true;
 }
@@ -406,6 +493,8 @@ hsim::EnergyArgs energy_args(hsim_plan P, int32_t batch, const void *S, const vo
     a.fwd_entry = (const int32_t *)P->d_fwd.p;
     a.ecol = (const int32_t *)P->d_uell_col.p;
     a.ebond = (const int32_t *)P->d_uell_bond.p;
+    a.hcol = (const int32_t *)P->d_uhalf_col.p;
+    a.hbond = (const int32_t *)P->d_uhalf_bond.p;
     a.n = P->n;
     a.nnz = P->nnz;
     a.nb = P->nb;

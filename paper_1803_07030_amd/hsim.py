@@ -62,6 +62,7 @@ _SIGNATURES = {
     "hsim_plan_info": [_vp, _vp],
     "hsim_plan_colouring": [_vp, _vp],
     "hsim_plan_bonds": [_vp, _vp, _vp],
+    "hsim_plan_half_rows": [_vp, _vp, _vp, _vp],
     "hsim_batch_create": [_vp, _i32, _vp, _u64, _vp, _i32, _i32],
     "hsim_batch_info": [_vp, _vp],
     "hsim_batch_set_shape": [_vp, _i32, _i32],
@@ -164,6 +165,17 @@ def hsim_plan_bonds(plan):
     ij = np.empty(2 * max(nb.value, 1), dtype=np.int32)
     _check(lib().hsim_plan_bonds(plan, _ptr(ij), None))
     return ij[:2 * nb.value].reshape(nb.value, 2)
+
+
+def hsim_plan_half_rows(plan, n):
+    """(col, bond) [width][n] of the energy forward's half rows."""
+    w = ctypes.c_int32()
+    _check(lib().hsim_plan_half_rows(plan, ctypes.byref(w), None, None))
+    col = np.empty((w.value, n), dtype=np.int32)
+    bond = np.empty((w.value, n), dtype=np.int32)
+    if col.size:
+        _check(lib().hsim_plan_half_rows(plan, None, _ptr(col), _ptr(bond)))
+    return col, bond
 
 
 def hsim_plan_set_types(plan, site_type):
@@ -387,6 +399,9 @@ class Plan:
 
     def bonds(self):
         return hsim_plan_bonds(self.handle)
+
+    def half_rows(self):
+        return hsim_plan_half_rows(self.handle, self.n)
 
     def set_types(self, site_type):
         """Site types (user order, 0..7), or None for type 0 everywhere."""

@@ -280,6 +280,61 @@ def test_energy_and_gradients_match_oracle(dtype):
         assert dB <= bB, (dB, bB)
 
 
+def _degree8_lattice(n=400, seed=11):
+    """Random graph with degrees up to 8 (many odd), per-bond J, per-site K,
+    axes and field directions: padded rows of width 8, half rows of 4."""
+    rng = np.random.default_rng(seed)
+    deg = np.zeros(n, dtype=np.int64)
+    pairs = set()
+    for _ in range(8 * n):
+        a, b = (int(x) for x in rng.integers(0, n, 2))
+        if a == b or deg[a] >= 8 or deg[b] >= 8 or (min(a, b), max(a, b)) in pairs:
+            continue
+        pairs.add((min(a, b), max(a, b)))
+        deg[a] += 1
+        deg[b] += 1
+    bi, bj = (np.array(x) for x in zip(*sorted(pairs)))
+    lat = synth.from_bonds(n, bi, bj, rng.uniform(-1.0, 1.5, bi.size), name="deg8")
+    lat.k = rng.uniform(0.0, 0.3, n)
+    lat.axis = synth.unit_vectors(seed, n, tag=1)
+    lat.ndir = synth.unit_vectors(seed, n, tag=2)
+    assert lat.degree.max() == 8 and np.any(lat.degree % 2 == 1)
+    return lat
+
+
+@pytest.mark.parametrize("kind", ["film", "deg8"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_energy_forward_from_half_rows(kind, dtype):
+    """The forward reads each bond once, from half rows that an Euler
+    orientation of the bonds gives each site (at most ceil(deg/2) of them);
+    with odd degrees and rows of up to 8 entries its energies equal the
+    oracle's (FP64: 1e-12 of the scale; FP32: 2e-6 of the scale)."""
+    from paper_1803_07030_amd.energy import heisenberg_energy
+    if kind == "film":
+        lat = synth.diluted_film(21, 5, seed=12)
+        lat.ndir = synth.unit_vectors(12, lat.n, tag=3)
+    else:
+        lat = _degree8_lattice()
+    plan = hsim.Plan(lat)
+    nbatch = 40
+    S = synth.random_spins(13, lat.n, batch=nbatch)
+    if dtype == torch.float32:
+        S = S.astype(np.float32).astype(np.float64)
+    _, _, Jb = lat.bonds()
+    dev = "cuda"
+    St = torch.tensor(S.transpose(0, 2, 1).copy(), dtype=dtype, device=dev)
+    J = torch.tensor(Jb, dtype=dtype, device=dev)
+    k = torch.tensor(lat.k, dtype=dtype, device=dev)
+    ax = torch.tensor(lat.axis.T.copy(), dtype=dtype, device=dev)
+    nd = torch.tensor(lat.ndir.T.copy(), dtype=dtype, device=dev)
+    B = torch.tensor(0.7, dtype=torch.float64, device=dev)
+    E = heisenberg_energy(St, J, k, B, plan, ax, nd).cpu().numpy()
+    tol = 1e-12 if dtype == torch.float64 else 2e-6
+    for b_ in range(nbatch):
+        e = oracle.energy(lat, 0.7, S[b_])
+        assert abs(E[b_] - e["E"]) <= tol * e["scale"], (b_, E[b_], e["E"])
+
+
 @pytest.mark.parametrize("layout", [hsim.LAYOUT_SITE, hsim.LAYOUT_REPLICA])
 def test_phase_timing_counts_and_leaves_results_unchanged(layout):
     """Sampled timing of the colour-phase launches (every 3rd MCS of a plain

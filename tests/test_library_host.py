@@ -49,6 +49,54 @@ def test_colouring_and_bonds_equal_oracle(idx):
     assert p.info.n_bonds == lat.n_bonds
 
 
+def _random_graph(n, maxd, seed):
+    rng = np.random.default_rng(seed)
+    deg = np.zeros(n, dtype=np.int64)
+    pairs = set()
+    for _ in range(6 * n):
+        a, b = (int(x) for x in rng.integers(0, n, 2))
+        if a == b or deg[a] >= maxd or deg[b] >= maxd or (min(a, b), max(a, b)) in pairs:
+            continue
+        pairs.add((min(a, b), max(a, b)))
+        deg[a] += 1
+        deg[b] += 1
+    bi, bj = (np.array(x) for x in zip(*sorted(pairs)))
+    return synth.from_bonds(n, bi, bj, np.ones(bi.size))
+
+
+@pytest.mark.parametrize("idx", range(11))
+def test_half_rows_hold_every_bond_once(idx):
+    """The energy forward's half rows (each bond at the end a closed-walk
+    orientation makes it leave): every bond exactly once, its far end and
+    bond id as the lattice has them, at most ceil(d/2) bonds per site of
+    degree d, empty slots naming the site itself; no half rows when a site's
+    degree exceeds 8."""
+    lats = _lat_variants() + [_random_graph(500, 8, 1), _random_graph(701, 7, 2),
+                              synth.sc_periodic(3)]
+    lat = lats[idx]
+    p = hsim.Plan(lat)
+    col, bond = p.half_rows()
+    deg = np.diff(lat.row_ptr)
+    if deg.max(initial=0) > 8:
+        assert col.shape[0] == 0
+        return
+    assert col.shape == (3 if deg.max(initial=0) <= 6 else 4, lat.n)
+    ij = p.bonds()
+    seen = np.zeros(len(ij), dtype=np.int64)
+    held = np.zeros(lat.n, dtype=np.int64)
+    for q in range(col.shape[0]):
+        for i in range(lat.n):
+            b, c = bond[q, i], col[q, i]
+            if b < 0:
+                assert c == i
+                continue
+            seen[b] += 1
+            held[i] += 1
+            assert sorted((i, c)) == sorted(ij[b].tolist())
+    assert np.all(seen == 1)
+    assert np.all(held <= (deg + 1) // 2)
+
+
 def _expect(code, fn):
     with pytest.raises(hsim.HsimError) as e:
         fn()
