@@ -231,14 +231,16 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
             const double sx = tsx, sy = tsy, sz = tsz;
             const double an = sx * (double)ex + sy * (double)ey + sz * (double)ez;
             const double zn = sx * (double)nx + sy * (double)ny + sz * (double)nz;
-            // full rows count every bond from both ends (half each); half
-            // rows count it once, at the end it leaves
-            constexpr double kBond = HALF ? 1.0 : 0.5;
-            double e = -kBond * (sx * (double)thx + sy * (double)thy + sz * (double)thz) - a.B * zn -
-                       (double)k * an * an;
-            // cubic term of Eq. 3, -kc (Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2)
-            if (a.kc) e -= (double)kc * ((sx * sx * (sy * sy) + sy * sy * (sz * sz)) + sx * sx * (sz * sz));
-            ev[u] = ok ? e : 0.0;
+            if constexpr (!BWD) {
+                // full rows count every bond from both ends (half each); half
+                // rows count it once, at the end it leaves
+                constexpr double kBond = HALF ? 1.0 : 0.5;
+                double e = -kBond * (sx * (double)thx + sy * (double)thy + sz * (double)thz) -
+                           a.B * zn - (double)k * an * an;
+                // cubic term of Eq. 3, -kc (Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2)
+                if (a.kc) e -= (double)kc * ((sx * sx * (sy * sy) + sy * sy * (sz * sz)) + sx * sx * (sz * sz));
+                ev[u] = ok ? e : 0.0;
+            }
             zv[u] = ok ? zn : 0.0;
             if (BWD) {
                 const double gb = ok ? gE[b] : 0.0;
@@ -265,18 +267,19 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
                     // bonds whose lower end is i (padding: col == i, skipped)
 #pragma unroll
                     for (int q = 0; q < W; ++q) {
-                        const double d = sx * (double)nb[u][q][0] + sy * (double)nb[u][q][1] +
-                                         sz * (double)nb[u][q][2];
-                        gj[q] += col[q] > i ? gb * -d : 0.0;
+                        // the pair product in the spins' precision, summed in double
+                        const T d = tsx * nb[u][q][0] + tsy * nb[u][q][1] + tsz * nb[u][q][2];
+                        gj[q] += col[q] > i ? gb * -(double)d : 0.0;
                     }
                 }
             }
         }
-        const double es = halving_sum<kEU>(ev, ln);
         const int cw = c0 + halving_index<kEU>(ln);
         const bool wr = (ln & (64 / kEU - 1)) == 0 && cw < nc;
-        if (wr) ew[cw][wv] = es;
-        if (BWD) {
+        if constexpr (!BWD) {
+            const double es = halving_sum<kEU>(ev, ln);
+            if (wr) ew[cw][wv] = es;
+        } else {
             const double zs = halving_sum<kEU>(zv, ln);
             if (wr) zw[cw][wv] = zs;
         }
@@ -287,10 +290,10 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
         const size_t t = (size_t)b * ntile + tile;
         double et = 0.0, zt = 0.0;
         for (int q = 0; q < kW; ++q) {
-            et += ew[c][q];
+            if (!BWD) et += ew[c][q];
             if (BWD) zt += zw[c][q];
         }
-        if (partE) partE[t] = et;
+        if (!BWD && partE) partE[t] = et;
         if (BWD) partB[t] = -gE[b] * zt;
     }
     if (!params || !live) return;
@@ -436,6 +439,23 @@ __global__ __launch_bounds__(256) void k_energy_tiles(int cnt, int ntile, const 
     if (ln == 0) out[b] = v;
 }
 
+// Sum of column t of part [ngroups][stride] in group order; the loads of
+// eight groups are issued together, the additions stay in order.
+__device__ __forceinline__ double group_sum(const double *part, int ngroups, int64_t stride, int64_t t)
+{
+    double v = 0.0;
+    int g = 0;
+    for (; g + 8 <= ngroups; g += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = part[(size_t)(g + u) * stride + t];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += x[u];
+    }
+    for (; g < ngroups; ++g) v += part[(size_t)g * stride + t];
+    return v;
+}
+
 // dE/dk and dE/dJ of a pass: the groups' partials summed in order, added to
 // the sums of the earlier passes (first: start them); the last pass writes
 // the outputs in the inputs' precision.
@@ -447,15 +467,13 @@ __global__ __launch_bounds__(256) void k_energy_params(int64_t n, int64_t nb, in
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gJ && t < nb) {
-        double v = 0.0;
-        for (int g = 0; g < ngroups; ++g) v += partJ[(size_t)g * nb + t];
+        double v = group_sum(partJ, ngroups, nb, t);
         if (!first) v = accJ[t] + v;
         if (last) gJ[t] = (T)v;
         else accJ[t] = v;
     }
     if (gk && t < n) {
-        double v = 0.0;
-        for (int g = 0; g < ngroups; ++g) v += partK[(size_t)g * n + t];
+        double v = group_sum(partK, ngroups, n, t);
         if (!first) v = accK[t] + v;
         if (last) gk[t] = (T)v;
         else accK[t] = v;
