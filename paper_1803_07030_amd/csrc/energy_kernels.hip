@@ -194,9 +194,11 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
     const int b0 = grp * kEG;
     const int nc = min(kEG, a.batch - b0);
     const bool params = BWD && (partK || partJ);
-    double gk = 0.0, gj[W];
+    // dE/dk and dE/dJ of the group, summed over its configurations in the
+    // spins' precision (at most kEG terms), then handed on in double
+    T gk = T(0), gj[W];
 #pragma unroll
-    for (int q = 0; q < W; ++q) gj[q] = 0.0;
+    for (int q = 0; q < W; ++q) gj[q] = T(0);
 #pragma unroll 1
     for (int c0 = 0; c0 < nc; c0 += kEU) {
         double ev[kEU], zv[kEU];
@@ -263,13 +265,12 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
                     o[2 * a.n + i] = g * (-thz - B * nz - two_ka * ez - cz);
                 }
                 if (params) {
-                    gk += gb * -(an * an);
+                    gk += g * -(an_t * an_t);
                     // bonds whose lower end is i (padding: col == i, skipped)
 #pragma unroll
                     for (int q = 0; q < W; ++q) {
-                        // the pair product in the spins' precision, summed in double
                         const T d = tsx * nb[u][q][0] + tsy * nb[u][q][1] + tsz * nb[u][q][2];
-                        gj[q] += col[q] > i ? gb * -(double)d : 0.0;
+                        gj[q] += col[q] > i ? g * -d : T(0);
                     }
                 }
             }
@@ -297,11 +298,11 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
         if (BWD) partB[t] = -gE[b] * zt;
     }
     if (!params || !live) return;
-    if (partK) partK[(size_t)grp * a.n + i] = gk;
+    if (partK) partK[(size_t)grp * a.n + i] = (double)gk;
     if (!partJ) return;
 #pragma unroll
     for (int q = 0; q < W; ++q)
-        if (col[q] > i) partJ[(size_t)grp * a.nb + bid[q]] = gj[q];
+        if (col[q] > i) partJ[(size_t)grp * a.nb + bid[q]] = (double)gj[q];
 }
 
 // Rows longer than the padded width (any degree): grid (site tiles, chunks of
