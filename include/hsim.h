@@ -193,6 +193,17 @@ hsim_status hsim_batch_info(hsim_batch b, hsim_batch_info_t *out);
  * last bits may differ.  HSIM_E_UNSUPPORTED outside the replica layout.  May
  * be called while bound (the workspace covers every shape). */
 hsim_status hsim_batch_set_shape(hsim_batch b, int32_t sites_per_wave, int32_t masked_store);
+/* The replica layout's dispatch order of each colour's tiles inside an
+ * XCD's range (section "Monte Carlo Metropolis algorithm": the order of the
+ * updates inside a colour class is free).  plane_sites > 1: tiles are
+ * started in order of (tile mod p, tile / p), p = plane_sites / tile sites,
+ * so that tiles one plane of the class apart, which read the same neighbour
+ * rows, run together; 0: in order; -1 (the default): plane_sites derived
+ * from the lattice's neighbour offsets and used only when a colour has more
+ * tiles per XCD than the XCD runs at once.  Changes no result, spins or
+ * history (records are kept per tile).  HSIM_E_ARG for 1 or below -1,
+ * HSIM_E_UNSUPPORTED outside the replica layout. */
+hsim_status hsim_batch_set_order(hsim_batch b, int32_t plane_sites);
 
 /* Device bytes the caller must provide for a history of n_steps steps of
  * mcs_per_step MCS.  History layout: double [n_rep][n_steps][mcs_per_step][5]

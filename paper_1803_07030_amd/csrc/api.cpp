@@ -21,6 +21,7 @@ void energy_backward_impl(hsim_plan, int32_t, hsim_precision, const void *, cons
 hsim_batch batch_create_impl(int32_t, const hsim_plan *, uint64_t, const uint32_t *,
                              hsim_precision, hsim_layout);
 void batch_set_shape_impl(hsim_batch, int32_t, int32_t);
+void batch_set_order_impl(hsim_batch, int32_t);
 void batch_sizes_impl(hsim_batch, int32_t, int32_t, size_t *, size_t *, size_t *);
 void batch_bind_impl(hsim_batch, int32_t, int32_t, void *, void *, void *);
 void batch_init_impl(hsim_batch, int32_t, const double *, hipStream_t);
@@ -179,6 +180,11 @@ hsim_status hsim_batch_info(hsim_batch b, hsim_batch_info_t *out)
 hsim_status hsim_batch_set_shape(hsim_batch b, int32_t spw, int32_t masked)
 {
     return guarded([&] { batch_set_shape_impl(b, spw, masked); });
+}
+
+hsim_status hsim_batch_set_order(hsim_batch b, int32_t plane_sites)
+{
+    return guarded([&] { batch_set_order_impl(b, plane_sites); });
 }
 
 hsim_status hsim_batch_sizes(hsim_batch b, int32_t n_steps, int32_t mcs, size_t *ws, size_t *sp,

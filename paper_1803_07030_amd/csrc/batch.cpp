@@ -4,6 +4,7 @@
 // package": history after every MCS of every temperature/field step).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <limits>
@@ -113,6 +114,78 @@ RepTiling rep_tiling(hsim_batch b, int spw)
 
 }  // namespace
 
+// Distance, in sites of a colour class, at which two sites of the class share
+// a neighbour a plane apart: the 95th percentile of the class-position
+// offsets between neighbours (a periodic wrap is rare, the largest regular
+// offset common).  On a simple-cubic L^3 lattice it is L^2 / 2, the sites of
+// one class in one plane.
+int64_t derive_plane_sites(hsim_plan P)
+{
+    if (P->ncol < 2 || P->n == 0) return 0;
+    std::vector<int32_t> cls(P->n);
+    for (int c = 0; c < P->ncol; ++c)
+        for (int32_t t = P->cls_off[c]; t < P->cls_off[c + 1]; ++t) cls[t] = c;
+    const int32_t n0 = P->cls_off[1];
+    const int32_t step = std::max<int32_t>(1, n0 / 65536);
+    std::vector<int64_t> d;
+    for (int32_t t = 0; t < n0; t += step)
+        for (int32_t p = P->rp[t]; p < P->rp[t + 1]; ++p) {
+            const int32_t j = P->ci[p];
+            d.push_back(std::llabs((int64_t)(j - P->cls_off[cls[j]]) - (int64_t)t));
+        }
+    if (d.empty()) return 0;
+    const size_t k = d.size() * 95 / 100;
+    std::nth_element(d.begin(), d.begin() + k, d.end());
+    return d[k];
+}
+
+// Dispatch order of the replica layout's tiles inside each XCD's range:
+// ordered by (tile mod pt, tile / pt), pt = tiles per plane of the class, so
+// that tiles one plane apart, which read the same neighbour rows, start
+// together instead of a plane of traffic apart.  Results do not depend on it
+// (records are kept per tile).  Used when a colour has more tiles per XCD
+// than the XCD runs at once (8 blocks per CU).
+void rep_order(hsim_batch b)
+{
+    b->tord.clear();
+    int64_t ps = 0;
+    if (b->order_mode > 1) ps = b->order_mode;
+    else if (b->order_mode < 0) {
+        if (b->plane_sites < 0) b->plane_sites = derive_plane_sites(b->plans[0]);
+        int max_nt = 0;
+        for (int c = 0; c < b->plans[0]->ncol; ++c)
+            max_nt = std::max(max_nt, b->la.tile_off[c + 1] - b->la.tile_off[c]);
+        const int cus = device_cus() > 0 ? device_cus() : 256;
+        if (max_nt / 8 > cus) ps = b->plane_sites;
+    }
+    const int64_t tile_sites = (int64_t)hsim::kRepWaves * b->la.spw;
+    const int pt = (int)((ps + tile_sites / 2) / tile_sites);
+    if (pt >= 2) {
+        const int C = b->plans[0]->ncol;
+        b->tord.resize((size_t)b->rep_ntiles);
+        for (int c = 0; c < C; ++c) {
+            const int t0 = b->la.tile_off[c], nt = b->la.tile_off[c + 1] - t0;
+            const int q = nt >> 3, rm = nt & 7;   // the XCD ranges of xcd_tile
+            for (int x = 0; x < 8; ++x) {
+                const int s = x * q + std::min(x, rm), len = q + (x < rm ? 1 : 0);
+                std::vector<int32_t> r(len);
+                for (int k = 0; k < len; ++k) r[k] = s + k;
+                std::stable_sort(r.begin(), r.end(), [pt](int32_t u, int32_t v) {
+                    return std::make_pair(u % pt, u / pt) < std::make_pair(v % pt, v / pt);
+                });
+                for (int k = 0; k < len; ++k) b->tord[(size_t)t0 + s + k] = r[k];
+            }
+        }
+    }
+    if (b->tables_on_device) {
+        if (b->tord.empty()) b->la.tord = nullptr;
+        else {
+            b->d_tord.upload(b->tord);
+            b->la.tord = (const int32_t *)b->d_tord.p;
+        }
+    }
+}
+
 // The replica layout's tile shape; the workspace is sized for every shape
 // the autotuner may pick, so a bound batch can switch.
 void set_rep_tiles(hsim_batch b, int spw)
@@ -122,6 +195,17 @@ void set_rep_tiles(hsim_batch b, int spw)
     for (int c = 0; c <= hsim::kMaxColours; ++c) b->la.tile_off[c] = c <= b->plans[0]->ncol ? t.tile_off[c] : 0;
     b->rep_ntiles = t.ntiles;
     b->rec_win = t.rec_win;
+    rep_order(b);
+    b->drop_graph();
+}
+
+void batch_set_order_impl(hsim_batch b, int32_t plane_sites)
+{
+    if (!b) throw Error(HSIM_E_ARG, "set_order: NULL batch");
+    if (b->layout != HSIM_LAYOUT_REPLICA) throw Error(HSIM_E_UNSUPPORTED, "set_order: replica layout only");
+    if (plane_sites < -1 || plane_sites == 1) throw Error(HSIM_E_ARG, "set_order: bad plane stride");
+    b->order_mode = plane_sites;
+    rep_order(b);
     b->drop_graph();
 }
 
@@ -336,6 +420,11 @@ void hsim_batch_s::upload_tables()
         la.ncol = P->ncol;
         la.ell_w = P->ell_w;
         for (int c = 0; c <= P->ncol; ++c) la.cls_off[c] = P->cls_off[c];
+        if (tord.empty()) la.tord = nullptr;
+        else {
+            d_tord.upload(tord);
+            la.tord = (const int32_t *)d_tord.p;
+        }
     } else {
         reps.assign(R, hsim::RepDesc{});
         int64_t uoff = 0;

@@ -143,6 +143,9 @@ struct RepLaneArgs {
     int32_t ncol, ell_w;        // ell_w: padded row width (6 or 8), 0 = CSR walk
     int32_t cls_off[kMaxColours + 1];
     int32_t tile_off[kMaxColours + 1];   // first tile of each colour
+    // dispatch order: slot u of colour c (after the XCD split) runs tile
+    // tord[tile_off[c] + u] of the class; NULL: tile u
+    const int32_t *tord;
 };
 
 // XCD-aware bijection of [0, nt): blocks are dispatched round-robin over the

@@ -167,6 +167,14 @@ struct hsim_batch_s {
                 (size_t)hsim::kChunks) * Rp * 8;
     }
     hsim::RepLaneArgs la{};
+    // replica layout: dispatch order of each colour's tiles (see rep_order):
+    // order_mode -1 derives the plane stride from the lattice and uses it on
+    // lattices too large to have every tile of a colour in flight, 0 keeps
+    // the tiles in order, > 1 is the plane stride in sites
+    int32_t order_mode = -1;
+    int64_t plane_sites = -1;    // derived once (0: none found)
+    std::vector<int32_t> tord;
+    hsim::DevBuf d_tord;
 
     hsim::DevBuf d_reps, d_tiles, d_rep_tiles, d_rep_id;
     bool tables_on_device = false;

@@ -664,8 +664,9 @@ __global__ __launch_bounds__(kRepThreads) void k_rep_phase(RepLaneArgs a, int co
     __shared__ double red[kRedDoubles];
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     const int nt = a.tile_off[colour + 1] - a.tile_off[colour];
-    rep_tile<KM, FM, W, MAXD, VAR>(a, colour, xcd_tile(blockIdx.x, nt), blockIdx.y, g, ra,
-                                   rep_slot(ra, a, ntiles, t_off % ra.rec_win), red);
+    const int u = xcd_tile(blockIdx.x, nt);
+    rep_tile<KM, FM, W, MAXD, VAR>(a, colour, a.tord ? a.tord[a.tile_off[colour] + u] : u, blockIdx.y, g,
+                                   ra, rep_slot(ra, a, ntiles, t_off % ra.rec_win), red);
 }
 
 // Adaptive widths after MCS t_off of the sequence: the accepted adaptive
@@ -979,8 +980,11 @@ __global__ __launch_bounds__(kRepThreads) void k_rep_persistent(RepLaneArgs a, i
         }
         for (int c = 0; c < a.ncol; ++c) {
             const int nt = a.tile_off[c + 1] - a.tile_off[c];
-            for (XcdRange it(nt * groups, xb); it.u < it.end; it.u += it.step)
-                rep_tile<KM, FM, W, MAXD>(a, c, it.u % nt, it.u / nt, g, ra, part, red);
+            for (XcdRange it(nt * groups, xb); it.u < it.end; it.u += it.step) {
+                const int u = it.u % nt;
+                rep_tile<KM, FM, W, MAXD>(a, c, a.tord ? a.tord[a.tile_off[c] + u] : u, it.u / nt, g, ra,
+                                          part, red);
+            }
             xcd_barrier(ra.ctl, xb, epoch, cap);
             // the chunk sums of the previous MCS are complete once colour 0
             // of this one is: the last block adds them and writes its history

@@ -66,6 +66,7 @@ _SIGNATURES = {
     "hsim_batch_create": [_vp, _i32, _vp, _u64, _vp, _i32, _i32],
     "hsim_batch_info": [_vp, _vp],
     "hsim_batch_set_shape": [_vp, _i32, _i32],
+    "hsim_batch_set_order": [_vp, _i32],
     "hsim_batch_sizes": [_vp, _i32, _i32, _vp, _vp, _vp],
     "hsim_batch_bind": [_vp, _i32, _i32, _vp, _vp, _vp],
     "hsim_batch_init_spins": [_vp, _i32, _vp, _vp],
@@ -210,6 +211,10 @@ def hsim_batch_info(batch):
 
 def hsim_batch_set_shape(batch, sites_per_wave, masked_store):
     _check(lib().hsim_batch_set_shape(batch, sites_per_wave, masked_store))
+
+
+def hsim_batch_set_order(batch, plane_sites):
+    _check(lib().hsim_batch_set_order(batch, plane_sites))
 
 
 def hsim_batch_sizes(batch, n_steps, mcs):
@@ -475,6 +480,11 @@ class Batch:
         """Replica layout: tile shape and store policy (the tuner's knobs)."""
         hsim_batch_set_shape(self.handle, sites_per_wave, masked_store)
         self.info = hsim_batch_info(self.handle)
+
+    def set_order(self, plane_sites):
+        """Replica layout: dispatch order of the tiles (-1 derived, 0 in order,
+        > 1 plane stride in sites of a class); changes no result."""
+        hsim_batch_set_order(self.handle, plane_sites)
 
     def set_policies(self, policies, sigma_min=SIGMA_MIN, sigma_max=SIGMA_MAX):
         """policies: list of (POLICY_*, param) per site type; [] for the

@@ -121,6 +121,36 @@ def test_tile_shapes_and_store_policies_give_identical_spins(R):
                 assert np.allclose(got[1], ref[1], rtol=0, atol=1e-9 * lat.n), (spw, masked, launch)
 
 
+@pytest.mark.parametrize("spw", [8, 32])
+def test_tile_dispatch_order_changes_nothing(spw):
+    """The replica layout's tile dispatch order (tiles one plane of the class
+    apart started together; explicit plane strides and the derived one) in
+    plain, graph and persistent launches: spins and history bit-identical to
+    tiles in order (records are kept per tile)."""
+    lat = synth.sc_periodic(24)
+    lat.k = np.full(lat.n, 0.1)
+    plan = hsim.Plan(lat)
+    R, M = 64, 8
+    T = np.linspace(0.3, 2.8, R)[:, None]
+    ref = None
+    for order in (0, 288, 96, -1):
+        for launch in (hsim.LAUNCH_PLAIN, hsim.LAUNCH_GRAPH, hsim.LAUNCH_PERSISTENT):
+            b = hsim.Batch([plan] * R, seed=12, precision=hsim.FP32,
+                           layout=hsim.LAYOUT_REPLICA).bind(1, M)
+            b.set_shape(spw, 0)
+            b.set_order(order)
+            b.init_spins(hsim.INIT_RANDOM)
+            b.run(T, 0.1, recompute_every=3, launch=launch)
+            torch.cuda.synchronize()
+            assert b.status() == 0
+            got = (_user(b, R), b.history.cpu().numpy())
+            if ref is None:
+                ref = got
+                continue
+            assert np.array_equal(got[0], ref[0]), (order, launch)
+            assert np.array_equal(got[1], ref[1]), (order, launch)
+
+
 # ------------------------------------------------ more than 64 replicas
 def test_replica_layout_two_lane_columns():
     """R = 100 (128 lanes): the same spins as the site layout after 8 MCS in

@@ -157,8 +157,13 @@ def test_batch_layouts_sizes_and_errors():
     assert b.layout == "replica"
     ws, sp, hi = hsim.hsim_batch_sizes(b.handle, 1, 10000)
     assert sp == 3 * 64 ** 3 * 64 * 4 and hi == 64 * 10000 * 5 * 8
+    for order in (0, -1, 2048):
+        b.set_order(order)
+    _expect(-1, lambda: b.set_order(1))
+    _expect(-1, lambda: b.set_order(-2))
     b = hsim.Batch([big], seed=1, precision=hsim.FP32)
     assert b.layout == "site"
+    _expect(-6, lambda: b.set_order(0))
     _expect(-6, lambda: hsim.Batch([big] * 4, seed=0, precision=hsim.FP64_EXACT,
                                    layout=hsim.LAYOUT_REPLICA))
     _expect(-6, lambda: hsim.Batch([big, sc], seed=0, layout=hsim.LAYOUT_REPLICA))
