@@ -191,7 +191,8 @@ hsim_status hsim_batch_info(hsim_batch b, hsim_batch_info_t *out);
  * masked_store 0 or 1.  Neither changes any spin: every site's update is
  * the same computation; the history's sums are grouped by tiles, so their
  * last bits may differ.  HSIM_E_UNSUPPORTED outside the replica layout.  May
- * be called while bound (the workspace covers every shape). */
+ * be called while bound (the workspace covers every shape); a new shape
+ * waits for the device before it replaces the tile order table. */
 hsim_status hsim_batch_set_shape(hsim_batch b, int32_t sites_per_wave, int32_t masked_store);
 /* The replica layout's dispatch order of each colour's tiles inside an
  * XCD's range (section "Monte Carlo Metropolis algorithm": the order of the
@@ -202,7 +203,9 @@ hsim_status hsim_batch_set_shape(hsim_batch b, int32_t sites_per_wave, int32_t m
  * from the lattice's neighbour offsets and used only when a colour has more
  * tiles per XCD than the XCD runs at once.  Changes no result, spins or
  * history (records are kept per tile).  HSIM_E_ARG for 1 or below -1,
- * HSIM_E_UNSUPPORTED outside the replica layout. */
+ * HSIM_E_UNSUPPORTED outside the replica layout.  On a bound batch it waits
+ * for the device before it replaces the order table (as hsim_batch_set_shape
+ * does when the shape changes). */
 hsim_status hsim_batch_set_order(hsim_batch b, int32_t plane_sites);
 
 /* Device bytes the caller must provide for a history of n_steps steps of

@@ -178,8 +178,12 @@ void rep_order(hsim_batch b)
         }
     }
     if (b->tables_on_device) {
-        if (b->tord.empty()) b->la.tord = nullptr;
-        else {
+        // launches already enqueued may still read the old table
+        if (b->d_tord.p) hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        if (b->tord.empty()) {
+            b->la.tord = nullptr;
+            b->d_tord.release();
+        } else {
             b->d_tord.upload(b->tord);
             b->la.tord = (const int32_t *)b->d_tord.p;
         }
@@ -195,8 +199,8 @@ void set_rep_tiles(hsim_batch b, int spw)
     for (int c = 0; c <= hsim::kMaxColours; ++c) b->la.tile_off[c] = c <= b->plans[0]->ncol ? t.tile_off[c] : 0;
     b->rep_ntiles = t.ntiles;
     b->rec_win = t.rec_win;
+    b->drop_graph();   // waits for replays that read the old order table
     rep_order(b);
-    b->drop_graph();
 }
 
 void batch_set_order_impl(hsim_batch b, int32_t plane_sites)
@@ -205,8 +209,8 @@ void batch_set_order_impl(hsim_batch b, int32_t plane_sites)
     if (b->layout != HSIM_LAYOUT_REPLICA) throw Error(HSIM_E_UNSUPPORTED, "set_order: replica layout only");
     if (plane_sites < -1 || plane_sites == 1) throw Error(HSIM_E_ARG, "set_order: bad plane stride");
     b->order_mode = plane_sites;
+    b->drop_graph();   // waits for replays that read the old order table
     rep_order(b);
-    b->drop_graph();
 }
 
 void batch_set_shape_impl(hsim_batch b, int32_t spw, int32_t masked)
