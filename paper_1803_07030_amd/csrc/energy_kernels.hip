@@ -15,7 +15,10 @@
 // read as padded rows (slot-major, padding = the site itself with constant
 // 0, which leaves every sum unchanged), so each configuration's gathers are
 // issued together without branches; kEU configurations are in flight at
-// once.  The lattice tables of a site are read once per group.  Sums over
+// once.  The forward, which needs every bond once, reads half rows (the
+// bonds each site leaves under the plan's Euler orientation) and counts each
+// bond term whole; the backward reads full rows, since dE/dS needs every
+// neighbour.  The lattice tables of a site are read once per group.  Sums over
 // sites and configurations are double precision in a fixed order: lanes by
 // recursive halving, waves in order, tiles lane-strided then butterfly,
 // groups and passes in order.  Batches larger than the plan's pass size run
