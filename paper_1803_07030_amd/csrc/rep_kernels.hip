@@ -12,8 +12,10 @@
 //
 // A tile is kRepWaves * spw consecutive sites of one colour class (spw =
 // kRepSitesPerWave, or fewer for small lattices); wave w of the tile's block
-// takes spw of them in order (kRepSitesPerStep at
-// a time with 64-lane groups, two at a time with 32-lane groups).
+// takes spw of them in order (kRepSitesPerStep at a time with 64-lane
+// groups, two at a time with 32-lane groups).  Each XCD takes a contiguous
+// range of a colour's tiles; inside it an optional order table starts tiles
+// one plane of the class apart together (large lattices).
 // Per-MCS history: every tile writes one record per replica; records are
 // summed in 64 fixed chunks of tiles, and the chunks in order, the same way in
 // every launch mode.  Plain and graph launches keep the records of a window of
