@@ -500,7 +500,10 @@ hsim::EnergyArgs energy_args(hsim_plan P, int32_t batch, const void *S, const vo
     a.nb = P->nb;
     a.batch = batch;
     a.S = S;
-    a.Jb = Jb;
+    // the padded-row kernels read Jb[0] for empty slots (and discard it);
+    // without bonds the caller may pass no array, so point them at a table
+    // of the plan that holds at least one element
+    a.Jb = P->nb > 0 ? Jb : P->d_uell_bond.p;
     a.k = k;
     a.ax = ax;
     a.nd = nd;

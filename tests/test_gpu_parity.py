@@ -302,7 +302,7 @@ def _degree8_lattice(n=400, seed=11):
     return lat
 
 
-@pytest.mark.parametrize("kind", ["film", "deg8"])
+@pytest.mark.parametrize("kind", ["film", "deg8", "isolated", "chain"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_energy_forward_from_half_rows(kind, dtype):
     """The forward reads each bond once, from half rows that an Euler
@@ -313,8 +313,15 @@ def test_energy_forward_from_half_rows(kind, dtype):
     if kind == "film":
         lat = synth.diluted_film(21, 5, seed=12)
         lat.ndir = synth.unit_vectors(12, lat.n, tag=3)
-    else:
+    elif kind == "deg8":
         lat = _degree8_lattice()
+    else:
+        # no bonds (every half-row slot empty), or an open chain (the ends
+        # have odd degree)
+        lat = synth.isolated(300) if kind == "isolated" else synth.open_chain(301)
+        lat.k = synth.uniform01(14, lat.n, tag=1)
+        lat.axis = synth.unit_vectors(14, lat.n, tag=2)
+        lat.ndir = synth.unit_vectors(14, lat.n, tag=3)
     plan = hsim.Plan(lat)
     nbatch = 40
     S = synth.random_spins(13, lat.n, batch=nbatch)

@@ -121,16 +121,17 @@ def test_tile_shapes_and_store_policies_give_identical_spins(R):
                 assert np.allclose(got[1], ref[1], rtol=0, atol=1e-9 * lat.n), (spw, masked, launch)
 
 
-@pytest.mark.parametrize("spw", [8, 32])
-def test_tile_dispatch_order_changes_nothing(spw):
+@pytest.mark.parametrize("spw,R", [(8, 64), (32, 64), (4, 100)])
+def test_tile_dispatch_order_changes_nothing(spw, R):
     """The replica layout's tile dispatch order (tiles one plane of the class
     apart started together; explicit plane strides and the derived one) in
-    plain, graph and persistent launches: spins and history bit-identical to
-    tiles in order (records are kept per tile)."""
+    plain, graph and persistent launches, with 64-lane rows and with two
+    lane columns (R = 100): spins and history bit-identical to tiles in order
+    (records are kept per tile)."""
     lat = synth.sc_periodic(24)
     lat.k = np.full(lat.n, 0.1)
     plan = hsim.Plan(lat)
-    R, M = 64, 8
+    M = 8
     T = np.linspace(0.3, 2.8, R)[:, None]
     ref = None
     for order in (0, 288, 96, -1):
