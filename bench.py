@@ -310,9 +310,9 @@ def b_alg_site_lane(zbar, a):
 def films_bench(args, stream):
     """256 diluted films (L in 16..128, d in 2..10, 10% vacancies, per-bond J
     in [0.5, 1.5], K = 0.05 z), each film one replica at its own temperature
-    in [0.2, 2.0], single precision, site-lane layout.  Plain launches time
-    the colour-phase launches of every n-th MCS; graph and autotuned launches
-    are timed per step."""
+    in [0.2, 2.0], single precision, site-lane layout.  The roofline is taken
+    over the whole step; plain launches also time the colour-phase launches
+    of every n-th MCS."""
     import torch
     import synth
     from paper_1803_07030_amd import hsim
@@ -351,11 +351,17 @@ def films_bench(args, stream):
         hist = batch.history.cpu().numpy()
     acc = float(hist[..., 4].sum() / (nsites * mcs))
     balg = b_alg_site_lane(zbar, acc)
-    if timed_phases:
-        kernel, launch_ms, upd, n_timed = "k_site_phase", ph_ms / ph_n, ph_upd / ph_n, ph_n
-    else:
-        kernel, launch_ms, upd, n_timed = "step", wall / args.steps * 1e3, nsites * mcs, args.steps
+    # the films with trailing colour classes and the others run as two groups
+    # on two streams, so single phase launches overlap the other group's
+    # work: the roofline is taken over the whole step, and the sampled
+    # phase-launch times are reported beside it
+    kernel, launch_ms, upd, n_timed = "step", wall / args.steps * 1e3, nsites * mcs, args.steps
     achieved = balg * upd / (launch_ms / 1e3) / 1e9
+    phases = None
+    if timed_phases:
+        phases = {"kernel": "k_site_phase", "launch_ms": ph_ms / ph_n, "updates_per_launch": ph_upd / ph_n,
+                  "timed_launches": ph_n,
+                  "achieved_GBps": balg * (ph_upd / ph_n) / (ph_ms / ph_n / 1e3) / 1e9}
     print(json.dumps({
         "metric": "spin updates/sec, site-lane films batch", "value": nsites * mcs * args.steps / wall,
         "unit": "spin updates/s", "steps": args.steps, "warmup": args.warmup,
@@ -368,7 +374,8 @@ def films_bench(args, stream):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "kernel": kernel,
                      "launch_ms": launch_ms, "updates_per_launch": upd,
-                     "bytes_per_update": balg, "timed_launches": n_timed}}))
+                     "bytes_per_update": balg, "timed_launches": n_timed},
+        "phase_launches": phases}))
 
 
 def ball_bench(args, stream):

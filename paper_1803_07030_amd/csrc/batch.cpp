@@ -64,6 +64,12 @@ void hsim_batch_s::drop_graph()
 hsim_batch_s::~hsim_batch_s()
 {
     drop_graph();
+    for (int g = 0; g < 2; ++g) {
+        if (gstream[g]) (void)hipStreamSynchronize(gstream[g]);
+        if (gjoin[g]) (void)hipEventDestroy(gjoin[g]);
+        if (gstream[g]) (void)hipStreamDestroy(gstream[g]);
+    }
+    if (gfork) (void)hipEventDestroy(gfork);
     if (g_done) (void)hipEventDestroy(g_done);
     if (g_cap) (void)hipStreamDestroy(g_cap);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -318,30 +324,47 @@ hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
             b->spin_elems = off;
             if (lay == HSIM_LAYOUT_SITE) {
                 const int C = b->ncol_max;
-                b->tile_off.assign(C + 1, 0);
-                b->rep_tiles.assign((size_t)R * C * 2, 0);
-                for (int c = 0; c < C; ++c) {
-                    b->tile_off[c] = (int32_t)b->tiles.size();
-                    for (int r = 0; r < R; ++r) {
-                        hsim_plan P = plans[r];
-                        const int32_t t0 = (int32_t)b->tiles.size();
-                        if (c < P->ncol)
-                            for (int32_t s = P->cls_off[c]; s < P->cls_off[c + 1]; s += hsim::kSiteBlock)
-                                b->tiles.push_back({r, s, std::min(s + hsim::kSiteBlock, P->cls_off[c + 1]), c});
-                        b->rep_tiles[((size_t)r * C + c) * 2] = t0;
-                        b->rep_tiles[((size_t)r * C + c) * 2 + 1] = (int32_t)b->tiles.size();
-                    }
-                }
-                b->tile_off[C] = (int32_t)b->tiles.size();
-                if (b->tiles.size() > (size_t)INT32_MAX / 2) throw Error(HSIM_E_UNSUPPORTED, "too many tiles");
                 // trailing colour classes beyond the first two with fewer than
                 // two tiles per CU run inside the per-replica finish launch
                 // instead of a launch each (the extra colours of odd-size
                 // films: a few tiles per film, latency-bound as phases)
+                std::vector<int64_t> ct(C, 0);
+                for (int r = 0; r < R; ++r)
+                    for (int c = 0; c < plans[r]->ncol; ++c)
+                        ct[c] += (plans[r]->cls_off[c + 1] - plans[r]->cls_off[c] + hsim::kSiteBlock - 1) /
+                                 hsim::kSiteBlock;
                 const int cus = device_cus() > 0 ? device_cus() : 256;
                 b->c_tail = C;
-                while (b->c_tail > 2 && b->tile_off[b->c_tail] - b->tile_off[b->c_tail - 1] < 2 * cus)
-                    --b->c_tail;
+                while (b->c_tail > 2 && ct[b->c_tail - 1] < 2 * cus) --b->c_tail;
+                // two groups when both are non-empty
+                for (int r = 0; r < R; ++r) b->grp_reps[plans[r]->ncol > b->c_tail ? 1 : 0].push_back(r);
+                b->ngroups = (!b->grp_reps[0].empty() && !b->grp_reps[1].empty()) ? 2 : 1;
+                if (b->ngroups == 1) {
+                    b->grp_reps[0].clear();
+                    b->grp_reps[1].clear();
+                    for (int r = 0; r < R; ++r) b->grp_reps[0].push_back(r);
+                }
+                b->rep_tiles.assign((size_t)R * C * 2, 0);
+                for (int g = 0; g < b->ngroups; ++g) {
+                    b->gtile_off[g].assign(C + 1, 0);
+                    b->gunits[g].assign(C, 0);
+                    for (int c = 0; c < C; ++c) {
+                        b->gtile_off[g][c] = (int32_t)b->tiles.size();
+                        for (int r : b->grp_reps[g]) {
+                            hsim_plan P = plans[r];
+                            const int32_t t0 = (int32_t)b->tiles.size();
+                            if (c < P->ncol) {
+                                b->gunits[g][c] += P->cls_off[c + 1] - P->cls_off[c];
+                                for (int32_t s = P->cls_off[c]; s < P->cls_off[c + 1]; s += hsim::kSiteBlock)
+                                    b->tiles.push_back({r, s, std::min(s + hsim::kSiteBlock, P->cls_off[c + 1]), c});
+                            }
+                            b->rep_tiles[((size_t)r * C + c) * 2] = t0;
+                            b->rep_tiles[((size_t)r * C + c) * 2 + 1] = (int32_t)b->tiles.size();
+                        }
+                    }
+                    b->gtile_off[g][C] = (int32_t)b->tiles.size();
+                }
+                if (b->tiles.size() > (size_t)INT32_MAX / 2) throw Error(HSIM_E_UNSUPPORTED, "too many tiles");
             } else {
                 b->lds = fits_lds;
                 b->lds_bytes = (size_t)(3 * pad64(max_n)) * elem;
@@ -467,6 +490,7 @@ void hsim_batch_s::upload_tables()
         if (layout == HSIM_LAYOUT_SITE) {
             d_tiles.upload(tiles);
             d_rep_tiles.upload(rep_tiles);
+            for (int g = 0; g < ngroups; ++g) d_grp_reps[g].upload(grp_reps[g]);
         }
     }
     tables_on_device = true;
@@ -693,7 +717,8 @@ struct PhaseTimer {
     hipStream_t st;
     hipEvent_t e1 = nullptr;
     int64_t units = 0;
-    PhaseTimer(hsim_batch b_, hipStream_t st_, bool on, int colour) : b(b_), st(st_)
+    PhaseTimer(hsim_batch b_, hipStream_t st_, bool on, int colour, int64_t units_ = -1)
+        : b(b_), st(st_)
     {
         if (!on) return;
         if (b->ev_used + 2 > b->ev_pool.size()) {
@@ -706,7 +731,7 @@ struct PhaseTimer {
         }
         hipEvent_t e0 = b->ev_pool[b->ev_used++];
         e1 = b->ev_pool[b->ev_used++];
-        units = b->phase_updates(colour);
+        units = units_ >= 0 ? units_ : b->phase_updates(colour);
         hip_check(hipEventRecord(e0, st), "hipEventRecord");
     }
     ~PhaseTimer() noexcept(false)
@@ -738,33 +763,69 @@ void enqueue_outputs(hsim_batch b, const hsim::RunArgs &ra, int t, uint32_t gb, 
     }
 }
 
+// Site layout, one group's MCS t of a sequence: the energy recompute when
+// due, the colour phases below c_tail, the finish launch (trailing classes
+// and history) of the group's replicas.
 template <typename F>
-void enqueue_site_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F efull_mask,
-                           hipStream_t st, uint32_t gb, bool dev_check)
+void enqueue_site_mcs(hsim_batch b, const hsim::RunArgs &ra, int g, int t, F efull_mask, hipStream_t st)
 {
     const auto *reps = (const hsim::RepDesc *)b->d_reps.p;
     const auto *tiles = (const hsim::Tile *)b->d_tiles.p;
-    for (int t = 0; t < count; ++t) {
-        if (efull_mask(t))
-            hip_check(hsim::launch_site_efull(st, b->f64, b->kmode, b->fmode, reps, tiles,
-                                              (int)b->tiles.size(), t, ra),
-                      "efull launch");
-        const bool timed = b->time_every > 0 && t % b->time_every == 0;
-        for (int c = 0; c < b->c_tail; ++c) {
-            PhaseTimer pt(b, st, timed, c);
-            hip_check(hsim::launch_site_phase(st, b->f64, b->kmode, b->fmode, ra.trace != nullptr,
-                                              b->ellw, reps, tiles, b->tile_off[c],
-                                              b->tile_off[c + 1] - b->tile_off[c], t, ra),
-                      "phase launch");
-        }
-        // trailing small colours and the per-MCS history
-        hip_check(hsim::launch_site_finish(st, b->f64, b->kmode, b->fmode, ra.trace != nullptr, b->ellw,
-                                           reps, (const int32_t *)b->d_rep_tiles.p, b->ncol_max,
-                                           b->c_tail, t, ra),
-                  "finish launch");
-        enqueue_outputs(b, ra, t, gb, dev_check, st);
+    const std::vector<int32_t> &to = b->gtile_off[g];
+    const int C = b->ncol_max;
+    if (efull_mask(t))
+        hip_check(hsim::launch_site_efull(st, b->f64, b->kmode, b->fmode, reps, tiles, to[0], to[C] - to[0],
+                                          t, ra),
+                  "efull launch");
+    const bool timed = b->time_every > 0 && t % b->time_every == 0;
+    for (int c = 0; c < b->c_tail; ++c) {
+        PhaseTimer pt(b, st, timed && to[c + 1] > to[c], c, b->gunits[g][c]);
+        hip_check(hsim::launch_site_phase(st, b->f64, b->kmode, b->fmode, ra.trace != nullptr, b->ellw, reps,
+                                          tiles, to[c], to[c + 1] - to[c], t, ra),
+                  "phase launch");
     }
-    if (count > 0) hip_check(hsim::launch_ctl_advance(st, ra.ctl, (uint32_t)count), "control launch");
+    hip_check(hsim::launch_site_finish(st, b->f64, b->kmode, b->fmode, ra.trace != nullptr, b->ellw, reps,
+                                       (const int32_t *)b->d_rep_tiles.p,
+                                       b->ngroups > 1 ? (const int32_t *)b->d_grp_reps[g].p : nullptr,
+                                       (int)b->grp_reps[g].size(), b->ncol_max, b->c_tail, t, ra),
+              "finish launch");
+}
+
+// Site layout: MCS t_off = 0..count-1 of a launch sequence starting at
+// ctl->g, then ctl->g moves on.  With two groups and no per-MCS outputs the
+// groups run their sequences on the batch's two streams, forked from st and
+// joined back into it (also inside a capture, where the fork and join become
+// graph edges); otherwise both groups' launches go to st, MCS by MCS.
+// Optional outputs after MCS t of a sequence: per-type magnetisation; the
+// spins at a step end, which the host knows from the sequence's first MCS gb
+// (plain launches) or the device checks (dev_check: captured graphs).
+template <typename F>
+void enqueue_site_sequence(hsim_batch b, const hsim::RunArgs &ra, int count, F efull_mask,
+                           hipStream_t st, uint32_t gb, bool dev_check, bool split)
+{
+    if (count <= 0) return;
+    if (split && b->ngroups > 1) {
+        if (!b->gfork) {
+            hip_check(hipEventCreateWithFlags(&b->gfork, hipEventDisableTiming), "hipEventCreate");
+            for (int g = 0; g < 2; ++g) {
+                hip_check(hipEventCreateWithFlags(&b->gjoin[g], hipEventDisableTiming), "hipEventCreate");
+                hip_check(hipStreamCreateWithFlags(&b->gstream[g], hipStreamNonBlocking), "hipStreamCreate");
+            }
+        }
+        hip_check(hipEventRecord(b->gfork, st), "hipEventRecord");
+        for (int g = 0; g < 2; ++g) {
+            hip_check(hipStreamWaitEvent(b->gstream[g], b->gfork, 0), "hipStreamWaitEvent");
+            for (int t = 0; t < count; ++t) enqueue_site_mcs(b, ra, g, t, efull_mask, b->gstream[g]);
+            hip_check(hipEventRecord(b->gjoin[g], b->gstream[g]), "hipEventRecord");
+            hip_check(hipStreamWaitEvent(st, b->gjoin[g], 0), "hipStreamWaitEvent");
+        }
+    } else {
+        for (int t = 0; t < count; ++t) {
+            for (int g = 0; g < b->ngroups; ++g) enqueue_site_mcs(b, ra, g, t, efull_mask, st);
+            enqueue_outputs(b, ra, t, gb, dev_check, st);
+        }
+    }
+    hip_check(hsim::launch_ctl_advance(st, ra.ctl, (uint32_t)count), "control launch");
 }
 
 // Replica layout: MCS t_off = 0..count-1 of a launch sequence starting at
@@ -805,13 +866,26 @@ bool due(uint32_t g, int M, int P)
     return m == 0 || (P > 0 && m % (uint32_t)P == 0);
 }
 
+// Whether the site layout's groups may run on the batch's own streams: two
+// groups, no per-MCS outputs (they read every replica after each MCS), and st
+// not recording into a caller's graph (the library's own capture, in
+// run_graph, forks and joins its streams inside the capture).
+bool split_ok(hsim_batch b, hipStream_t st, bool own_capture)
+{
+    if (b->ngroups < 2 || b->type_mag || b->snapshots) return false;
+    if (own_capture || st == nullptr) return true;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hip_check(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing");
+    return cs == hipStreamCaptureStatusNone;
+}
+
 void run_plain(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st, int from, int to)
 {
     // ctl->g is at g0 + from here
     const uint32_t gb = ra.g0 + (uint32_t)from;
     auto mask = [&](int t) { return due(gb + (uint32_t)t, ra.M, ra.P); };
     if (b->layout == HSIM_LAYOUT_REPLICA) enqueue_rep_sequence(b, ra, to - from, mask, st, gb, false);
-    else enqueue_site_sequence(b, ra, to - from, mask, st, gb, false);
+    else enqueue_site_sequence(b, ra, to - from, mask, st, gb, false, split_ok(b, st, false));
 }
 
 // Whether work enqueued on st is being recorded into a caller's graph.
@@ -872,7 +946,7 @@ void run_graph(hsim_batch b, const hsim::RunArgs &ra, hipStream_t st)
         try {
             auto mask = [&](int t) { return efull_each || t == 0; };
             if (b->layout == HSIM_LAYOUT_REPLICA) enqueue_rep_sequence(b, rc, U, mask, b->g_cap, 0, true);
-            else enqueue_site_sequence(b, rc, U, mask, b->g_cap, 0, true);
+            else enqueue_site_sequence(b, rc, U, mask, b->g_cap, 0, true, split_ok(b, b->g_cap, true));
         } catch (...) {
             (void)hipStreamEndCapture(b->g_cap, &graph);
             if (graph) (void)hipGraphDestroy(graph);

@@ -184,13 +184,13 @@ hipError_t launch_site_phase(hipStream_t st, bool f64, int kmode, int fmode, boo
                              const RepDesc *reps, const Tile *tiles, int tile_off, int ntiles,
                              int t_off, const RunArgs &ra);
 hipError_t launch_site_efull(hipStream_t st, bool f64, int kmode, int fmode, const RepDesc *reps,
-                             const Tile *tiles, int ntiles, int t_off, const RunArgs &ra);
+                             const Tile *tiles, int tile_off, int ntiles, int t_off, const RunArgs &ra);
 // Colour classes c_tail .. ncol_max-1 (one block per replica) plus the
 // per-MCS history of every replica (the same results as a phase launch per
 // class).
 hipError_t launch_site_finish(hipStream_t st, bool f64, int kmode, int fmode, bool trace, int ellw,
-                              const RepDesc *reps, const int32_t *rep_tiles, int ncol_max, int c_tail,
-                              int t_off, const RunArgs &ra);
+                              const RepDesc *reps, const int32_t *rep_tiles, const int32_t *rlist,
+                              int nrep, int ncol_max, int c_tail, int t_off, const RunArgs &ra);
 hipError_t launch_ctl_advance(hipStream_t st, Ctl *ctl, uint32_t n);
 hipError_t launch_block_sweep(hipStream_t st, bool f64, int kmode, int fmode, bool trace,
                               int ellw, bool lds, int threads, size_t lds_bytes, const RepDesc *reps,

@@ -139,8 +139,18 @@ struct hsim_batch_s {
     std::vector<hsim::RepDesc> reps;
     std::vector<hsim::Tile> tiles;
     std::vector<int32_t> rep_tiles;   // [R][ncol_max][2]
-    std::vector<int32_t> tile_off;    // ncol_max+1
     int32_t c_tail = 0;               // colours >= c_tail run in the per-replica finish launch
+    // site layout: the replicas with trailing classes (group 1) and the
+    // others (group 0); tiles are group-major, then colour, then replica.
+    // With two groups each runs its launch sequence on a stream of its own,
+    // so one group's latency-bound finish overlaps the other's phases.
+    int ngroups = 1;
+    std::vector<int32_t> gtile_off[2];   // [ncol_max+1] first tile of colour c in group g
+    std::vector<int64_t> gunits[2];      // [ncol_max] updates of colour c in group g
+    std::vector<int32_t> grp_reps[2];
+    hsim::DevBuf d_grp_reps[2];
+    hipStream_t gstream[2] = {nullptr, nullptr};
+    hipEvent_t gfork = nullptr, gjoin[2] = {nullptr, nullptr};
     std::vector<int64_t> spin_off;    // elements, per replica
     int64_t spin_elems = 0;
     // replica layout

@@ -402,12 +402,12 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_phase(const RepDesc *__rest
 template <typename T, int KM, int FM>
 __global__ __launch_bounds__(kSiteBlock) void k_site_efull(const RepDesc *__restrict__ reps,
                                                            const Tile *__restrict__ tiles,
-                                                           int t_off, RunArgs ra)
+                                                           int tile_off, int t_off, RunArgs ra)
 {
     __shared__ double red[(kSiteBlock / 64)];
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     if (!recompute_due(g % (uint32_t)ra.M, ra.P)) return;
-    const int tl = xcd_tile((int)blockIdx.x, (int)gridDim.x);   // this block's tile
+    const int tl = tile_off + xcd_tile((int)blockIdx.x, (int)gridDim.x);   // this block's tile
     const Tile t = tiles[tl];
     const RepDesc &rd = reps[t.rep];
     const uint32_t s_abs = g / (uint32_t)ra.M;
@@ -466,19 +466,20 @@ hipError_t launch_site_phase(hipStream_t st, bool f64, int kmode, int fmode, boo
 }
 
 hipError_t launch_site_efull(hipStream_t st, bool f64, int kmode, int fmode, const RepDesc *reps,
-                             const Tile *tiles, int ntiles, int t_off, const RunArgs &ra)
+                             const Tile *tiles, int tile_off, int ntiles, int t_off, const RunArgs &ra)
 {
     if (ntiles <= 0) return hipSuccess;
     dim3 grid((unsigned)ntiles), blk(kSiteBlock);
     HSIM_DISPATCH_KF(kmode, fmode, {
-        if (f64) hipLaunchKernelGGL((k_site_efull<double, KM, FM>), grid, blk, 0, st, reps, tiles, t_off, ra);
-        else hipLaunchKernelGGL((k_site_efull<float, KM, FM>), grid, blk, 0, st, reps, tiles, t_off, ra);
+        if (f64) hipLaunchKernelGGL((k_site_efull<double, KM, FM>), grid, blk, 0, st, reps, tiles, tile_off, t_off, ra);
+        else hipLaunchKernelGGL((k_site_efull<float, KM, FM>), grid, blk, 0, st, reps, tiles, tile_off, t_off, ra);
     });
     return hipGetLastError();
 }
 
-// The colour classes c_tail .. ncol-1 of every replica and then its per-MCS
-// history, in one launch of one block of kFinThreads threads per replica
+// The colour classes c_tail .. ncol-1 of every replica (of the list rlist, or
+// all) and then its per-MCS history, in one launch of one block of
+// kFinThreads threads per replica
 // (512: 1024 would spill the double-precision state and measured no faster
 // in single precision on the films).
 // Small trailing classes (the extra colours of odd-size films: a few hundred
@@ -493,10 +494,11 @@ hipError_t launch_site_efull(hipStream_t st, bool f64, int kmode, int fmode, con
 template <typename T, int KM, int FM, bool TRACE, int MAXD>
 __global__ __launch_bounds__(kFinThreads) void k_site_finish(const RepDesc *__restrict__ reps,
                                                     const int32_t *__restrict__ rep_tiles,
-                                                    int ncol_max, int c_tail, int t_off, RunArgs ra)
+                                                    const int32_t *__restrict__ rlist, int ncol_max,
+                                                    int c_tail, int t_off, RunArgs ra)
 {
     __shared__ double red[(kFinThreads / 64) * 7];
-    const int r = blockIdx.x;
+    const int r = rlist ? rlist[blockIdx.x] : (int)blockIdx.x;
     const RepDesc &rd = reps[r];
     const uint32_t g = ra.ctl->g + (uint32_t)t_off;
     const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
@@ -544,17 +546,18 @@ __global__ __launch_bounds__(kFinThreads) void k_site_finish(const RepDesc *__re
 }
 
 hipError_t launch_site_finish(hipStream_t st, bool f64, int kmode, int fmode, bool trace, int ellw,
-                              const RepDesc *reps, const int32_t *rep_tiles, int ncol_max, int c_tail,
-                              int t_off, const RunArgs &ra)
+                              const RepDesc *reps, const int32_t *rep_tiles, const int32_t *rlist,
+                              int nrep, int ncol_max, int c_tail, int t_off, const RunArgs &ra)
 {
-    const dim3 grid((unsigned)ra.R), blk(kFinThreads);
+    if (nrep <= 0) return hipSuccess;
+    const dim3 grid((unsigned)nrep), blk(kFinThreads);
     HSIM_DISPATCH_KF(kmode, fmode, HSIM_DISPATCH_W(ellw, {
         if (f64) {
-            if (trace) hipLaunchKernelGGL((k_site_finish<double, KM, FM, true, MAXD>), grid, blk, 0, st, reps, rep_tiles, ncol_max, c_tail, t_off, ra);
-            else hipLaunchKernelGGL((k_site_finish<double, KM, FM, false, MAXD>), grid, blk, 0, st, reps, rep_tiles, ncol_max, c_tail, t_off, ra);
+            if (trace) hipLaunchKernelGGL((k_site_finish<double, KM, FM, true, MAXD>), grid, blk, 0, st, reps, rep_tiles, rlist, ncol_max, c_tail, t_off, ra);
+            else hipLaunchKernelGGL((k_site_finish<double, KM, FM, false, MAXD>), grid, blk, 0, st, reps, rep_tiles, rlist, ncol_max, c_tail, t_off, ra);
         } else {
-            if (trace) hipLaunchKernelGGL((k_site_finish<float, KM, FM, true, MAXD>), grid, blk, 0, st, reps, rep_tiles, ncol_max, c_tail, t_off, ra);
-            else hipLaunchKernelGGL((k_site_finish<float, KM, FM, false, MAXD>), grid, blk, 0, st, reps, rep_tiles, ncol_max, c_tail, t_off, ra);
+            if (trace) hipLaunchKernelGGL((k_site_finish<float, KM, FM, true, MAXD>), grid, blk, 0, st, reps, rep_tiles, rlist, ncol_max, c_tail, t_off, ra);
+            else hipLaunchKernelGGL((k_site_finish<float, KM, FM, false, MAXD>), grid, blk, 0, st, reps, rep_tiles, rlist, ncol_max, c_tail, t_off, ra);
         }
     }));
     return hipGetLastError();

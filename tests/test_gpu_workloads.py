@@ -166,6 +166,42 @@ def test_c3_uneven_film_batch_fp64_bit_exact():
         assert np.array_equal(H[r][..., 4], ref["history"][..., 4])
 
 
+def test_c3_groups_on_two_streams_change_nothing():
+    """Films with trailing colour classes and films without run as two groups
+    on the batch's two streams (plain and graph launches); with per-MCS
+    outputs bound the same batch interleaves both groups on the caller's
+    stream, and each group alone is a batch of its own: spins and history
+    bit-identical in all of them."""
+    films, Ts = synth.film_batch()
+    order = np.argsort([f.n for f in films], kind="stable")[:24]
+    plans = {int(f): hsim.Plan(films[f]) for f in order}
+    pick = [int(f) for f in order]
+    tail = [f for f in pick if plans[f].info.n_colours > 2]
+    rest = [f for f in pick if plans[f].info.n_colours <= 2]
+    assert tail and rest
+    M = 6
+    T = np.array([Ts[f] for f in pick])[:, None] * np.ones((1, 2))
+
+    def run(fs, launch, outputs=False):
+        b = hsim.Batch([plans[f] for f in fs], seed=7, replica_ids=np.array(fs, dtype=np.uint32),
+                       precision=hsim.FP32, layout=hsim.LAYOUT_SITE).bind(2, M)
+        if outputs:
+            b.bind_outputs(snapshots=True)
+        b.init_spins(hsim.INIT_RANDOM)
+        idx = [pick.index(f) for f in fs]
+        b.run(T[idx], 0.2, recompute_every=3, launch=launch)
+        torch.cuda.synchronize()
+        assert b.status() == 0
+        return {f: (b.spins_user(k).cpu().numpy(), b.history.cpu().numpy()[k]) for k, f in enumerate(fs)}
+
+    ref = run(pick, hsim.LAUNCH_PLAIN)
+    for got in (run(pick, hsim.LAUNCH_GRAPH), run(pick, hsim.LAUNCH_PLAIN, outputs=True),
+                {**run(tail, hsim.LAUNCH_PLAIN), **run(rest, hsim.LAUNCH_GRAPH)}):
+        for f in pick:
+            assert np.array_equal(got[f][0], ref[f][0]), f
+            assert np.array_equal(got[f][1], ref[f][1]), f
+
+
 def test_c3_full_batch_fp32():
     """All 256 films (8.6M sites) in one site-layout batch, FP32, graph
     launch: unit spins, incremental vs full energy and one-MCS site agreement
