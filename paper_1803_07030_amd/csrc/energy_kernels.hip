@@ -17,8 +17,10 @@
 // issued together without branches; kEU configurations are in flight at
 // once.  The forward, which needs every bond once, reads half rows (the
 // bonds each site leaves under the plan's Euler orientation) and counts each
-// bond term whole; the backward reads full rows, since dE/dS needs every
-// neighbour.  The lattice tables of a site are read once per group.  Sums over
+// bond term whole, and stages each step's own spins of its tile in LDS, so
+// that neighbours inside the tile are read there instead of gathered; the
+// backward reads full rows, since dE/dS needs every neighbour.  The lattice
+// tables of a site are read once per group.  Sums over
 // sites and configurations are double precision in a fixed order: lanes by
 // recursive halving, waves in order, tiles lane-strided then butterfly,
 // groups and passes in order.  Batches larger than the plan's pass size run
@@ -193,6 +195,17 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
     const T ex = ax ? ax[ii] : T(0), ey = ax ? ax[a.n + ii] : T(0), ez = ax ? ax[2 * a.n + ii] : T(1);
     const T nx = nd ? nd[ii] : T(0), ny = nd ? nd[a.n + ii] : T(0), nz = nd ? nd[2 * a.n + ii] : T(1);
     const T kc = a.kc ? ((const T *)a.kc)[ii] : T(0);
+    // Forward on half rows: the tile's own spins also go to LDS (two buffers,
+    // alternate steps), and a neighbour inside the tile is read there; only
+    // the others are gathered from memory.  loc: the neighbour's place in the
+    // tile, or -1.
+    __shared__ T sh_own[HALF ? 2 : 1][kEU][3][HALF ? kEBlock : 1];
+    int loc[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        const int64_t d = (int64_t)col[q] - (int64_t)tile * kEBlock;
+        loc[q] = HALF && d >= 0 && d < kEBlock ? (int)d : -1;
+    }
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
     const int b0 = grp * kEG;
     const int nc = min(kEG, a.batch - b0);
@@ -215,10 +228,29 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
             own[u][2] = S[2 * a.n + ii];
 #pragma unroll
             for (int q = 0; q < W; ++q) {
+                if (loc[q] >= 0) continue;
                 nb[u][q][0] = S[col[q]];
                 nb[u][q][1] = S[a.n + col[q]];
                 nb[u][q][2] = S[2 * a.n + col[q]];
             }
+        }
+        if constexpr (HALF) {
+            // a thread of a site past the end holds site 0's spins: no row
+            // names that slot
+            const int p = (c0 / kEU) & 1;
+#pragma unroll
+            for (int u = 0; u < kEU; ++u)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) sh_own[p][u][d][threadIdx.x] = own[u][d];
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kEU; ++u)
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    if (loc[q] < 0) continue;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) nb[u][q][d] = sh_own[p][u][d][loc[q]];
+                }
         }
 #pragma unroll
         for (int u = 0; u < kEU; ++u) {
@@ -233,20 +265,27 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
                 thz += J[q] * nb[u][q][2];
             }
             const T tsx = own[u][0], tsy = own[u][1], tsz = own[u][2];
-            const double sx = tsx, sy = tsy, sz = tsz;
-            const double an = sx * (double)ex + sy * (double)ey + sz * (double)ez;
-            const double zn = sx * (double)nx + sy * (double)ny + sz * (double)nz;
             if constexpr (!BWD) {
                 // full rows count every bond from both ends (half each); half
-                // rows count it once, at the end it leaves
-                constexpr double kBond = HALF ? 1.0 : 0.5;
-                double e = -kBond * (sx * (double)thx + sy * (double)thy + sz * (double)thz) -
-                           a.B * zn - (double)k * an * an;
+                // rows count it once, at the end it leaves.  A site's terms in
+                // the spins' precision (fused multiply-adds), the sums over
+                // sites in double.
+                constexpr T kBond = HALF ? T(1) : T(0.5);
+                const T dot = fma(tsx, thx, fma(tsy, thy, tsz * thz));
+                const T an_t = fma(tsx, ex, fma(tsy, ey, tsz * ez));
+                const T zn_t = fma(tsx, nx, fma(tsy, ny, tsz * nz));
+                T e = fma(-k * an_t, an_t, fma(-(T)a.B, zn_t, -kBond * dot));
                 // cubic term of Eq. 3, -kc (Sx^2 Sy^2 + Sy^2 Sz^2 + Sx^2 Sz^2)
-                if (a.kc) e -= (double)kc * ((sx * sx * (sy * sy) + sy * sy * (sz * sz)) + sx * sx * (sz * sz));
-                ev[u] = ok ? e : 0.0;
+                if (a.kc) {
+                    const T x2 = tsx * tsx, y2 = tsy * tsy, z2 = tsz * tsz;
+                    e = fma(-kc, fma(x2, y2, fma(y2, z2, x2 * z2)), e);
+                }
+                ev[u] = ok ? (double)e : 0.0;
             }
-            zv[u] = ok ? zn : 0.0;
+            if constexpr (BWD) {
+                const double sx = tsx, sy = tsy, sz = tsz;
+                zv[u] = ok ? sx * (double)nx + sy * (double)ny + sz * (double)nz : 0.0;
+            }
             if (BWD) {
                 const double gb = ok ? gE[b] : 0.0;
                 const T g = (T)gb;
