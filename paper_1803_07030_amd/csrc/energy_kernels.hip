@@ -260,9 +260,9 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
             T thx = T(0), thy = T(0), thz = T(0);
 #pragma unroll
             for (int q = 0; q < W; ++q) {
-                thx += J[q] * nb[u][q][0];
-                thy += J[q] * nb[u][q][1];
-                thz += J[q] * nb[u][q][2];
+                thx = fma(J[q], nb[u][q][0], thx);
+                thy = fma(J[q], nb[u][q][1], thy);
+                thz = fma(J[q], nb[u][q][2], thz);
             }
             const T tsx = own[u][0], tsy = own[u][1], tsz = own[u][2];
             if constexpr (!BWD) {
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
                 const double gb = ok ? gE[b] : 0.0;
                 const T g = (T)gb;
                 const T B = (T)a.B;
-                const T an_t = tsx * ex + tsy * ey + tsz * ez;
+                const T an_t = fma(tsx, ex, fma(tsy, ey, tsz * ez));
                 const T two_ka = T(2) * k * an_t;
                 T cx = T(0), cy = T(0), cz = T(0);
                 if (a.kc) {
@@ -302,17 +302,17 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
                 }
                 if (gS && ok) {
                     T *o = gS + (size_t)b * 3 * a.n;
-                    o[i] = g * (-thx - B * nx - two_ka * ex - cx);
-                    o[a.n + i] = g * (-thy - B * ny - two_ka * ey - cy);
-                    o[2 * a.n + i] = g * (-thz - B * nz - two_ka * ez - cz);
+                    o[i] = -g * (fma(two_ka, ex, fma(B, nx, thx)) + cx);
+                    o[a.n + i] = -g * (fma(two_ka, ey, fma(B, ny, thy)) + cy);
+                    o[2 * a.n + i] = -g * (fma(two_ka, ez, fma(B, nz, thz)) + cz);
                 }
                 if (params) {
-                    gk += g * -(an_t * an_t);
+                    gk = fma(-g, an_t * an_t, gk);
                     // bonds whose lower end is i (padding: col == i, skipped)
 #pragma unroll
                     for (int q = 0; q < W; ++q) {
-                        const T d = tsx * nb[u][q][0] + tsy * nb[u][q][1] + tsz * nb[u][q][2];
-                        gj[q] += col[q] > i ? g * -d : T(0);
+                        const T d = fma(tsx, nb[u][q][0], fma(tsy, nb[u][q][1], tsz * nb[u][q][2]));
+                        gj[q] = col[q] > i ? fma(-g, d, gj[q]) : gj[q];
                     }
                 }
             }
