@@ -167,7 +167,7 @@ struct SiteTables {
 // thread one site and the kEG configurations of the item, kEU at a time.
 template <typename T, bool BWD, int W, bool HALF = false>
 __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile, int items,
-                                                        const double *gE, T *gS, double *partE,
+                                                        const double *__restrict__ gE, T *gS, double *partE,
                                                         double *partB, double *partK, double *partJ)
 {
     static_assert(!(HALF && BWD), "half rows serve the forward only");
@@ -219,6 +219,11 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
     for (int c0 = 0; c0 < nc; c0 += kEU) {
         double ev[kEU], zv[kEU];
         T own[kEU][3], nb[kEU][W][3];
+        // the step's weights dL/dE, read before the spins: the index is the
+        // same in every lane, so these are scalar loads
+        double gw[BWD ? kEU : 1];
+#pragma unroll
+        for (int u = 0; u < (BWD ? kEU : 0); ++u) gw[u] = gE[min(b0 + c0 + u, a.batch - 1)];
 #pragma unroll
         for (int u = 0; u < kEU; ++u) {
             const int b = min(b0 + c0 + u, a.batch - 1);
@@ -252,6 +257,11 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
                     for (int d = 0; d < 3; ++d) nb[u][q][d] = sh_own[p][u][d][loc[q]];
                 }
         }
+        // dE/dS of the step's configurations, stored after the last of them
+        // is formed: with a store issued between two configurations, the
+        // waits for the second one's loads (on the one counter of
+        // outstanding vector-memory operations) also waited for the store
+        T go[BWD ? kEU : 1][3];
 #pragma unroll
         for (int u = 0; u < kEU; ++u) {
             const int c = c0 + u, b = b0 + c;
@@ -287,7 +297,7 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
                 zv[u] = ok ? sx * (double)nx + sy * (double)ny + sz * (double)nz : 0.0;
             }
             if (BWD) {
-                const double gb = ok ? gE[b] : 0.0;
+                const double gb = ok ? gw[BWD ? u : 0] : 0.0;
                 const T g = (T)gb;
                 const T B = (T)a.B;
                 const T an_t = fma(tsx, ex, fma(tsy, ey, tsz * ez));
@@ -300,12 +310,9 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
                     cy = kc2 * tsy * (x2 + z2);
                     cz = kc2 * tsz * (x2 + y2);
                 }
-                if (gS && ok) {
-                    T *o = gS + (size_t)b * 3 * a.n;
-                    o[i] = -g * (fma(two_ka, ex, fma(B, nx, thx)) + cx);
-                    o[a.n + i] = -g * (fma(two_ka, ey, fma(B, ny, thy)) + cy);
-                    o[2 * a.n + i] = -g * (fma(two_ka, ez, fma(B, nz, thz)) + cz);
-                }
+                go[BWD ? u : 0][0] = -g * (fma(two_ka, ex, fma(B, nx, thx)) + cx);
+                go[BWD ? u : 0][1] = -g * (fma(two_ka, ey, fma(B, ny, thy)) + cy);
+                go[BWD ? u : 0][2] = -g * (fma(two_ka, ez, fma(B, nz, thz)) + cz);
                 if (params) {
                     gk = fma(-g, an_t * an_t, gk);
                     // bonds whose lower end is i (padding: col == i, skipped)
@@ -314,6 +321,25 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
                         const T d = fma(tsx, nb[u][q][0], fma(tsy, nb[u][q][1], tsz * nb[u][q][2]));
                         gj[q] = col[q] > i ? fma(-g, d, gj[q]) : gj[q];
                     }
+                }
+            }
+        }
+        if constexpr (BWD) {
+            // every value is formed here (an empty asm takes them in
+            // registers, so their arithmetic cannot sink below the stores),
+            // and nothing moves past the scheduling barrier
+#pragma unroll
+            for (int u = 0; u < kEU; ++u)
+                asm volatile("" : "+v"(go[u][0]), "+v"(go[u][1]), "+v"(go[u][2]));
+            __builtin_amdgcn_sched_barrier(0);
+            if (gS && live) {
+#pragma unroll
+                for (int u = 0; u < kEU; ++u) {
+                    if (c0 + u >= nc) continue;
+                    T *o = gS + (size_t)(b0 + c0 + u) * 3 * a.n;
+                    o[i] = go[u][0];
+                    o[a.n + i] = go[u][1];
+                    o[2 * a.n + i] = go[u][2];
                 }
             }
         }
