@@ -315,6 +315,22 @@ hsim_status hsim_batch_status(hsim_batch b, int32_t *device_status_out);
  * directions) is reused; a new choice is appended to the file. */
 hsim_status hsim_autotune(hsim_batch b, const char *cache_path, int32_t trial_mcs,
                           void *stream);
+/* The spin layout for a batch that hsim_batch_create would build from these
+ * arguments, chosen by timing the MCS (section "Monte Carlo Metropolis
+ * algorithm") in each candidate layout: every layout the batch
+ * can use (SITE; REPLICA for FP32 batches on one shared lattice; BLOCK when
+ * a replica's spins fit in LDS, or when it is the static choice) runs as a
+ * fresh batch of its own, one warm-up step and one timed step of trial_mcs
+ * MCS from a cold start, with the launch mode HSIM_LAUNCH_AUTO gives a batch
+ * that was not tuned.  T, B: host arrays [n_rep], the temperature (>= 0,
+ * +inf allowed) and field intensity of each replica.  *layout_out receives
+ * the static HSIM_LAYOUT_AUTO choice unless another layout was more than 2%
+ * faster.  Layouts give the same spins (the history can differ in rounding),
+ * so the choice only changes speed.  Allocates and frees its scratch batches
+ * and buffers and synchronises the stream; HSIM_E_ARG for a bad argument. */
+hsim_status hsim_choose_layout(int32_t n_rep, const hsim_plan *plan_of_rep, uint64_t seed,
+                               const uint32_t *replica_id, hsim_precision precision, const double *T,
+                               const double *B, int32_t trial_mcs, int32_t *layout_out, void *stream);
 void hsim_batch_destroy(hsim_batch b);
 
 /* ------------------------------------------------- energy and its gradient */

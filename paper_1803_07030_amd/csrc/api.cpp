@@ -30,6 +30,8 @@ void batch_run_impl(hsim_batch, int32_t, int32_t, const double *, const double *
 void batch_to_user_impl(hsim_batch, int32_t, double *, hipStream_t);
 int32_t batch_status_impl(hsim_batch);
 void autotune_impl(hsim_batch, const char *, int32_t, hipStream_t);
+int32_t choose_layout_impl(int32_t, const hsim_plan *, uint64_t, const uint32_t *, hsim_precision,
+                           const double *, const double *, int32_t, hipStream_t);
 void batch_time_phases_impl(hsim_batch, int32_t);
 void plan_set_types_impl(hsim_plan, const int32_t *);
 void plan_set_site_terms_impl(hsim_plan, const double *, const double *);
@@ -256,6 +258,17 @@ hsim_status hsim_batch_status(hsim_batch b, int32_t *out)
 hsim_status hsim_autotune(hsim_batch b, const char *cache_path, int32_t trial_mcs, void *stream)
 {
     return guarded([&] { autotune_impl(b, cache_path, trial_mcs, S(stream)); });
+}
+
+hsim_status hsim_choose_layout(int32_t n_rep, const hsim_plan *plan_of_rep, uint64_t seed,
+                               const uint32_t *replica_id, hsim_precision precision, const double *T,
+                               const double *B, int32_t trial_mcs, int32_t *layout_out, void *stream)
+{
+    return guarded([&] {
+        if (!layout_out) throw hsim::Error(HSIM_E_ARG, "choose_layout: NULL layout_out");
+        *layout_out = choose_layout_impl(n_rep, plan_of_rep, seed, replica_id, precision, T, B, trial_mcs,
+                                         S(stream));
+    });
 }
 
 void hsim_batch_destroy(hsim_batch b) { delete b; }

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <fstream>
 #include <limits>
+#include <memory>
 #include <sstream>
 
 #include "hsim_host.h"
@@ -1334,6 +1335,86 @@ void autotune_impl(hsim_batch b, const char *cache_path, int32_t trial_mcs, hipS
         std::ofstream out(cache_path, std::ios::app);
         out << key << " " << win.mode << " " << win.grid << " " << win.spw << " " << win.masked << "\n";
     }
+}
+
+// ------------------------------------------------------------ layout choice
+// Times every layout these replicas can use, each as a fresh batch of its
+// own: one warm-up step and one timed step of trial_mcs MCS from a cold start
+// at the given temperatures and fields, with the launch mode a fresh batch
+// runs under HSIM_LAUNCH_AUTO.  Candidates: SITE; REPLICA when the batch
+// allows it (FP32, one shared lattice); BLOCK when a replica's spins fit in
+// LDS.  The static choice of HSIM_LAYOUT_AUTO is kept unless another layout
+// is more than 2% faster.
+int32_t choose_layout_impl(int32_t R, const hsim_plan *plans, uint64_t seed, const uint32_t *rep_id,
+                           hsim_precision prec, const double *T, const double *B, int32_t trial_mcs,
+                           hipStream_t st)
+{
+    if (R < 1 || !plans || !T || !B) throw Error(HSIM_E_ARG, "choose_layout: bad argument");
+    if (trial_mcs < 1) throw Error(HSIM_E_ARG, "choose_layout: trial_mcs must be >= 1");
+    for (int r = 0; r < R; ++r)
+        if (!(T[r] >= 0.0) || std::isnan(B[r]) || std::isinf(B[r]))
+            throw Error(HSIM_E_ARG, "choose_layout: temperatures >= 0 and finite fields");
+    struct Del { void operator()(hsim_batch b) const { delete b; } };
+    int32_t auto_layout;
+    {
+        std::unique_ptr<hsim_batch_s, Del> b(batch_create_impl(R, plans, seed, rep_id, prec, HSIM_LAYOUT_AUTO));
+        auto_layout = b->layout;
+    }
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    std::string err;
+    std::vector<std::pair<int32_t, float>> times;
+    try {
+        for (int32_t lay : {(int32_t)HSIM_LAYOUT_SITE, (int32_t)HSIM_LAYOUT_REPLICA, (int32_t)HSIM_LAYOUT_BLOCK}) {
+            std::unique_ptr<hsim_batch_s, Del> b;
+            try {
+                b.reset(batch_create_impl(R, plans, seed, rep_id, prec, (hsim_layout)lay));
+            } catch (const Error &e) {
+                if (e.code == HSIM_E_UNSUPPORTED) continue;   // not a layout for this batch
+                throw;
+            }
+            if (lay == HSIM_LAYOUT_BLOCK && !b->lds && lay != auto_layout) continue;
+            size_t wsb = 0, spb = 0, hb = 0;
+            batch_sizes_impl(b.get(), 2, trial_mcs, &wsb, &spb, &hb);
+            hsim::DevBuf ws, sp, hist;
+            ws.alloc(wsb);
+            sp.alloc(spb);
+            hist.alloc(hb);
+            batch_bind_impl(b.get(), 2, trial_mcs, ws.p, sp.p, hist.p);
+            batch_init_impl(b.get(), HSIM_INIT_COLD_Z, nullptr, st);
+            // step 0 warms up (and captures a graph where the mode uses one);
+            // T and B are [n_rep][1] for a run of one step
+            batch_run_impl(b.get(), 0, 1, T, B, 0, HSIM_LAUNCH_AUTO, 0, nullptr, st);
+            hip_check(hipEventRecord(e0, st), "hipEventRecord");
+            batch_run_impl(b.get(), 1, 1, T, B, 0, HSIM_LAUNCH_AUTO, 0, nullptr, st);
+            hip_check(hipEventRecord(e1, st), "hipEventRecord");
+            hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.0f;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (batch_status_impl(b.get()) != 0) throw Error(HSIM_E_DEVICE, "choose_layout: a trial run failed");
+            hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+            times.push_back({lay, ms});
+        }
+    } catch (const std::exception &e) {
+        err = e.what();
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!err.empty()) throw Error(HSIM_E_DEVICE, "choose_layout: " + err);
+    // the static choice is always among the trials: it is creatable, and the
+    // block layout is tried whenever it is the static choice
+    float base = 0.0f;
+    for (auto &t : times)
+        if (t.first == auto_layout) base = t.second;
+    int32_t win = auto_layout;
+    float best = base;
+    for (auto &t : times)
+        if (t.second < 0.98f * base && t.second < best) {
+            win = t.first;
+            best = t.second;
+        }
+    return win;
 }
 
 // ------------------------------------------------------------ launch timing

@@ -74,6 +74,7 @@ _SIGNATURES = {
     "hsim_batch_spins_to_user": [_vp, _i32, _vp, _vp],
     "hsim_batch_status": [_vp, _vp],
     "hsim_autotune": [_vp, ctypes.c_char_p, _i32, _vp],
+    "hsim_choose_layout": [_i32, _vp, _u64, _vp, _i32, _vp, _vp, _i32, _vp, _vp],
     "hsim_batch_time_phases": [_vp, _i32],
     "hsim_plan_set_types": [_vp, _vp],
     "hsim_plan_set_site_terms": [_vp, _vp, _vp],
@@ -258,6 +259,18 @@ def hsim_autotune(batch, cache_path=None, trial_mcs=20):
     _check(lib().hsim_autotune(batch, cp, trial_mcs, _stream()))
 
 
+def hsim_choose_layout(plans, seed, T, B, replica_ids=None, precision=FP32, trial_mcs=10):
+    """plans: Plan handles; T, B: one temperature and field per replica."""
+    arr = (ctypes.c_void_p * len(plans))(*[p.value for p in plans])
+    ids = None if replica_ids is None else np.ascontiguousarray(replica_ids, dtype=np.uint32)
+    Tv = np.ascontiguousarray(np.broadcast_to(np.asarray(T, dtype=np.float64), (len(plans),)))
+    Bv = np.ascontiguousarray(np.broadcast_to(np.asarray(B, dtype=np.float64), (len(plans),)))
+    out = ctypes.c_int32(-1)
+    _check(lib().hsim_choose_layout(len(plans), arr, seed & (2 ** 64 - 1), _ptr(ids), precision,
+                                    _ptr(Tv), _ptr(Bv), trial_mcs, ctypes.byref(out), _stream()))
+    return out.value
+
+
 def hsim_batch_set_policies(batch, policies, sigma_min=SIGMA_MIN, sigma_max=SIGMA_MAX):
     pol = np.ascontiguousarray([int(a) for a, _ in policies], dtype=np.int32)
     prm = np.ascontiguousarray([float(b) for _, b in policies], dtype=np.float64)
@@ -421,6 +434,12 @@ class Plan:
 
 class Batch:
     """Replicas over plans with caller-owned (torch) device buffers."""
+
+    @staticmethod
+    def choose_layout(plans, seed, T, B, replica_ids=None, precision=FP32, trial_mcs=10):
+        """The layout to create the batch with, chosen by timing (hsim_choose_layout)."""
+        return hsim_choose_layout([p.handle for p in plans], seed, T, B, replica_ids, precision,
+                                  trial_mcs)
 
     def __init__(self, plans, seed, replica_ids=None, precision=FP32, layout=LAYOUT_AUTO,
                  device="cuda"):

@@ -88,6 +88,41 @@ def test_autotune_without_policies_matches_plain():
     assert np.allclose(out[0][1], out[1][1], rtol=0, atol=1e-9 * lat.n)
 
 
+@pytest.mark.parametrize("case", ["replicas", "films", "fp64"])
+def test_choose_layout_returns_a_usable_layout(case):
+    """hsim_choose_layout times the layouts a batch can use and returns one of
+    them: never the replica layout for uneven lattices or double precision;
+    a batch built with its choice gives the same spins as one built with
+    HSIM_LAYOUT_AUTO."""
+    if case == "replicas":
+        lats = [synth.sc_periodic(12)] * 32
+        prec = hsim.FP32
+    elif case == "films":
+        films, _ = synth.film_batch()
+        order = np.argsort([f.n for f in films], kind="stable")[:12]
+        lats = [films[f] for f in order]
+        prec = hsim.FP32
+    else:
+        lats = [synth.sc_periodic(8)] * 4
+        prec = hsim.FP64_EXACT
+    plans = [hsim.Plan(lat) for lat in lats]
+    R, M = len(plans), 5
+    T = np.linspace(0.4, 2.0, R)
+    lay = hsim.Batch.choose_layout(plans, 9, T, 0.2, precision=prec, trial_mcs=5)
+    allowed = {hsim.LAYOUT_SITE, hsim.LAYOUT_BLOCK} | ({hsim.LAYOUT_REPLICA} if case == "replicas" else set())
+    assert lay in allowed, (case, lay)
+    out = []
+    for layout in (hsim.LAYOUT_AUTO, lay):
+        b = hsim.Batch(plans, seed=9, precision=prec, layout=layout).bind(1, M)
+        b.init_spins(hsim.INIT_RANDOM)
+        b.run(T[:, None], 0.2, launch=hsim.LAUNCH_PLAIN)
+        torch.cuda.synchronize()
+        assert b.status() == 0
+        out.append([b.spins_user(r).cpu().numpy() for r in range(R)])
+    for r in range(R):
+        assert np.array_equal(out[0][r], out[1][r]), (case, r)
+
+
 @pytest.mark.parametrize("R", [64, 20], ids=["64-lane rows", "32-lane rows"])
 def test_tile_shapes_and_store_policies_give_identical_spins(R):
     """Every tile shape (4, 8, 32 sites per wave) and store policy (whole
