@@ -356,8 +356,12 @@ hsim_batch batch_create_impl(int32_t R, const hsim_plan *plans, uint64_t seed,
                             const int32_t t0 = (int32_t)b->tiles.size();
                             if (c < P->ncol) {
                                 b->gunits[g][c] += P->cls_off[c + 1] - P->cls_off[c];
-                                for (int32_t s = P->cls_off[c]; s < P->cls_off[c + 1]; s += hsim::kSiteBlock)
-                                    b->tiles.push_back({r, s, std::min(s + hsim::kSiteBlock, P->cls_off[c + 1]), c});
+                                for (int32_t s = P->cls_off[c]; s < P->cls_off[c + 1]; s += hsim::kSiteBlock) {
+                                    const int32_t e = std::min(s + hsim::kSiteBlock, P->cls_off[c + 1]);
+                                    int32_t nsl = 0;   // slots past every row's end are padding
+                                    for (int32_t t = s; t < e; ++t) nsl = std::max(nsl, P->rp[t + 1] - P->rp[t]);
+                                    b->tiles.push_back({r, s, e, c, nsl});
+                                }
                             }
                             b->rep_tiles[((size_t)r * C + c) * 2] = t0;
                             b->rep_tiles[((size_t)r * C + c) * 2 + 1] = (int32_t)b->tiles.size();

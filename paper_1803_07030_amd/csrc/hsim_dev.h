@@ -67,6 +67,7 @@ struct RepDesc {
 // A block's share of one colour phase of one replica: internal sites [begin, end).
 struct Tile {
     int32_t rep, begin, end, colour;
+    int32_t nsl;   // padded-row slots that any site of the tile uses (its largest degree)
 };
 
 // Update policy of every site type.

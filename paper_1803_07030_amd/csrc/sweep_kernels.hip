@@ -100,10 +100,16 @@ struct SiteParams {
 // Exchange field of site i: the CSR row walk (MAXD == 0) or the padded row of
 // MAXD slots (slot-major copy, coalesced across the lanes of a wave).  A
 // padding slot holds the site itself with constant 0 and leaves every sum
-// unchanged, so both walks give the same bits.
+// unchanged, so both walks give the same bits.  Slots from nsl on are padding
+// for every site of the block's tile (the same in every lane; the surface
+// layers of a film, one neighbour short, leave their last slot empty): they
+// are read at the tile's first site, ts, whose entry there is padding too
+// (itself, constant 0), so every lane reads one cached line instead of the
+// tile's stretch of the slot, and the sum is unchanged (h + 0 * S_ts == h for
+// the finite, never negative-zero partial sums h).
 template <typename T, int MAXD>
 __device__ __forceinline__ void exchange_field(const RepDesc &rd, const T *S, int i, T &hx, T &hy,
-                                               T &hz)
+                                               T &hz, int nsl = MAXD, int ts = 0)
 {
     const int np = rd.n_pad;
     hx = T(0);
@@ -113,8 +119,9 @@ __device__ __forceinline__ void exchange_field(const RepDesc &rd, const T *S, in
         const T *EJ = (const T *)rd.ellT_J;
 #pragma unroll
         for (int sl = 0; sl < MAXD; ++sl) {
-            const int32_t j = rd.ellT_col[sl * rd.n + i];
-            const T Jp = EJ[sl * rd.n + i];
+            const int src = sl < nsl ? i : ts;
+            const int32_t j = rd.ellT_col[sl * rd.n + src];
+            const T Jp = EJ[sl * rd.n + src];
             if constexpr (sizeof(T) == 4) {
                 hx = fmaf(Jp, S[j], hx);
                 hy = fmaf(Jp, S[np + j], hy);
@@ -147,7 +154,8 @@ __device__ __forceinline__ void exchange_field(const RepDesc &rd, const T *S, in
 template <typename T, int KM, int FM, bool TRACE, int MAXD>
 __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint32_t g,
                                             const RunArgs &ra, int rep, T beta, T b,
-                                            double sigma, double (&acc)[5], double &ad)
+                                            double sigma, double (&acc)[5], double &ad,
+                                            int nsl = MAXD, int ts = 0)
 {
     const int np = rd.n_pad;
     const SiteParams<T, KM, FM> sp(rd, i);
@@ -156,7 +164,7 @@ __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint
     bool acc_move;
     T nx, ny, nz, dE;
     T hx, hy, hz;
-    exchange_field<T, MAXD>(rd, S, i, hx, hy, hz);
+    exchange_field<T, MAXD>(rd, S, i, hx, hy, hz, nsl, ts);
     SitePol pl{POL_RANDOM, 0.0, 1.0};
     if (ra.pol.n_types > 0) {
         pl = pick_policy(ra.pol.pol, ra.pol.param, ra.pol.cos_t, rd.type ? rd.type[i] : 0);
@@ -388,7 +396,7 @@ __global__ __launch_bounds__(kSiteBlock) void k_site_phase(const RepDesc *__rest
     const int i = t.begin + (int)threadIdx.x;
     if (i < t.end)
         site_update<T, KM, FM, TRACE, MAXD>(rd, (T *)rd.spins, i, g, ra, t.rep, beta, b, sigma,
-                                            acc, ad);
+                                            acc, ad, t.nsl, t.begin);
     double v[6] = {acc[0], acc[1], acc[2], acc[3], acc[4], ad};
     block_sum<6>(v, red);
     if (threadIdx.x == 0) {
