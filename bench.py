@@ -45,8 +45,9 @@ def parse():
                     help="replica tiles: 'SPW,MASKED' (sites per wave 4/8/32, store policy 0/1)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the tile shape and store policy before timing (untimed)")
-    ap.add_argument("--time-every", type=int, default=10,
-                    help="plain launch: time every n-th MCS's colour-phase launches with HIP events")
+    ap.add_argument("--time-every", type=int, default=None,
+                    help="plain launch: time every n-th MCS's colour-phase launches with HIP events "
+                         "(default 10; films 0: their roofline is taken over the whole step)")
     ap.add_argument("--plain-mcs", type=int, default=8, help="MCS per replica of the plain-launch sample")
     ap.add_argument("--cpu-mcs", type=int, default=400, help="MCS per thread of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -167,6 +168,8 @@ def b_alg_replica_lane(zbar, a, lanes):
 
 def main():
     args = parse()
+    if args.time_every is None and args.workload != "films":
+        args.time_every = 10
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(replicas shard across GPUs without communication)", file=sys.stderr)
@@ -311,8 +314,8 @@ def films_bench(args, stream):
     """256 diluted films (L in 16..128, d in 2..10, 10% vacancies, per-bond J
     in [0.5, 1.5], K = 0.05 z), each film one replica at its own temperature
     in [0.2, 2.0], single precision, site-lane layout.  The roofline is taken
-    over the whole step; plain launches also time the colour-phase launches
-    of every n-th MCS."""
+    over the whole step; with --time-every n, plain launches also time the
+    colour-phase launches of every n-th MCS."""
     import torch
     import synth
     from paper_1803_07030_amd import hsim
@@ -324,7 +327,8 @@ def films_bench(args, stream):
                   plain=hsim.LAUNCH_PLAIN, auto=hsim.LAUNCH_AUTO)[args.launch]
     if launch == hsim.LAUNCH_PERSISTENT:
         sys.exit("the persistent launch needs the replica layout; films use the site layout")
-    timed_phases = launch == hsim.LAUNCH_PLAIN and args.time_every > 0
+    every = 0 if args.time_every is None else args.time_every
+    timed_phases = launch == hsim.LAUNCH_PLAIN and every > 0
     with torch.cuda.stream(stream):
         plans = [hsim.Plan(f) for f in films]
         batch = hsim.Batch(plans, seed=3, precision=hsim.FP32, layout=hsim.LAYOUT_SITE).bind(1, mcs)
@@ -337,7 +341,7 @@ def films_bench(args, stream):
         stream.synchronize()
         if timed_phases:
             batch.phase_times()
-            batch.time_phases(args.time_every)
+            batch.time_phases(every)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             batch.init_spins(hsim.INIT_COLD_Z)
