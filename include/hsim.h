@@ -327,7 +327,8 @@ hsim_status hsim_autotune(hsim_batch b, const char *cache_path, int32_t trial_mc
  * the static HSIM_LAYOUT_AUTO choice unless another layout was more than 2%
  * faster.  Layouts give the same spins (the history can differ in rounding),
  * so the choice only changes speed.  Allocates and frees its scratch batches
- * and buffers and synchronises the stream; HSIM_E_ARG for a bad argument. */
+ * and buffers and synchronises the stream; HSIM_E_ARG for a bad argument,
+ * HSIM_E_PARAM for a negative or NaN temperature or a non-finite field. */
 hsim_status hsim_choose_layout(int32_t n_rep, const hsim_plan *plan_of_rep, uint64_t seed,
                                const uint32_t *replica_id, hsim_precision precision, const double *T,
                                const double *B, int32_t trial_mcs, int32_t *layout_out, void *stream);

@@ -1357,7 +1357,7 @@ int32_t choose_layout_impl(int32_t R, const hsim_plan *plans, uint64_t seed, con
     if (trial_mcs < 1) throw Error(HSIM_E_ARG, "choose_layout: trial_mcs must be >= 1");
     for (int r = 0; r < R; ++r)
         if (!(T[r] >= 0.0) || std::isnan(B[r]) || std::isinf(B[r]))
-            throw Error(HSIM_E_ARG, "choose_layout: temperatures >= 0 and finite fields");
+            throw Error(HSIM_E_PARAM, "choose_layout: temperatures >= 0 and finite fields");
     struct Del { void operator()(hsim_batch b) const { delete b; } };
     int32_t auto_layout;
     {

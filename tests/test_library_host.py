@@ -240,11 +240,11 @@ def test_energy_wrapper_rejects_mismatched_inputs():
 
 def test_choose_layout_argument_errors():
     """hsim_choose_layout checks its arguments before it builds or times a
-    batch (HSIM_E_ARG = -1)."""
+    batch (HSIM_E_ARG = -1, HSIM_E_PARAM = -3 for the schedule's values)."""
     sc = hsim.Plan(synth.sc_periodic(6))
     plans = [sc] * 4
     _expect(-1, lambda: hsim.Batch.choose_layout(plans, 1, 1.0, 0.0, trial_mcs=0))
-    _expect(-1, lambda: hsim.Batch.choose_layout(plans, 1, [1.0, -0.5, 1.0, 1.0], 0.0))
-    _expect(-1, lambda: hsim.Batch.choose_layout(plans, 1, [1.0, np.nan, 1.0, 1.0], 0.0))
-    _expect(-1, lambda: hsim.Batch.choose_layout(plans, 1, 1.0, [0.0, 0.0, np.inf, 0.0]))
+    _expect(-3, lambda: hsim.Batch.choose_layout(plans, 1, [1.0, -0.5, 1.0, 1.0], 0.0))
+    _expect(-3, lambda: hsim.Batch.choose_layout(plans, 1, [1.0, np.nan, 1.0, 1.0], 0.0))
+    _expect(-3, lambda: hsim.Batch.choose_layout(plans, 1, 1.0, [0.0, 0.0, np.inf, 0.0]))
     _expect(-1, lambda: hsim.Batch.choose_layout([], 1, 1.0, 0.0))
