@@ -336,10 +336,11 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
 #pragma unroll
                 for (int u = 0; u < kEU; ++u) {
                     if (c0 + u >= nc) continue;
+                    // non-temporal: dE/dS is not read again by this kernel
                     T *o = gS + (size_t)(b0 + c0 + u) * 3 * a.n;
-                    o[i] = go[u][0];
-                    o[a.n + i] = go[u][1];
-                    o[2 * a.n + i] = go[u][2];
+                    __builtin_nontemporal_store(go[u][0], &o[i]);
+                    __builtin_nontemporal_store(go[u][1], &o[a.n + i]);
+                    __builtin_nontemporal_store(go[u][2], &o[2 * a.n + i]);
                 }
             }
         }
