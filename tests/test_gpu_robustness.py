@@ -265,6 +265,44 @@ def test_fp64_bit_exact_with_a_hub_site(layout):
     assert np.max(np.abs(h[..., 0] - ref["history"][..., 0])) <= 1e-12 * scale
 
 
+def _padded_tiles_lattice():
+    """Isolated sites, then an open chain, then a periodic SC 6^3 block (one
+    lattice, rows padded to 6 slots): the site layout's tiles of 256 sites of
+    a class use 0, 2 or 6 slots, and some mix two parts."""
+    n_iso, n_chain = 700, 400
+    sc = synth.sc_periodic(6)
+    si, sj, sJ = sc.bonds()
+    ci = np.arange(n_chain - 1) + n_iso
+    bi = np.concatenate([ci, si + n_iso + n_chain])
+    bj = np.concatenate([ci + 1, sj + n_iso + n_chain])
+    rng = np.random.default_rng(17)
+    bJ = rng.uniform(0.5, 1.5, bi.size)
+    n = n_iso + n_chain + sc.n
+    lat = synth.from_bonds(n, bi, bj, bJ, name="padded_tiles")
+    lat.k = rng.uniform(0.0, 0.3, n)
+    lat.axis = synth.unit_vectors(17, n, tag=1)
+    return lat
+
+
+def test_fp64_bit_exact_with_tiles_of_every_row_width():
+    """Site layout: slots past a tile's largest degree are read at the tile's
+    first site (its padding entry); accepts and spins stay bit-exact with the
+    oracle for tiles whose sites use 0, 2 and 6 slots."""
+    lat = _padded_tiles_lattice()
+    assert lat.degree.max() == 6 and (lat.degree == 0).sum() == 700
+    plan = hsim.Plan(lat)
+    T = synth.cooling_schedule(6, 2.5, 0.2)
+    b = hsim.Batch([plan], seed=8, precision=hsim.FP64_EXACT, layout=hsim.LAYOUT_SITE).bind(6, 5)
+    b.init_spins(hsim.INIT_RANDOM)
+    tr = b.new_trace(6)
+    b.run(T, 0.3, trace=tr, recompute_every=3, launch=hsim.LAUNCH_PLAIN)
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    ref = oracle.run(lat, T, 0.3, 5, seed=8, init="random", recompute_every=3, trace_accepts=True)
+    assert np.array_equal(hsim.unpack_trace(tr, lat.n)[0], ref["accept"].astype(bool))
+    assert np.array_equal(b.spins_user(0).cpu().numpy(), ref["spins"])
+
+
 def test_fp32_hub_site_layouts_identical_and_match_oracle():
     lat = _hub_lattice()
     plan = hsim.Plan(lat)
