@@ -19,7 +19,8 @@
 // bonds each site leaves under the plan's Euler orientation) and counts each
 // bond term whole, and stages each step's own spins of its tile in LDS, so
 // that neighbours inside the tile are read there instead of gathered; the
-// backward reads full rows, since dE/dS needs every neighbour.  The lattice
+// backward reads full rows, since dE/dS needs every neighbour, and in single
+// precision on rows of 6 stages its tile the same way.  The lattice
 // tables of a site are read once per group.  Sums over
 // sites and configurations are double precision in a fixed order: lanes by
 // recursive halving, waves in order, tiles lane-strided then butterfly,
@@ -27,6 +28,7 @@
 // in passes over a fixed scratch (no allocation per call).
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "hsim_dev.h"
 
@@ -165,12 +167,15 @@ struct SiteTables {
 
 // Padded rows of width W: one work item per block (XCD-aware order), each
 // thread one site and the kEG configurations of the item, kEU at a time.
-template <typename T, bool BWD, int W, bool HALF = false>
-__global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile, int items,
-                                                        const double *__restrict__ gE, T *gS, double *partE,
-                                                        double *partB, double *partK, double *partJ)
+// STAGE: each step's own spins of the tile also go to LDS, and neighbours
+// inside the tile are read there.
+template <typename T, bool BWD, int W, bool HALF, bool STAGE>
+__device__ __forceinline__ void energy_ell(const EnergyArgs &a, int ntile, int items,
+                                           const double *__restrict__ gE, T *gS, double *partE,
+                                           double *partB, double *partK, double *partJ)
 {
     static_assert(!(HALF && BWD), "half rows serve the forward only");
+    static_assert(!HALF || STAGE, "the half-row forward stages its tile");
     const int u_item = xcd_tile((int)blockIdx.x, items);
     const int grp = u_item / ntile, tile = u_item - grp * ntile;
     constexpr int kW = kEBlock / 64;
@@ -195,16 +200,15 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
     const T ex = ax ? ax[ii] : T(0), ey = ax ? ax[a.n + ii] : T(0), ez = ax ? ax[2 * a.n + ii] : T(1);
     const T nx = nd ? nd[ii] : T(0), ny = nd ? nd[a.n + ii] : T(0), nz = nd ? nd[2 * a.n + ii] : T(1);
     const T kc = a.kc ? ((const T *)a.kc)[ii] : T(0);
-    // Forward on half rows: the tile's own spins also go to LDS (two buffers,
-    // alternate steps), and a neighbour inside the tile is read there; only
-    // the others are gathered from memory.  loc: the neighbour's place in the
-    // tile, or -1.
-    __shared__ T sh_own[HALF ? 2 : 1][kEU][3][HALF ? kEBlock : 1];
+    // Staged: the tile's own spins also go to LDS (two buffers, alternate
+    // steps), and a neighbour inside the tile is read there; only the others
+    // are gathered from memory.  loc: the neighbour's place in the tile, or -1.
+    __shared__ T sh_own[STAGE ? 2 : 1][kEU][3][STAGE ? kEBlock : 1];
     int loc[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) {
         const int64_t d = (int64_t)col[q] - (int64_t)tile * kEBlock;
-        loc[q] = HALF && d >= 0 && d < kEBlock ? (int)d : -1;
+        loc[q] = STAGE && d >= 0 && d < kEBlock ? (int)d : -1;
     }
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
     const int b0 = grp * kEG;
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
                 nb[u][q][2] = S[2 * a.n + col[q]];
             }
         }
-        if constexpr (HALF) {
+        if constexpr (STAGE) {
             // a thread of a site past the end holds site 0's spins: no row
             // names that slot
             const int p = (c0 / kEU) & 1;
@@ -372,6 +376,27 @@ __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile,
 #pragma unroll
     for (int q = 0; q < W; ++q)
         if (col[q] > i) partJ[(size_t)grp * a.nb + bid[q]] = (double)gj[q];
+}
+
+template <typename T, bool BWD, int W, bool HALF = false>
+__global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile, int items,
+                                                        const double *__restrict__ gE, T *gS, double *partE,
+                                                        double *partB, double *partK, double *partJ)
+{
+    energy_ell<T, BWD, W, HALF, HALF>(a, ntile, items, gE, gS, partE, partB, partK, partJ);
+}
+
+// The single-precision backward on rows of 6, staged: its rows, group sums
+// and LDS addressing take about 121 VGPRs when the compiler is held to four
+// waves per SIMD (129, i.e. three waves, otherwise); staging pays only at
+// four.  The double-precision and 8-wide backwards would spill under that
+// limit and stay unstaged.
+template <typename T, int W>
+__global__ __launch_bounds__(kEBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_energy_ell_bwd_staged(
+    EnergyArgs a, int ntile, int items, const double *__restrict__ gE, T *gS, double *partE, double *partB,
+    double *partK, double *partJ)
+{
+    energy_ell<T, true, W, false, true>(a, ntile, items, gE, gS, partE, partB, partK, partJ);
 }
 
 // Rows longer than the padded width (any degree): grid (site tiles, chunks of
@@ -623,6 +648,13 @@ hipError_t launch_site_kernel(hipStream_t st, const EnergyArgs &a, const EnergyL
                                st, a, L.ntile, items, gE, gS, partE, partB, partK, partJ);
     } else if (L.ell_w == 6 || L.ell_w == 8) {
         const int items = ngroups * L.ntile;
+        if constexpr (BWD && std::is_same<T, float>::value) {
+            if (L.ell_w == 6) {
+                hipLaunchKernelGGL((k_energy_ell_bwd_staged<T, 6>), dim3((unsigned)items), dim3(kEBlock), 0,
+                                   st, a, L.ntile, items, gE, gS, partE, partB, partK, partJ);
+                return hipGetLastError();
+            }
+        }
         if (L.ell_w == 6)
             hipLaunchKernelGGL((k_energy_ell<T, BWD, 6>), dim3((unsigned)items), dim3(kEBlock), 0, st, a,
                                L.ntile, items, gE, gS, partE, partB, partK, partJ);
