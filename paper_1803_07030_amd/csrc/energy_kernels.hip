@@ -19,8 +19,8 @@
 // bonds each site leaves under the plan's Euler orientation) and counts each
 // bond term whole, and stages each step's own spins of its tile in LDS, so
 // that neighbours inside the tile are read there instead of gathered; the
-// backward reads full rows, since dE/dS needs every neighbour, and in single
-// precision on rows of 6 stages its tile the same way.  The lattice
+// backward reads full rows, since dE/dS needs every neighbour, and on rows
+// of 6 stages its tile the same way.  The lattice
 // tables of a site are read once per group.  Sums over
 // sites and configurations are double precision in a fixed order: lanes by
 // recursive halving, waves in order, tiles lane-strided then butterfly,
@@ -378,19 +378,20 @@ __device__ __forceinline__ void energy_ell(const EnergyArgs &a, int ntile, int i
         if (col[q] > i) partJ[(size_t)grp * a.nb + bid[q]] = (double)gj[q];
 }
 
-template <typename T, bool BWD, int W, bool HALF = false>
+template <typename T, bool BWD, int W, bool HALF = false, bool STAGE = HALF>
 __global__ __launch_bounds__(kEBlock) void k_energy_ell(EnergyArgs a, int ntile, int items,
                                                         const double *__restrict__ gE, T *gS, double *partE,
                                                         double *partB, double *partK, double *partJ)
 {
-    energy_ell<T, BWD, W, HALF, HALF>(a, ntile, items, gE, gS, partE, partB, partK, partJ);
+    energy_ell<T, BWD, W, HALF, STAGE>(a, ntile, items, gE, gS, partE, partB, partK, partJ);
 }
 
 // The single-precision backward on rows of 6, staged: its rows, group sums
-// and LDS addressing take about 121 VGPRs when the compiler is held to four
-// waves per SIMD (129, i.e. three waves, otherwise); staging pays only at
-// four.  The double-precision and 8-wide backwards would spill under that
-// limit and stay unstaged.
+// and LDS addressing take 123 VGPRs when the compiler is held to four waves
+// per SIMD (129, i.e. three waves, otherwise); staging pays only at four.
+// The double-precision backward on rows of 6 is staged at two waves either
+// way (190 VGPRs unstaged, 197 staged) and needs no limit; under this one it
+// would spill.
 template <typename T, int W>
 __global__ __launch_bounds__(kEBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_energy_ell_bwd_staged(
     EnergyArgs a, int ntile, int items, const double *__restrict__ gE, T *gS, double *partE, double *partB,
@@ -656,7 +657,7 @@ hipError_t launch_site_kernel(hipStream_t st, const EnergyArgs &a, const EnergyL
             }
         }
         if (L.ell_w == 6)
-            hipLaunchKernelGGL((k_energy_ell<T, BWD, 6>), dim3((unsigned)items), dim3(kEBlock), 0, st, a,
+            hipLaunchKernelGGL((k_energy_ell<T, BWD, 6, false, BWD>), dim3((unsigned)items), dim3(kEBlock), 0, st, a,
                                L.ntile, items, gE, gS, partE, partB, partK, partJ);
         else
             hipLaunchKernelGGL((k_energy_ell<T, BWD, 8>), dim3((unsigned)items), dim3(kEBlock), 0, st, a,

@@ -226,11 +226,18 @@ def test_fp32_energy_history_consistent():
 
 
 # ------------------------------------------------------------ energy / grads
+@pytest.mark.parametrize("kind", ["sc9", "deg8"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_energy_and_gradients_match_oracle(dtype):
+def test_energy_and_gradients_match_oracle(dtype, kind):
+    """Energies and every gradient against the oracle: SC 9^3 (padded rows
+    of 6, three tiles, the last one ragged) and a random graph of degree up
+    to 8 (rows of 8, two tiles)."""
     from paper_1803_07030_amd.energy import heisenberg_energy
-    lat = synth.gradient_lattice(L=9, seed=4)
-    lat.ndir = synth.unit_vectors(4, lat.n, tag=9)
+    if kind == "sc9":
+        lat = synth.gradient_lattice(L=9, seed=4)
+        lat.ndir = synth.unit_vectors(4, lat.n, tag=9)
+    else:
+        lat = _degree8_lattice()
     plan = hsim.Plan(lat)
     Bn = 8
     S = synth.random_spins(12, lat.n, batch=Bn)                     # [b, n, 3]
