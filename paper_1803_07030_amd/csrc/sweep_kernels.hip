@@ -155,7 +155,9 @@ template <typename T, int KM, int FM, bool TRACE, int MAXD>
 __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint32_t g,
                                             const RunArgs &ra, int rep, T beta, T b,
                                             double sigma, double (&acc)[5], double &ad,
-                                            int nsl = MAXD, int ts = 0)
+                                            int nsl = MAXD, int ts = 0, bool given = false,
+                                            double gu = 0.0, double gx = 0.0, double gy = 0.0,
+                                            double gz = 0.0)
 {
     const int np = rd.n_pad;
     const SiteParams<T, KM, FM> sp(rd, i);
@@ -204,7 +206,19 @@ __device__ __forceinline__ void site_update(const RepDesc &rd, T *S, int i, uint
                                         sy, sz, hx, hy, hz, sp.k, sp.ex, sp.ey, sp.ez, rd.kc != nullptr,
                                         rd.kc ? ((const double *)rd.kc)[i] : 0.0, rd.mu != nullptr,
                                         rd.mu ? ((const double *)rd.mu)[i] : 1.0, beta, nx, ny, nz, dd);
-        else if (pl.pol == POL_RANDOM)
+        else if (pl.pol == POL_RANDOM && given) {
+            // update64 with its acceptance word and trial point drawn ahead
+            // (draw_ahead64): the same operations in the same order
+            nx = gx;
+            ny = gy;
+            nz = gz;
+            const double dSx = nx - sx, dSy = ny - sy, dSz = nz - sz;
+            const double q = (dSx * hx + dSy * hy) + dSz * hz;
+            const double a1 = dot64(nx, ny, nz, sp.ex, sp.ey, sp.ez);
+            const double a0 = dot64(sx, sy, sz, sp.ex, sp.ey, sp.ez);
+            dd = -q - sp.k * (a1 * a1 - a0 * a0);
+            acc_move = dd <= 0.0 || gu < exp(-beta * dd);
+        } else if (pl.pol == POL_RANDOM)
             acc_move = update64(ra.seed, orig, g, rd.rep_id, sx, sy, sz, hx, hy, hz, sp.k, sp.ex,
                                 sp.ey, sp.ez, beta, nx, ny, nz, dd);
         else
@@ -572,11 +586,54 @@ hipError_t launch_site_finish(hipStream_t st, bool f64, int kmode, int fmode, bo
 }
 
 // --------------------------------------------------------- block layout
+// The acceptance word and the trial point of a double-precision random move
+// depend on the counters only (site, MCS, replica, attempt), not on the
+// state: update64's attempt 0 and Marsaglia's map on attempts 1, 2, ...
+// (sphere64).  Both sites' first two draws are formed together, four
+// independent Philox chains, so their latencies overlap; a rejected first
+// point continues from attempt 2 as sphere64 does.
+__device__ __forceinline__ void draw_ahead64(uint64_t seed, const uint32_t (&o)[2], uint32_t g,
+                                             uint32_t rep, double (&u)[2], double (&x)[2],
+                                             double (&y)[2], double (&z)[2])
+{
+    uint4 w0[2], w1[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        w0[c] = draw(seed, o[c], g, rep, 0);
+        w1[c] = draw(seed, o[c], g, rep, 1);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        u[c] = u53(w0[c].x, w0[c].y);
+        uint4 w = w1[c];
+        x[c] = 0.0;
+        y[c] = 0.0;
+        z[c] = 1.0;
+        for (uint32_t t = 1; t <= 32; ++t) {
+            if (t > 1) w = draw(seed, o[c], g, rep, t);
+            const double v1 = 2.0 * u53(w.x, w.y) - 1.0;
+            const double v2 = 2.0 * u53(w.z, w.w) - 1.0;
+            const double s = v1 * v1 + v2 * v2;
+            if (s < 1.0) {
+                const double f = 2.0 * sqrt(1.0 - s);
+                x[c] = v1 * f;
+                y[c] = v2 * f;
+                z[c] = 1.0 - 2.0 * s;
+                break;
+            }
+        }
+    }
+}
+
 // One workgroup owns one replica for the whole run: colour classes are
 // separated by workgroup barriers, spins live in LDS when they fit, and the
 // per-MCS history is written directly.
-template <typename T, int KM, int FM, bool TRACE, bool LDS, int MAXD>
-__global__ __launch_bounds__(1024) void k_block_sweep(const RepDesc *__restrict__ reps, RunArgs ra)
+// NT: the largest block it is launched with.  The double-precision kernel
+// needs more than the 128 VGPRs a block of 1024 threads leaves each lane, so
+// blocks of up to 256 threads (classes of up to 256 sites) use an
+// instantiation bounded at 256.
+template <typename T, int KM, int FM, bool TRACE, bool LDS, int MAXD, int NT = 1024>
+__global__ __launch_bounds__(NT) void k_block_sweep(const RepDesc *__restrict__ reps, RunArgs ra)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[16 * 6];
@@ -593,9 +650,25 @@ __global__ __launch_bounds__(1024) void k_block_sweep(const RepDesc *__restrict_
         }
         __syncthreads();
     }
+    // Double precision, random moves, no cubic term or spin lengths, at most
+    // two classes of at most one site per thread: the draws of both of a
+    // thread's sites are made ahead of the phases
+    bool ahead = sizeof(T) == 8 && ra.pol.n_types == 0 && !rd.kc && !rd.mu && rd.ncol <= 2;
+    for (int c = 0; c < rd.ncol; ++c)
+        ahead = ahead && rd.cls_off[c + 1] - rd.cls_off[c] <= (int)blockDim.x;
+    uint32_t ao[2] = {0u, 0u};
+    if (ahead)
+        for (int c = 0; c < rd.ncol; ++c) {
+            // a thread past its class's end draws for the class's last site
+            // and never uses the result
+            const int lo = rd.cls_off[c], hi = rd.cls_off[c + 1];
+            ao[c] = hi > lo ? rd.orig[min(lo + (int)threadIdx.x, hi - 1)] : 0u;
+        }
     double E = 0.0;
     for (int t = 0; t < ra.n_mcs_run; ++t) {
         const uint32_t g = ra.g0 + (uint32_t)t;
+        double au[2], ax[2], ay[2], az[2];
+        if (ahead) draw_ahead64(ra.seed, ao, g, rd.rep_id, au, ax, ay, az);
         const uint32_t s_abs = g / (uint32_t)ra.M, m = g % (uint32_t)ra.M;
         const size_t sidx = (size_t)rep * ra.S_hist + s_abs;
         const double bd = ra.bfield[sidx];
@@ -614,7 +687,9 @@ __global__ __launch_bounds__(1024) void k_block_sweep(const RepDesc *__restrict_
         for (int c = 0; c < rd.ncol; ++c) {
             const int ce = rd.cls_off[c + 1];
             for (int i = rd.cls_off[c] + threadIdx.x; i < ce; i += blockDim.x)
-                site_update<T, KM, FM, TRACE, MAXD>(rd, S, i, g, ra, rep, beta, b, sigma, acc, ad);
+                site_update<T, KM, FM, TRACE, MAXD>(rd, S, i, g, ra, rep, beta, b, sigma, acc, ad, MAXD, 0,
+                                                    ahead, c ? au[1] : au[0], c ? ax[1] : ax[0],
+                                                    c ? ay[1] : ay[0], c ? az[1] : az[0]);
             __syncthreads();
         }
         double v[6] = {acc[0], acc[1], acc[2], acc[3], acc[4], ad};
@@ -680,21 +755,24 @@ hipError_t launch_block_sweep(hipStream_t st, bool f64, int kmode, int fmode, bo
 {
     dim3 grid((unsigned)ra.R), blk((unsigned)threads);
     const size_t sh = lds ? lds_bytes : 0;
-#define HSIM_BLK(T_, TR_, L_)                                                                  \
+#define HSIM_BLK(T_, TR_, L_, NT_)                                                             \
     do {                                                                                       \
-        auto kfn = k_block_sweep<T_, KM, FM, TR_, L_, MAXD>;                                         \
+        auto kfn = k_block_sweep<T_, KM, FM, TR_, L_, MAXD, NT_>;                                    \
         if (sh > 65536)                                                                        \
             (void)hipFuncSetAttribute((const void *)kfn,                                       \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);    \
         hipLaunchKernelGGL(kfn, grid, blk, sh, st, reps, ra);                                  \
     } while (0)
     HSIM_DISPATCH_KF(kmode, fmode, HSIM_DISPATCH_W(ellw, {
-        if (f64) {
-            if (trace) { if (lds) HSIM_BLK(double, true, true); else HSIM_BLK(double, true, false); }
-            else { if (lds) HSIM_BLK(double, false, true); else HSIM_BLK(double, false, false); }
+        if (f64 && threads <= 256) {
+            if (trace) { if (lds) HSIM_BLK(double, true, true, 256); else HSIM_BLK(double, true, false, 256); }
+            else { if (lds) HSIM_BLK(double, false, true, 256); else HSIM_BLK(double, false, false, 256); }
+        } else if (f64) {
+            if (trace) { if (lds) HSIM_BLK(double, true, true, 1024); else HSIM_BLK(double, true, false, 1024); }
+            else { if (lds) HSIM_BLK(double, false, true, 1024); else HSIM_BLK(double, false, false, 1024); }
         } else {
-            if (trace) { if (lds) HSIM_BLK(float, true, true); else HSIM_BLK(float, true, false); }
-            else { if (lds) HSIM_BLK(float, false, true); else HSIM_BLK(float, false, false); }
+            if (trace) { if (lds) HSIM_BLK(float, true, true, 1024); else HSIM_BLK(float, true, false, 1024); }
+            else { if (lds) HSIM_BLK(float, false, true, 1024); else HSIM_BLK(float, false, false, 1024); }
         }
     }));
 #undef HSIM_BLK
