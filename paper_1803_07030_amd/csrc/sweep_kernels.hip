@@ -630,8 +630,8 @@ __device__ __forceinline__ void draw_ahead64(uint64_t seed, const uint32_t (&o)[
 // per-MCS history is written directly.
 // NT: the largest block it is launched with.  The double-precision kernel
 // needs more than the 128 VGPRs a block of 1024 threads leaves each lane, so
-// blocks of up to 256 threads (classes of up to 256 sites) use an
-// instantiation bounded at 256.
+// blocks of up to 256 threads (classes of up to 256 sites) with spins in LDS
+// use an instantiation bounded at 256.
 template <typename T, int KM, int FM, bool TRACE, bool LDS, int MAXD, int NT = 1024>
 __global__ __launch_bounds__(NT) void k_block_sweep(const RepDesc *__restrict__ reps, RunArgs ra)
 {
@@ -764,9 +764,9 @@ hipError_t launch_block_sweep(hipStream_t st, bool f64, int kmode, int fmode, bo
         hipLaunchKernelGGL(kfn, grid, blk, sh, st, reps, ra);                                  \
     } while (0)
     HSIM_DISPATCH_KF(kmode, fmode, HSIM_DISPATCH_W(ellw, {
-        if (f64 && threads <= 256) {
-            if (trace) { if (lds) HSIM_BLK(double, true, true, 256); else HSIM_BLK(double, true, false, 256); }
-            else { if (lds) HSIM_BLK(double, false, true, 256); else HSIM_BLK(double, false, false, 256); }
+        if (f64 && threads <= 256 && lds) {
+            if (trace) HSIM_BLK(double, true, true, 256);
+            else HSIM_BLK(double, false, true, 256);
         } else if (f64) {
             if (trace) { if (lds) HSIM_BLK(double, true, true, 1024); else HSIM_BLK(double, true, false, 1024); }
             else { if (lds) HSIM_BLK(double, false, true, 1024); else HSIM_BLK(double, false, false, 1024); }
