@@ -81,6 +81,33 @@ def test_fp64_full_c0_run():
     assert np.max(np.abs(h[..., 0] - ref["history"][..., 0])) <= 1e-12 * _energy_scale(lat)
 
 
+@pytest.mark.parametrize("kind", ["sc10", "sc14", "isolated"])
+def test_fp64_block_layout_class_sizes(kind):
+    """The double-precision block kernel draws a site's acceptance word and
+    trial point ahead of the colour phases when there are at most two
+    classes of at most one site per thread.  SC 10^3: two classes of 500
+    sites, a 512-thread block (the kernel bounded at 1024 threads); SC 14^3:
+    classes of 1372 sites, more than a block's 1024 threads, drawn in the
+    phases; isolated spins: one class.  Per-site anisotropy, field steps of
+    both signs; accepts and spins bit-exact."""
+    if kind == "isolated":
+        lat = synth.isolated(300)
+    else:
+        lat = synth.sc_periodic(10 if kind == "sc10" else 14)
+    lat.k = 0.4 * synth.uniform01(21, lat.n, tag=1) - 0.1
+    lat.axis = synth.unit_vectors(21, lat.n, tag=2)
+    T = [2.0, 0.5, 0.0]
+    B = [0.3, -0.4, 0.1]
+    M = 8
+    b, acc, h, s = _fp64_run(lat, T, B, M, 21, hsim.LAYOUT_BLOCK)
+    assert b.layout == "block"
+    ref = oracle.run(lat, T, B, M, seed=21, init="random", trace_accepts=True)
+    assert np.array_equal(acc, ref["accept"].astype(bool))
+    assert np.array_equal(s, ref["spins"])
+    assert np.array_equal(h[..., 4], ref["history"][..., 4])
+    assert np.max(np.abs(h[..., 0] - ref["history"][..., 0])) <= 1e-12 * _energy_scale(lat)
+
+
 @pytest.mark.parametrize("layout", [hsim.LAYOUT_BLOCK, hsim.LAYOUT_SITE])
 def test_fp64_irregular_lattice_with_all_terms(layout):
     """Film with vacancies (odd L: 5 colours), random per-bond J, per-site k
