@@ -652,8 +652,10 @@ __global__ __launch_bounds__(NT) void k_block_sweep(const RepDesc *__restrict__ 
     }
     // Double precision, random moves, no cubic term or spin lengths, at most
     // two classes of at most one site per thread: the draws of both of a
-    // thread's sites are made ahead of the phases
-    bool ahead = sizeof(T) == 8 && ra.pol.n_types == 0 && !rd.kc && !rd.mu && rd.ncol <= 2;
+    // thread's sites are made ahead of the phases.  Only in the kernel
+    // bounded at 256 threads: under the 1024-thread bound the extra live
+    // values spill (143 VGPRs against 43) and cost more than they save.
+    bool ahead = NT <= 256 && sizeof(T) == 8 && ra.pol.n_types == 0 && !rd.kc && !rd.mu && rd.ncol <= 2;
     for (int c = 0; c < rd.ncol; ++c)
         ahead = ahead && rd.cls_off[c + 1] - rd.cls_off[c] <= (int)blockDim.x;
     uint32_t ao[2] = {0u, 0u};

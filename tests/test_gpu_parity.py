@@ -81,19 +81,20 @@ def test_fp64_full_c0_run():
     assert np.max(np.abs(h[..., 0] - ref["history"][..., 0])) <= 1e-12 * _energy_scale(lat)
 
 
-@pytest.mark.parametrize("kind", ["sc10", "sc14", "isolated"])
+@pytest.mark.parametrize("kind", ["sc6", "isolated", "sc10", "sc14"])
 def test_fp64_block_layout_class_sizes(kind):
-    """The double-precision block kernel draws a site's acceptance word and
-    trial point ahead of the colour phases when there are at most two
-    classes of at most one site per thread.  SC 10^3: two classes of 500
-    sites, a 512-thread block (the kernel bounded at 1024 threads); SC 14^3:
-    classes of 1372 sites, more than a block's 1024 threads, drawn in the
-    phases; isolated spins: one class.  Per-site anisotropy, field steps of
-    both signs; accepts and spins bit-exact."""
+    """The double-precision block kernel bounded at 256 threads draws a
+    site's acceptance word and trial point ahead of the colour phases when
+    there are at most two classes of at most one site per thread: SC 6^3
+    (two classes of 108 sites) and 200 isolated spins (one class).  The
+    kernel bounded at 1024 threads draws in the phases: SC 10^3 (two classes
+    of 500, a 512-thread block) and SC 14^3 (classes of 1372 sites, more
+    than a block's 1024 threads).  Per-site anisotropy, field steps of both
+    signs; accepts and spins bit-exact."""
     if kind == "isolated":
-        lat = synth.isolated(300)
+        lat = synth.isolated(200)
     else:
-        lat = synth.sc_periodic(10 if kind == "sc10" else 14)
+        lat = synth.sc_periodic({"sc6": 6, "sc10": 10, "sc14": 14}[kind])
     lat.k = 0.4 * synth.uniform01(21, lat.n, tag=1) - 0.1
     lat.axis = synth.unit_vectors(21, lat.n, tag=2)
     T = [2.0, 0.5, 0.0]
